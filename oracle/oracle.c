@@ -1,0 +1,851 @@
+/*
+ * oracle.c -- sequential FP64 reference implementation of the Gauss-Seidel
+ * cascadic multigrid (GS-CMG) Fiedler-vector solver of Gandhi, "Improvement of
+ * the Cascadic Multigrid Algorithm with a Gauss Seidel Smoother to Efficiently
+ * Compute the Fiedler Vector of a Graph Laplacian" (arXiv 1602.04386, 2015).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker for the HIP library: it
+ * is built and called by the tests, by the smoke check and by the benchmark's
+ * CPU-baseline leg, never by the library.  It shares no code, header, table or
+ * helper with the HIP path.  It is deliberately plain: one thread, no blocking,
+ * no fusion, every loop in the order the method states it, library primitives
+ * limited to qsort, sqrt and fabs.
+ *
+ * What the paper leaves open is fixed by the readings listed in the design
+ * notes; each function below names the passage it follows and the reading it
+ * takes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_INVALID (-1)
+#define OR_E_NOT_SYMMETRIC (-2)
+#define OR_E_NOT_LAPLACIAN (-3)
+#define OR_E_ISOLATED (-4)
+#define OR_E_NOMEM (-5)
+#define OR_E_NOT_CONVERGED (-7)
+
+#define OR_MAX_LEVELS 64
+
+/* ------------------------------------------------------------------------ */
+/* Hashes and random numbers (published definitions, re-typed here).        */
+/* ------------------------------------------------------------------------ */
+
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): draw k (k = 1, 2, ...) of the
+ * stream seeded s is mix(s + k * 0x9E3779B97F4A7C15). */
+static uint64_t or_splitmix64(uint64_t* state) {
+  uint64_t z = (*state += 0x9E3779B97F4A7C15ULL);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* MurmurHash3 32-bit finaliser (Appleby, public domain). */
+static uint32_t or_fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6BU;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35U;
+  h ^= h >> 16;
+  return h;
+}
+
+/* Tie-break hash of the vertex pair a < b. */
+uint32_t or_pair_hash(int32_t a, int32_t b) {
+  return or_fmix32(or_fmix32((uint32_t)a) ^ (uint32_t)b);
+}
+
+/* Per-level colouring seed derived from the user's 64-bit colour seed. */
+uint32_t or_level_seed(uint64_t colour_seed, int32_t level) {
+  uint32_t lo = (uint32_t)colour_seed, hi = (uint32_t)(colour_seed >> 32);
+  return or_fmix32(lo ^ or_fmix32(hi + (uint32_t)level));
+}
+
+/* Colouring priority of vertex v. */
+uint32_t or_colour_priority(int32_t v, uint32_t level_seed) {
+  return or_fmix32((uint32_t)v ^ level_seed);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Input: Definition 2.1 -- L(i,i) = weighted degree, L(i,j) = -w(i,j).      */
+/* ------------------------------------------------------------------------ */
+
+/* Binary search for column j in row i; returns the CSR position or -1. */
+static int64_t or_find(const int32_t* rp, const int32_t* col, int32_t i, int32_t j) {
+  int64_t lo = rp[i], hi = (int64_t)rp[i + 1] - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (col[mid] == j) return mid;
+    if (col[mid] < j) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/*
+ * Validates a CSR input and writes the off-diagonal weights W (w_ij > 0).
+ * is_adjacency = 0: the input is L (Def. 2.1): off-diagonals < 0, a diagonal
+ * entry per row equal to the weighted degree within 1e-12 max(1, L_ii).
+ * is_adjacency = 1: the input is W: no diagonal, entries > 0.
+ * Errors, by priority: structure (INVALID), signs/finiteness/diagonal
+ * (NOT_LAPLACIAN), bitwise symmetry (NOT_SYMMETRIC), a vertex without edges
+ * (ISOLATED).  out_* must hold nnz entries; *out_m receives the edge count.
+ */
+int32_t or_input_to_adjacency(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                              const double* val, int32_t is_adjacency, int32_t* out_rp,
+                              int32_t* out_col, double* out_w, int64_t* out_m) {
+  if (n < 2 || nnz < 0 || nnz > 2147483647LL || !rp || (nnz > 0 && (!col || !val)))
+    return OR_E_INVALID;
+  if (rp[0] != 0 || (int64_t)rp[n] != nnz) return OR_E_INVALID;
+  for (int32_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return OR_E_INVALID;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      if (col[p] < 0 || col[p] >= n) return OR_E_INVALID;
+      if (p > rp[i] && col[p] <= col[p - 1]) return OR_E_INVALID;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    int has_diag = 0;
+    double diag = 0.0, deg = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      double v = val[p];
+      if (!isfinite(v)) return OR_E_NOT_LAPLACIAN;
+      if (col[p] == i) {
+        if (is_adjacency) return OR_E_NOT_LAPLACIAN;
+        has_diag = 1;
+        diag = v;
+      } else {
+        double wij = is_adjacency ? v : -v;
+        if (!(wij > 0.0)) return OR_E_NOT_LAPLACIAN;
+        deg += wij;
+      }
+    }
+    if (!is_adjacency && rp[i + 1] > rp[i]) {
+      if (!has_diag) return OR_E_NOT_LAPLACIAN;
+      double tol = 1e-12 * (fabs(diag) > 1.0 ? fabs(diag) : 1.0);
+      if (fabs(diag - deg) > tol) return OR_E_NOT_LAPLACIAN;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      int32_t j = col[p];
+      if (j == i) continue;
+      int64_t t = or_find(rp, col, j, i);
+      if (t < 0 || memcmp(&val[t], &val[p], sizeof(double)) != 0) return OR_E_NOT_SYMMETRIC;
+    }
+  int64_t m = 0;
+  out_rp[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t start = m;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      if (col[p] == i) continue;
+      out_col[m] = col[p];
+      out_w[m] = is_adjacency ? val[p] : -val[p];
+      ++m;
+    }
+    if (m == start) return OR_E_ISOLATED;
+    out_rp[i + 1] = (int32_t)m;
+  }
+  *out_m = m;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heavy edge coarsening (Algorithm 1), deterministic reading.               */
+/* ------------------------------------------------------------------------ */
+
+/* The strict total order on undirected edges {a < b}: heavier first, then the
+ * smaller pair hash, then the smaller a, then the smaller b.  It replaces the
+ * random visiting order of Algorithm 1 and its first-index tie-break. */
+typedef struct {
+  double w;
+  uint32_t h;
+  int32_t a, b;
+} or_edge;
+
+static int or_edge_before(const or_edge* x, const or_edge* y) {
+  if (x->w != y->w) return x->w > y->w;
+  if (x->h != y->h) return x->h < y->h;
+  if (x->a != y->a) return x->a < y->a;
+  return x->b < y->b;
+}
+
+static int or_edge_cmp(const void* p, const void* q) {
+  const or_edge* x = (const or_edge*)p;
+  const or_edge* y = (const or_edge*)q;
+  if (or_edge_before(x, y)) return -1;
+  if (or_edge_before(y, x)) return 1;
+  return 0;
+}
+
+static or_edge or_make_edge(int32_t u, int32_t v, double w) {
+  or_edge e;
+  e.a = u < v ? u : v;
+  e.b = u < v ? v : u;
+  e.w = w;
+  e.h = or_pair_hash(e.a, e.b);
+  return e;
+}
+
+/*
+ * Heavy-edge matching: the greedy matching that takes the edges in the order
+ * above and keeps an edge when both ends are still free.  mate[v] = partner or
+ * -1.  (A locally-dominant parallel matching under the same strict order
+ * produces exactly this set.)
+ */
+int32_t or_match(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                 int32_t* mate) {
+  int64_t ne = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (col[p] > i) ++ne;
+  or_edge* e = (or_edge*)malloc(sizeof(or_edge) * (size_t)(ne > 0 ? ne : 1));
+  if (!e) return OR_E_NOMEM;
+  int64_t k = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (col[p] > i) e[k++] = or_make_edge(i, col[p], w[p]);
+  qsort(e, (size_t)ne, sizeof(or_edge), or_edge_cmp);
+  for (int32_t v = 0; v < n; ++v) mate[v] = -1;
+  for (int64_t t = 0; t < ne; ++t)
+    if (mate[e[t].a] < 0 && mate[e[t].b] < 0) {
+      mate[e[t].a] = e[t].b;
+      mate[e[t].b] = e[t].a;
+    }
+  free(e);
+  return OR_OK;
+}
+
+/*
+ * Aggregates from a maximal matching (Algorithm 1, the branch where a vertex
+ * joins the aggregate its heaviest neighbour already belongs to): a matched
+ * pair is an aggregate; an unmatched vertex with edges joins the aggregate of
+ * its best neighbour in the edge order (all its neighbours are matched, by
+ * maximality); a vertex without edges stays alone.  Aggregates are numbered by
+ * their smallest member, ascending.  Writes q[v] (the column index of the
+ * interpolation matrix) and returns the number of aggregates, or < 0.
+ */
+int32_t or_aggregate(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                     const int32_t* mate, int32_t* q) {
+  int32_t* root = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* minmem = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!root || !minmem) { free(root); free(minmem); return OR_E_NOMEM; }
+  for (int32_t v = 0; v < n; ++v) root[v] = -1;
+  for (int32_t v = 0; v < n; ++v)
+    if (mate[v] >= 0) root[v] = v < mate[v] ? v : mate[v];
+  for (int32_t v = 0; v < n; ++v) {
+    if (mate[v] >= 0) continue;
+    if (rp[v + 1] == rp[v]) { root[v] = v; continue; }
+    or_edge best = or_make_edge(v, col[rp[v]], w[rp[v]]);
+    int32_t bu = col[rp[v]];
+    for (int64_t p = rp[v] + 1; p < rp[v + 1]; ++p) {
+      or_edge c = or_make_edge(v, col[p], w[p]);
+      if (or_edge_before(&c, &best)) { best = c; bu = col[p]; }
+    }
+    if (mate[bu] < 0) { free(root); free(minmem); return OR_E_INVALID; } /* not maximal */
+    root[v] = bu < mate[bu] ? bu : mate[bu];
+  }
+  for (int32_t v = 0; v < n; ++v) minmem[v] = n;
+  for (int32_t v = 0; v < n; ++v)
+    if (v < minmem[root[v]]) minmem[root[v]] = v;
+  int32_t nc = 0;
+  int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!rank) { free(root); free(minmem); return OR_E_NOMEM; }
+  for (int32_t v = 0; v < n; ++v) rank[v] = -1;
+  for (int32_t v = 0; v < n; ++v)
+    if (minmem[root[v]] == v) rank[v] = nc++;
+  for (int32_t v = 0; v < n; ++v) q[v] = rank[minmem[root[v]]];
+  free(rank);
+  free(root);
+  free(minmem);
+  return nc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Galerkin coarse Laplacian L_c = I L I^T (Algorithm 3, Step 1).            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t A, B; /* coarse pair, A < B */
+  int64_t seq;  /* position in the canonical fine-edge enumeration */
+  double w;
+} or_term;
+
+static int or_term_cmp(const void* p, const void* q) {
+  const or_term* x = (const or_term*)p;
+  const or_term* y = (const or_term*)q;
+  if (x->A != y->A) return x->A < y->A ? -1 : 1;
+  if (x->B != y->B) return x->B < y->B ? -1 : 1;
+  if (x->seq != y->seq) return x->seq < y->seq ? -1 : 1;
+  return 0;
+}
+
+/*
+ * Off-diagonal part of I L I^T: W_c(A,B) = sum of w_ij over fine edges {i<j}
+ * with {q_i, q_j} = {A, B}, A != B, added in increasing (i, j) order (the same
+ * order for (A,B) and (B,A), so W_c is bitwise symmetric).  Edges inside one
+ * aggregate cancel against the diagonal and vanish.  The coarse diagonal is the
+ * row sum, as at every level.  out_* must hold m_fine entries.
+ */
+int32_t or_galerkin(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                    const int32_t* q, int32_t nc, int32_t* out_rp, int32_t* out_col,
+                    double* out_w, int64_t* out_m) {
+  int64_t nt = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (col[p] > i && q[i] != q[col[p]]) ++nt;
+  or_term* t = (or_term*)malloc(sizeof(or_term) * (size_t)(nt > 0 ? nt : 1));
+  int32_t* cnt = (int32_t*)calloc((size_t)nc + 1, sizeof(int32_t));
+  if (!t || !cnt) { free(t); free(cnt); return OR_E_NOMEM; }
+  int64_t k = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      int32_t j = col[p];
+      if (j > i && q[i] != q[j]) {
+        t[k].A = q[i] < q[j] ? q[i] : q[j];
+        t[k].B = q[i] < q[j] ? q[j] : q[i];
+        t[k].seq = k;
+        t[k].w = w[p];
+        ++k;
+      }
+    }
+  qsort(t, (size_t)nt, sizeof(or_term), or_term_cmp);
+  /* collapse runs: one upper-triangle entry per distinct (A,B) */
+  int64_t nu = 0;
+  for (int64_t s = 0; s < nt;) {
+    int64_t e = s;
+    double sum = 0.0;
+    while (e < nt && t[e].A == t[s].A && t[e].B == t[s].B) { sum += t[e].w; ++e; }
+    t[nu].A = t[s].A;
+    t[nu].B = t[s].B;
+    t[nu].w = sum;
+    ++nu;
+    s = e;
+  }
+  for (int64_t s = 0; s < nu; ++s) { cnt[t[s].A + 1]++; cnt[t[s].B + 1]++; }
+  out_rp[0] = 0;
+  for (int32_t c = 0; c < nc; ++c) out_rp[c + 1] = out_rp[c] + cnt[c + 1];
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc > 0 ? nc : 1));
+  if (!fill) { free(t); free(cnt); return OR_E_NOMEM; }
+  for (int32_t c = 0; c < nc; ++c) fill[c] = out_rp[c];
+  /* entries (B, A) with A < B come first in row B only if A is smaller than
+   * every upper neighbour of B; fill lower parts first (ascending A since the
+   * runs are sorted by A), then upper parts (ascending B). */
+  for (int64_t s = 0; s < nu; ++s) {
+    int32_t r = t[s].B;
+    out_col[fill[r]] = t[s].A;
+    out_w[fill[r]] = t[s].w;
+    fill[r]++;
+  }
+  for (int64_t s = 0; s < nu; ++s) {
+    int32_t r = t[s].A;
+    out_col[fill[r]] = t[s].B;
+    out_w[fill[r]] = t[s].w;
+    fill[r]++;
+  }
+  *out_m = 2 * nu;
+  free(fill);
+  free(t);
+  free(cnt);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Colouring for the multicolour Gauss-Seidel order.                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  uint32_t prio;
+  int32_t v;
+} or_prio;
+
+static int or_prio_cmp(const void* p, const void* q) {
+  const or_prio* x = (const or_prio*)p;
+  const or_prio* y = (const or_prio*)q;
+  if (x->prio != y->prio) return x->prio > y->prio ? -1 : 1;
+  return x->v < y->v ? -1 : (x->v > y->v ? 1 : 0);
+}
+
+/*
+ * Sequential first-fit colouring: vertices in decreasing priority (ties to
+ * the smaller index) each take the smallest colour no coloured neighbour has.
+ * Returns the number of colours.
+ */
+int32_t or_colour(int32_t n, const int32_t* rp, const int32_t* col, uint32_t level_seed,
+                  int32_t* colour) {
+  or_prio* o = (or_prio*)malloc(sizeof(or_prio) * (size_t)n);
+  int32_t maxdeg = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (rp[i + 1] - rp[i] > maxdeg) maxdeg = rp[i + 1] - rp[i];
+  char* used = (char*)calloc((size_t)maxdeg + 2, 1);
+  if (!o || !used) { free(o); free(used); return OR_E_NOMEM; }
+  for (int32_t v = 0; v < n; ++v) { o[v].prio = or_colour_priority(v, level_seed); o[v].v = v; }
+  qsort(o, (size_t)n, sizeof(or_prio), or_prio_cmp);
+  for (int32_t v = 0; v < n; ++v) colour[v] = -1;
+  int32_t ncol = 0;
+  for (int32_t t = 0; t < n; ++t) {
+    int32_t v = o[t].v;
+    for (int64_t p = rp[v]; p < rp[v + 1]; ++p) {
+      int32_t c = colour[col[p]];
+      if (c >= 0 && c <= maxdeg) used[c] = 1;
+    }
+    int32_t c = 0;
+    while (used[c]) ++c;
+    colour[v] = c;
+    if (c + 1 > ncol) ncol = c + 1;
+    for (int64_t p = rp[v]; p < rp[v + 1]; ++p) {
+      int32_t cc = colour[col[p]];
+      if (cc >= 0 && cc <= maxdeg) used[cc] = 0;
+    }
+  }
+  free(o);
+  free(used);
+  return ncol;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level operators.                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Shift sigma = 2 max_i d_i (Gershgorin bound on the spectrum of L). */
+double or_sigma(int32_t n, const int32_t* rp, const double* w) {
+  double mx = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    double d = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) d += w[p];
+    if (d > mx) mx = d;
+  }
+  return 2.0 * mx;
+}
+
+/* (L x)_i = sum_j w_ij (x_i - x_j), terms in CSR order. */
+static double or_lap_row(const int32_t* rp, const int32_t* col, const double* w,
+                         const double* x, int32_t i) {
+  double s = 0.0;
+  for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += w[p] * (x[i] - x[col[p]]);
+  return s;
+}
+
+/* y = sigma x - L x: one power-iteration step on the shifted Laplacian. */
+void or_pi_apply(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                 double sigma, const double* x, double* y) {
+  for (int32_t i = 0; i < n; ++i) y[i] = sigma * x[i] - or_lap_row(rp, col, w, x, i);
+}
+
+/*
+ * Whether row i takes part in a shifted sweep: its shifted diagonal d_i - rho
+ * must be at least d_i / 2.  A row below that (rho not small against its
+ * degree) keeps its value for the sweep, so the eigenvector stays a fixed
+ * point of the sweep; such rows are corrected by the power-iteration phase.
+ */
+static int or_row_active(double d, double rho) { return d > 0.0 && d - rho >= 0.5 * d; }
+
+/*
+ * One Gauss-Seidel sweep (Algorithm 2) on (L - rho I) x = 0, the eigenproblem
+ * written as a singular linear system with the current Rayleigh quotient as
+ * the shift.  Rows are visited colour by colour (ascending colour, ascending
+ * index inside a colour), in place:
+ *   x_i <- (1 - omega) x_i + omega sum_j w_ij x_j / (d_i - rho),
+ * d_i = sum_j w_ij, both sums in CSR order, for every active row (see
+ * or_row_active); omega = 1 is Gauss-Seidel, rho = 0 the plain sweep on
+ * L x = 0.
+ */
+void or_gs_sweep(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                 const int32_t* colour, int32_t ncolours, double rho, double omega, double* x) {
+  for (int32_t c = 0; c < ncolours; ++c)
+    for (int32_t i = 0; i < n; ++i) {
+      if (colour[i] != c) continue;
+      double num = 0.0, den = 0.0;
+      for (int64_t p = rp[i]; p < rp[i + 1]; ++p) { num += w[p] * x[col[p]]; den += w[p]; }
+      if (or_row_active(den, rho)) {
+        double g = num / (den - rho);
+        x[i] = omega == 1.0 ? g : (1.0 - omega) * x[i] + omega * g;
+      }
+    }
+}
+
+/* The same sweep in the lexicographic order i = 1..n that Algorithm 2 prints
+ * (oracle-only mode). */
+void or_gs_sweep_lex(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                     double rho, double* x) {
+  for (int32_t i = 0; i < n; ++i) {
+    double num = 0.0, den = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) { num += w[p] * x[col[p]]; den += w[p]; }
+    if (or_row_active(den, rho)) x[i] = num / (den - rho);
+  }
+}
+
+/* x <- (x - mean) / ||x - mean||_2: projection against the all-ones null
+ * vector, then unit length. */
+static void or_project_normalise(int32_t n, double* x) {
+  double s = 0.0;
+  for (int32_t i = 0; i < n; ++i) s += x[i];
+  double mu = s / (double)n;
+  double nn = 0.0;
+  for (int32_t i = 0; i < n; ++i) { x[i] -= mu; nn += x[i] * x[i]; }
+  double inv = 1.0 / sqrt(nn);
+  for (int32_t i = 0; i < n; ++i) x[i] *= inv;
+}
+
+void or_project_normalise_export(int32_t n, double* x) { or_project_normalise(n, x); }
+
+static double or_dot(int32_t n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+/*
+ * Rayleigh quotient rho = sum_{i<j} w_ij (x_i - x_j)^2 / sum x_i^2 and
+ * residual ||L x - rho x|| / ||x|| (finest-level eigenvalue estimate).
+ */
+void or_rq_residual(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                    const double* x, double* rho_out, double* res_out) {
+  double num = 0.0, den = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    double e = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      double d = x[i] - x[col[p]];
+      e += w[p] * d * d;
+    }
+    num += 0.5 * e;
+    den += x[i] * x[i];
+  }
+  double rho = num / den;
+  double r2 = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    double r = or_lap_row(rp, col, w, x, i) - rho * x[i];
+    r2 += r * r;
+  }
+  *rho_out = rho;
+  *res_out = sqrt(r2 / den);
+}
+
+/* Random start on the coarsest level: x_i = 2 u_i - 1, u_i the i-th uniform
+ * of SplitMix64(seed) with 53 bits. */
+void or_random_start(int32_t n, uint64_t seed, double* x) {
+  uint64_t s = seed;
+  for (int32_t i = 0; i < n; ++i) {
+    uint64_t z = or_splitmix64(&s);
+    double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    x[i] = 2.0 * u - 1.0;
+  }
+}
+
+/*
+ * Coarsest-level solve (Algorithm 3, Step 2; the text calls it a direct power
+ * iteration): power iteration on B = sigma I - L with the all-ones vector
+ * projected out, from the seeded random start.  Before each step the residual
+ * ||L x - (x^T L x) x|| of the unit iterate is compared with 1e-13 sigma; the
+ * loop ends below it or after max_it steps.  replay_it >= 0 forces exactly that
+ * many steps instead.  Returns the number of steps taken.
+ */
+int32_t or_coarsest(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                    double sigma, uint64_t seed, int32_t max_it, int32_t replay_it,
+                    double* x, int32_t* converged) {
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  double* lx = (double*)malloc(sizeof(double) * (size_t)n);
+  or_random_start(n, seed, x);
+  or_project_normalise(n, x);
+  int32_t it = 0;
+  *converged = 0;
+  for (;;) {
+    if (replay_it >= 0) {
+      if (it >= replay_it) { *converged = 1; break; }
+    } else {
+      for (int32_t i = 0; i < n; ++i) lx[i] = or_lap_row(rp, col, w, x, i);
+      double rho = or_dot(n, x, lx);
+      double r2 = 0.0;
+      for (int32_t i = 0; i < n; ++i) { double r = lx[i] - rho * x[i]; r2 += r * r; }
+      if (sqrt(r2) <= 1e-13 * sigma) { *converged = 1; break; }
+      if (it >= max_it) break;
+    }
+    or_pi_apply(n, rp, col, w, sigma, x, y);
+    or_project_normalise(n, y);
+    memcpy(x, y, sizeof(double) * (size_t)n);
+    ++it;
+  }
+  free(y);
+  free(lx);
+  return it;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchy (Algorithm 3, Step 1).                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t n;
+  int64_t m;
+  int32_t* rp;
+  int32_t* col;
+  double* w;
+  int32_t* q;      /* to the next level; NULL on the coarsest */
+  int32_t* colour; /* NULL on the coarsest */
+  int32_t ncolours;
+  double sigma;
+} or_level;
+
+typedef struct {
+  int32_t nlevels;
+  or_level lv[OR_MAX_LEVELS];
+} or_hier;
+
+void or_hier_free(void* hp) {
+  or_hier* h = (or_hier*)hp;
+  if (!h) return;
+  for (int32_t l = 0; l < h->nlevels; ++l) {
+    free(h->lv[l].rp);
+    free(h->lv[l].col);
+    free(h->lv[l].w);
+    free(h->lv[l].q);
+    free(h->lv[l].colour);
+  }
+  free(h);
+}
+
+/*
+ * Builds the hierarchy from the adjacency W of the finest graph: while the
+ * level has more than n_coarse vertices, aggregate (matching + attach), form
+ * the Galerkin coarse graph, and colour the level for the smoother.  The loop
+ * also stops when the next level would have fewer than 2 vertices or would not
+ * be smaller, and at max_levels levels.
+ */
+void* or_hier_build(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                    int32_t n_coarse, int32_t max_levels, uint64_t colour_seed,
+                    int32_t* status) {
+  or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
+  if (!h) { *status = OR_E_NOMEM; return NULL; }
+  if (max_levels < 1) max_levels = 1;
+  if (max_levels > OR_MAX_LEVELS) max_levels = OR_MAX_LEVELS;
+  int64_t m = rp[n];
+  or_level* L0 = &h->lv[0];
+  L0->n = n;
+  L0->m = m;
+  L0->rp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  L0->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  L0->w = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  memcpy(L0->rp, rp, sizeof(int32_t) * (size_t)(n + 1));
+  memcpy(L0->col, col, sizeof(int32_t) * (size_t)m);
+  memcpy(L0->w, w, sizeof(double) * (size_t)m);
+  h->nlevels = 1;
+  int32_t l = 0;
+  for (;;) {
+    or_level* F = &h->lv[l];
+    F->sigma = or_sigma(F->n, F->rp, F->w);
+    if (F->n <= n_coarse || l + 1 >= max_levels) break;
+    int32_t* mate = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
+    int32_t st = or_match(F->n, F->rp, F->col, F->w, mate);
+    int32_t nc = st == OR_OK ? or_aggregate(F->n, F->rp, F->col, F->w, mate, q) : st;
+    free(mate);
+    if (nc < 0) { free(q); or_hier_free(h); *status = nc; return NULL; }
+    if (nc < 2 || nc >= F->n) { free(q); break; }
+    F->q = q;
+    F->colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
+    F->ncolours = or_colour(F->n, F->rp, F->col, or_level_seed(colour_seed, l), F->colour);
+    or_level* C = &h->lv[l + 1];
+    C->n = nc;
+    C->rp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc + 1));
+    C->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(F->m > 0 ? F->m : 1));
+    C->w = (double*)malloc(sizeof(double) * (size_t)(F->m > 0 ? F->m : 1));
+    or_galerkin(F->n, F->rp, F->col, F->w, q, nc, C->rp, C->col, C->w, &C->m);
+    h->nlevels = l + 2;
+    ++l;
+  }
+  *status = OR_OK;
+  return h;
+}
+
+int32_t or_hier_nlevels(const void* hp) { return ((const or_hier*)hp)->nlevels; }
+
+/* info = {n, m, ncolours}; sigma returned. */
+double or_hier_level_info(const void* hp, int32_t l, int64_t* info) {
+  const or_level* L = &((const or_hier*)hp)->lv[l];
+  info[0] = L->n;
+  info[1] = L->m;
+  info[2] = L->ncolours;
+  return L->sigma;
+}
+
+void or_hier_level_copy(const void* hp, int32_t l, int32_t* rp, int32_t* col, double* w,
+                        int32_t* q, int32_t* colour) {
+  const or_level* L = &((const or_hier*)hp)->lv[l];
+  memcpy(rp, L->rp, sizeof(int32_t) * (size_t)(L->n + 1));
+  memcpy(col, L->col, sizeof(int32_t) * (size_t)L->m);
+  memcpy(w, L->w, sizeof(double) * (size_t)L->m);
+  if (q && L->q) memcpy(q, L->q, sizeof(int32_t) * (size_t)L->n);
+  if (colour && L->colour) memcpy(colour, L->colour, sizeof(int32_t) * (size_t)L->n);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solve (Algorithm 3, Steps 2 and 3, then the finest Rayleigh quotient).    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  uint64_t seed;
+  double tol_cos;      /* stop a phase when (x_k, x_{k-1}) > 1 - tol_cos */
+  double tol_res;      /* > 0: repeat level-0 phases until residual <= tol_res */
+  int32_t max_gs;      /* sweeps per smoothing phase */
+  int32_t max_pi;      /* steps per power-iteration phase */
+  int32_t max_outer;   /* extra level-0 rounds for tol_res */
+  int32_t max_coarsest;
+  int32_t gs_lexicographic; /* 1: paper's lexicographic order (oracle-only) */
+  int32_t gs_unshifted;     /* 1: plain sweeps on L x = 0 (oracle-only) */
+  double omega;             /* relaxation factor of the sweep; 1 = Gauss-Seidel */
+  const int32_t* replay;    /* NULL, or the phase counts to execute exactly */
+  int32_t replay_len;
+} or_solve_params;
+
+/* Rayleigh quotient x^T L x / x^T x in the edge form of or_rq_residual. */
+static double or_rq(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                    const double* x) {
+  double num = 0.0, den = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    double e = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      double d = x[i] - x[col[p]];
+      e += w[p] * d * d;
+    }
+    num += 0.5 * e;
+    den += x[i] * x[i];
+  }
+  return num / den;
+}
+
+double or_rq_export(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                    const double* x) {
+  return or_rq(n, rp, col, w, x);
+}
+
+/* One smoothing phase: each sweep takes the Rayleigh quotient of the current
+ * (unit, mean-free) iterate as its shift; sweeps continue until the cosine
+ * test passes or the cap. */
+static int32_t or_gs_phase(const or_level* L, const or_solve_params* P, int32_t forced,
+                           double* x, double* xp, double* cos_out) {
+  int32_t k = 0;
+  double c = 0.0;
+  for (;;) {
+    if (k >= (forced >= 0 ? forced : P->max_gs)) break;
+    memcpy(xp, x, sizeof(double) * (size_t)L->n);
+    double rho = P->gs_unshifted ? 0.0 : or_rq(L->n, L->rp, L->col, L->w, x);
+    if (P->gs_lexicographic)
+      or_gs_sweep_lex(L->n, L->rp, L->col, L->w, rho, x);
+    else
+      or_gs_sweep(L->n, L->rp, L->col, L->w, L->colour, L->ncolours, rho, P->omega, x);
+    or_project_normalise(L->n, x);
+    ++k;
+    c = or_dot(L->n, x, xp);
+    if (forced < 0 && c > 1.0 - P->tol_cos) break;
+  }
+  *cos_out = c;
+  return k;
+}
+
+/* One power-iteration phase on B = sigma I - L (projected). */
+static int32_t or_pi_phase(const or_level* L, const or_solve_params* P, int32_t forced,
+                           double* x, double* y, double* cos_out) {
+  int32_t k = 0;
+  double c = 0.0;
+  for (;;) {
+    if (k >= (forced >= 0 ? forced : P->max_pi)) break;
+    or_pi_apply(L->n, L->rp, L->col, L->w, L->sigma, x, y);
+    or_project_normalise(L->n, y);
+    ++k;
+    c = or_dot(L->n, x, y);
+    memcpy(x, y, sizeof(double) * (size_t)L->n);
+    if (forced < 0 && c > 1.0 - P->tol_cos) break;
+  }
+  *cos_out = c;
+  return k;
+}
+
+/* Output sign: the first entry with |x_i| >= 1e-3 max|x| is made positive. */
+void or_fix_sign(int32_t n, double* x) {
+  double mx = 0.0;
+  for (int32_t i = 0; i < n; ++i) if (fabs(x[i]) > mx) mx = fabs(x[i]);
+  for (int32_t i = 0; i < n; ++i)
+    if (fabs(x[i]) >= 1e-3 * mx) {
+      if (x[i] < 0.0) for (int32_t j = 0; j < n; ++j) x[j] = -x[j];
+      break;
+    }
+}
+
+/*
+ * Full solve on a built hierarchy.  counts receives the executed schedule:
+ * [coarsest steps, (gs, pi) for levels J-1 .. 0, then (gs, pi) per extra
+ * level-0 round]; scal = {lambda, residual, last cosine}.  Returns OR_OK, or
+ * OR_E_NOT_CONVERGED when tol_res was not met or the coarsest solve hit its
+ * cap (x and scal are filled either way).
+ */
+int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double* scal,
+                 int32_t* counts, int32_t counts_cap, int32_t* counts_len) {
+  const or_hier* h = (const or_hier*)hp;
+  int32_t J = h->nlevels - 1;
+  int32_t nmax = h->lv[0].n;
+  double* x = (double*)malloc(sizeof(double) * (size_t)nmax);
+  double* y = (double*)malloc(sizeof(double) * (size_t)nmax);
+  double* t = (double*)malloc(sizeof(double) * (size_t)nmax);
+  if (!x || !y || !t) { free(x); free(y); free(t); return OR_E_NOMEM; }
+  int32_t nc_out = 0;
+  int32_t status = OR_OK;
+  const int32_t* R = P->replay;
+  int32_t ri = 0;
+#define OR_NEXT_FORCED() ((R && ri < P->replay_len) ? R[ri++] : -1)
+#define OR_PUSH(v) do { if (nc_out < counts_cap) counts[nc_out] = (v); ++nc_out; } while (0)
+  const or_level* C = &h->lv[J];
+  int32_t conv = 0;
+  int32_t cit = or_coarsest(C->n, C->rp, C->col, C->w, C->sigma, P->seed, P->max_coarsest,
+                            OR_NEXT_FORCED(), x, &conv);
+  if (!conv) status = OR_E_NOT_CONVERGED;
+  OR_PUSH(cit);
+  double cosv = 1.0;
+  for (int32_t l = J - 1; l >= 0; --l) {
+    const or_level* F = &h->lv[l];
+    /* prolongation y^l = I^T y^{l+1}: x_f[i] = x_c[q(i)] */
+    for (int32_t i = 0; i < F->n; ++i) y[i] = x[F->q[i]];
+    memcpy(x, y, sizeof(double) * (size_t)F->n);
+    or_project_normalise(F->n, x);
+    int32_t g = or_gs_phase(F, P, OR_NEXT_FORCED(), x, t, &cosv);
+    int32_t p = or_pi_phase(F, P, OR_NEXT_FORCED(), x, y, &cosv);
+    OR_PUSH(g);
+    OR_PUSH(p);
+  }
+  const or_level* F0 = &h->lv[0];
+  double rho, res;
+  or_rq_residual(F0->n, F0->rp, F0->col, F0->w, x, &rho, &res);
+  int32_t outer = 0;
+  for (;;) {
+    int32_t fg, fp;
+    if (R) {
+      if (ri >= P->replay_len) break;
+      fg = OR_NEXT_FORCED();
+      fp = OR_NEXT_FORCED();
+    } else {
+      if (!(P->tol_res > 0.0) || res <= P->tol_res || outer >= P->max_outer) break;
+      fg = fp = -1;
+    }
+    if (J == 0) break; /* a one-level hierarchy is solved by the coarsest solve */
+    int32_t g = or_gs_phase(F0, P, fg, x, t, &cosv);
+    int32_t p = or_pi_phase(F0, P, fp, x, y, &cosv);
+    OR_PUSH(g);
+    OR_PUSH(p);
+    ++outer;
+    or_rq_residual(F0->n, F0->rp, F0->col, F0->w, x, &rho, &res);
+  }
+  if (!R && P->tol_res > 0.0 && res > P->tol_res) status = OR_E_NOT_CONVERGED;
+  or_fix_sign(F0->n, x);
+  memcpy(x_out, x, sizeof(double) * (size_t)F0->n);
+  scal[0] = rho;
+  scal[1] = res;
+  scal[2] = cosv;
+  *counts_len = nc_out;
+#undef OR_NEXT_FORCED
+#undef OR_PUSH
+  free(x);
+  free(y);
+  free(t);
+  return status;
+}

@@ -1,0 +1,474 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix,
+independently of the oracle's own code:
+
+* closed forms: path and grid Laplacian spectra (lambda_2 = 2 - 2cos(pi/n) and
+  2 - 2cos(pi/max(m,k)) for unit weights; the path Fiedler vector is
+  cos(pi(i + 1/2)/n));
+* dense brute force: numpy eigh on graphs of <= 64 vertices, the Galerkin
+  product I L I^T formed densely, the Gauss-Seidel sweep written as a matrix
+  splitting and solved with numpy, the power step as a dense product;
+* independent algorithms: the locally dominant pointer-round matching and the
+  Jones-Plassmann colouring simulated in Python must reproduce the oracle's
+  sequential greedy matching and first-fit colouring;
+* invariants: symmetry, zero row sums, connectivity, halving of levels, the
+  eigenvector as a fixed point of the shifted sweep, Courant-Fischer against
+  scipy's eigsh on a 30k-vertex grid.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import connected_components
+
+import gen
+
+
+def fmix32(h):
+    h ^= h >> 16
+    h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+    h ^= h >> 13
+    h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+    h ^= h >> 16
+    return h
+
+
+def pair_hash(a, b):
+    return fmix32(fmix32(a) ^ b)
+
+
+def dense_W(n, rp, col, w):
+    A = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A[rows, col] = w
+    return A
+
+
+def dense_L(n, rp, col, w):
+    A = dense_W(n, rp, col, w)
+    return np.diag(A.sum(1)) - A
+
+
+# ---------------------------------------------------------------- hashes --
+
+def test_hashes_match_published_finaliser(orc):
+    assert fmix32(1) == 0x514E28B7  # MurmurHash3 fmix32 of 1
+    for a, b in [(0, 1), (5, 9), (123456, 7654321)]:
+        assert orc.pair_hash(a, b) == pair_hash(a, b)
+    s = orc.level_seed(0x1234567890ABCDEF, 3)
+    assert s == fmix32(0x90ABCDEF ^ fmix32((0x12345678 + 3) & 0xFFFFFFFF))
+    assert orc.colour_priority(17, s) == fmix32(17 ^ s)
+
+
+def test_random_start_is_splitmix(orc):
+    x = orc.random_start(5, 42)
+    assert np.array_equal(x, 2.0 * gen.uniform01(42, 5) - 1.0)
+
+
+# ------------------------------------------------------------ validation --
+
+def _lap(g):
+    return g.laplacian()
+
+
+def test_validation_accepts_both_forms(orc):
+    g = gen.random_connected(30, 2)
+    st, W1 = orc.input_to_adjacency(g.n, g.rowptr, g.col, g.w, True)
+    rp, col, val = _lap(g)
+    st2, W2 = orc.input_to_adjacency(g.n, rp, col, val, False)
+    assert st == 0 and st2 == 0
+    for a, b in zip(W1, W2):
+        assert np.array_equal(a, b)
+
+
+def test_validation_error_codes(orc):
+    g = gen.random_connected(12, 3)
+    rp, col, w = g.rowptr.copy(), g.col.copy(), g.w.copy()
+    # asymmetric value
+    w2 = w.copy()
+    w2[0] += 1e-3
+    assert orc.input_to_adjacency(g.n, rp, col, w2, True)[0] == orc.E_NOT_SYMMETRIC
+    # negative weight in adjacency form
+    w3 = w.copy()
+    w3[1] = -w3[1]
+    assert orc.input_to_adjacency(g.n, rp, col, w3, True)[0] == orc.E_NOT_LAPLACIAN
+    # unsorted columns in a row
+    c2 = col.copy()
+    a = rp[0]
+    c2[a], c2[a + 1] = c2[a + 1], c2[a]
+    assert orc.input_to_adjacency(g.n, rp, c2, w, True)[0] == orc.E_INVALID
+    # column out of range
+    c3 = col.copy()
+    c3[-1] = g.n
+    assert orc.input_to_adjacency(g.n, rp, c3, w, True)[0] == orc.E_INVALID
+    # n < 2
+    assert orc.input_to_adjacency(1, np.array([0, 0]), np.zeros(0), np.zeros(0), True)[0] == \
+        orc.E_INVALID
+    # Laplacian with a wrong diagonal
+    lrp, lcol, lval = _lap(g)
+    lv = lval.copy()
+    lv[np.nonzero(lcol[lrp[0]:lrp[1]] == 0)[0][0] + lrp[0]] += 1.0
+    assert orc.input_to_adjacency(g.n, lrp, lcol, lv, False)[0] == orc.E_NOT_LAPLACIAN
+    # isolated vertex: path 0-1 plus a vertex 2 without edges
+    rp4 = np.array([0, 1, 2, 2])
+    assert orc.input_to_adjacency(3, rp4, np.array([1, 0]), np.array([1.0, 1.0]), True)[0] == \
+        orc.E_ISOLATED
+
+
+# --------------------------------------------------------------- matching --
+
+def _edges(n, rp, col, w):
+    E = []
+    for i in range(n):
+        for p in range(rp[i], rp[i + 1]):
+            j = int(col[p])
+            if j > i:
+                E.append((float(w[p]), i, j))
+    return E
+
+
+def _key(wv, a, b):
+    return (-wv, pair_hash(a, b), a, b)
+
+
+def pointer_round_matching(n, rp, col, w):
+    """Locally dominant matching by synchronous pointer rounds (an algorithm
+    different from the oracle's sorted greedy)."""
+    mate = [-1] * n
+    while True:
+        ptr = [-1] * n
+        for v in range(n):
+            if mate[v] != -1:
+                continue
+            best = None
+            for p in range(rp[v], rp[v + 1]):
+                u = int(col[p])
+                if mate[u] != -1:
+                    continue
+                k = _key(float(w[p]), min(u, v), max(u, v))
+                if best is None or k < best[0]:
+                    best = (k, u)
+            ptr[v] = -1 if best is None else best[1]
+        active = False
+        new = list(mate)
+        for v in range(n):
+            if mate[v] != -1:
+                continue
+            u = ptr[v]
+            if u < 0:
+                new[v] = -2
+            elif ptr[u] == v:
+                new[v] = u
+            else:
+                active = True
+        mate = new
+        if not active:
+            return [m if m >= 0 else -1 for m in mate]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_matching_equals_pointer_rounds(orc, seed):
+    if seed % 3 == 0:
+        g = gen.grid(6 + seed % 5, 5, "unit")  # all weights tie: the hash decides
+    elif seed % 3 == 1:
+        g = gen.random_connected(40 + seed, seed)
+    else:
+        g = gen.random_connected(30 + seed, seed, dyadic=True)  # many weight ties
+    mate = orc.match(g.n, g.rowptr, g.col, g.w)
+    assert list(mate) == pointer_round_matching(g.n, g.rowptr, g.col, g.w)
+
+
+def test_matching_is_maximal_and_greedy(orc):
+    g = gen.random_connected(60, 5)
+    mate = orc.match(g.n, g.rowptr, g.col, g.w)
+    E = _edges(g.n, g.rowptr, g.col, g.w)
+    for wv, a, b in E:
+        if mate[a] == b:
+            continue
+        # a non-matching edge has a matched neighbour edge that comes first
+        assert mate[a] >= 0 or mate[b] >= 0
+        earlier = False
+        for x in (a, b):
+            if mate[x] >= 0:
+                y = int(mate[x])
+                we = [float(g.w[p]) for p in range(g.rowptr[x], g.rowptr[x + 1]) if g.col[p] == y][0]
+                if _key(we, min(x, y), max(x, y)) < _key(wv, a, b):
+                    earlier = True
+        assert earlier
+
+
+# ------------------------------------------------------------ aggregation --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_aggregation_rule(orc, seed):
+    g = gen.random_connected(50 + 7 * seed, 100 + seed) if seed % 2 else gen.grid(9, 7, "unit")
+    mate = orc.match(g.n, g.rowptr, g.col, g.w)
+    q, nc = orc.aggregate(g.n, g.rowptr, g.col, g.w, mate)
+    # independent construction of the aggregates
+    root = {}
+    for v in range(g.n):
+        if mate[v] >= 0:
+            root[v] = min(v, int(mate[v]))
+    for v in range(g.n):
+        if mate[v] < 0:
+            best = min(((_key(float(g.w[p]), min(v, int(g.col[p])), max(v, int(g.col[p]))),
+                         int(g.col[p])) for p in range(g.rowptr[v], g.rowptr[v + 1])))[1]
+            root[v] = min(best, int(mate[best]))
+    groups = {}
+    for v in range(g.n):
+        groups.setdefault(root[v], []).append(v)
+    leaders = sorted(min(m) for m in groups.values())
+    expect = np.zeros(g.n, np.int64)
+    for members in groups.values():
+        expect[members] = leaders.index(min(members))
+    assert nc == len(groups)
+    assert np.array_equal(q, expect)
+    assert all(len(m) >= 2 for m in groups.values())
+    assert nc <= g.n // 2
+
+
+# --------------------------------------------------------------- Galerkin --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_galerkin_equals_dense_product_exactly(orc, seed):
+    g = gen.random_connected(40 + 5 * seed, 200 + seed, dyadic=True)
+    mate = orc.match(g.n, g.rowptr, g.col, g.w)
+    q, nc = orc.aggregate(g.n, g.rowptr, g.col, g.w, mate)
+    crp, ccol, cw = orc.galerkin(g.n, g.rowptr, g.col, g.w, q, nc)
+    I = np.zeros((nc, g.n))
+    I[q, np.arange(g.n)] = 1.0
+    Lc = I @ dense_L(g.n, g.rowptr, g.col, g.w) @ I.T
+    Lo = dense_L(nc, crp, ccol, cw)
+    assert np.array_equal(Lc, Lo)  # dyadic weights: every sum is exact
+    for r in range(nc):
+        assert np.all(np.diff(ccol[crp[r]:crp[r + 1]]) > 0)
+
+
+def test_galerkin_random_weights_symmetric_bitwise(orc):
+    g = gen.random_connected(300, 9)
+    mate = orc.match(g.n, g.rowptr, g.col, g.w)
+    q, nc = orc.aggregate(g.n, g.rowptr, g.col, g.w, mate)
+    crp, ccol, cw = orc.galerkin(g.n, g.rowptr, g.col, g.w, q, nc)
+    Wc = dense_W(nc, crp, ccol, cw)
+    assert np.array_equal(Wc, Wc.T)
+    I = np.zeros((nc, g.n))
+    I[q, np.arange(g.n)] = 1.0
+    Lc = I @ dense_L(g.n, g.rowptr, g.col, g.w) @ I.T
+    W_expect = np.diag(np.diag(Lc)) - Lc
+    assert np.allclose(Wc, W_expect, rtol=1e-14, atol=1e-14)
+
+
+# -------------------------------------------------------------- colouring --
+
+def jones_plassmann(n, rp, col, seed):
+    """Parallel rounds: colour a vertex once all higher-priority neighbours are
+    coloured (an algorithm different from the oracle's sorted first-fit)."""
+    pr = [fmix32(v ^ seed) for v in range(n)]
+    colour = [-1] * n
+    while -1 in colour:
+        snap = list(colour)
+        for v in range(n):
+            if snap[v] >= 0:
+                continue
+            nb = [int(col[p]) for p in range(rp[v], rp[v + 1])]
+            if any(snap[u] < 0 and (pr[u] > pr[v] or (pr[u] == pr[v] and u < v)) for u in nb):
+                continue
+            used = {snap[u] for u in nb if snap[u] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            colour[v] = c
+    return colour
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_colouring_equals_jones_plassmann(orc, seed):
+    g = gen.random_connected(60 + seed, 300 + seed) if seed % 2 else gen.grid(8, 6 + seed)
+    s = orc.level_seed(seed, seed)
+    c, k = orc.colour(g.n, g.rowptr, g.col, s)
+    assert list(c) == jones_plassmann(g.n, g.rowptr, g.col, s)
+    assert k == max(c) + 1
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    assert np.all(c[rows] != c[g.col])  # proper colouring
+    assert k <= np.diff(g.rowptr).max() + 1
+
+
+# ------------------------------------------------------ smoother and power --
+
+def _colour_order(c):
+    return np.lexsort((np.arange(len(c)), c))
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.5])
+def test_gs_sweep_is_matrix_splitting(orc, omega):
+    g = gen.random_connected(48, 17)
+    c, k = orc.colour(g.n, g.rowptr, g.col, orc.level_seed(0, 0))
+    x = np.sin(np.arange(g.n) * 0.7)
+    rho = 0.05
+    W = dense_W(g.n, g.rowptr, g.col, g.w)
+    d = W.sum(1)
+    o = _colour_order(c)
+    Wp = W[np.ix_(o, o)]
+    Dp = np.diag(np.maximum(d[o] - rho, 0.5 * d[o]))
+    Wl, Wu = np.tril(Wp, -1), np.triu(Wp, 1)
+    # SOR splitting: (D - omega W_l) x' = ((1 - omega) D + omega W_u) x
+    xp = np.linalg.solve(Dp - omega * Wl, ((1 - omega) * Dp + omega * Wu) @ x[o])
+    expect = np.empty(g.n)
+    expect[o] = xp
+    got = oracle_sweep(orc, g, c, k, x, rho, omega)
+    assert np.allclose(got, expect, rtol=1e-13, atol=1e-13)
+
+
+def oracle_sweep(orc, g, c, k, x, rho, omega):
+    import ctypes as C
+    xx = np.ascontiguousarray(x, dtype=np.float64).copy()
+    orc.lib().or_gs_sweep(g.n, g.rowptr, g.col, g.w, np.ascontiguousarray(c, np.int32), k, rho,
+                          omega, xx)
+    return xx
+
+
+def test_fiedler_vector_is_fixed_point_of_shifted_sweep(orc):
+    # weighted grid: lambda_2 < min degree / 2, so the shift guard is inactive
+    g = gen.grid(12, 10, "uniform", seed=1)
+    L = dense_L(g.n, g.rowptr, g.col, g.w)
+    ev, V = np.linalg.eigh(L)
+    phi = V[:, 1]
+    c, k = orc.colour(g.n, g.rowptr, g.col, 7)
+    out = oracle_sweep(orc, g, c, k, phi, ev[1], 1.0)
+    assert np.allclose(out, phi, atol=1e-12)
+    # the unshifted sweep of the b = 0 reading does not keep it (non-regular graph)
+    out0 = oracle_sweep(orc, g, c, k, phi, 0.0, 1.0)
+    assert np.linalg.norm(orc.project_normalise(out0) - phi) > 1e-3
+    # the all-ones vector is a fixed point of the unshifted sweep
+    one = np.ones(g.n)
+    assert np.allclose(oracle_sweep(orc, g, c, k, one, 0.0, 1.0), one, atol=1e-15)
+
+
+def test_power_step_and_sigma(orc):
+    g = gen.random_connected(30, 4)
+    L = dense_L(g.n, g.rowptr, g.col, g.w)
+    sig = orc.sigma(g.n, g.rowptr, g.w)
+    def row_sum(i):  # sequential, in row order
+        s = 0.0
+        for v in g.w[g.rowptr[i]:g.rowptr[i + 1]]:
+            s += float(v)
+        return s
+
+    assert sig == 2.0 * max(row_sum(i) for i in range(g.n))
+    assert sig >= np.linalg.eigvalsh(L).max()  # Gershgorin: B = sigma I - L >= 0
+    x = np.cos(np.arange(g.n))
+    assert np.allclose(orc.pi_apply(g.n, g.rowptr, g.col, g.w, sig, x), sig * x - L @ x,
+                       rtol=1e-14, atol=1e-13)
+
+
+def test_rayleigh_and_residual_dense(orc):
+    g = gen.random_connected(35, 8)
+    L = dense_L(g.n, g.rowptr, g.col, g.w)
+    x = np.sin(np.arange(g.n) * 1.3) + 0.2
+    rho, res = orc.rq_residual(g.n, g.rowptr, g.col, g.w, x)
+    r_exp = x @ L @ x / (x @ x)
+    assert abs(rho - r_exp) <= 1e-14 * abs(r_exp)
+    assert abs(res - np.linalg.norm(L @ x - r_exp * x) / np.linalg.norm(x)) < 1e-13
+
+
+# --------------------------------------------------------------- coarsest --
+
+@pytest.mark.parametrize("seed", range(5))
+def test_coarsest_power_iteration_vs_eigh(orc, seed):
+    g = gen.random_connected(8 + 4 * seed, 50 + seed)
+    L = dense_L(g.n, g.rowptr, g.col, g.w)
+    ev, V = np.linalg.eigh(L)
+    sig = orc.sigma(g.n, g.rowptr, g.w)
+    x, it, conv = orc.coarsest(g.n, g.rowptr, g.col, g.w, sig, seed + 1)
+    assert conv
+    lam = x @ L @ x
+    assert abs(lam - ev[1]) <= 1e-12 * max(1.0, ev[1])
+    if ev[2] - ev[1] > 1e-3:
+        assert 1 - abs(x @ V[:, 1]) <= 1e-12
+    assert abs(x.sum()) < 1e-12 and abs(np.linalg.norm(x) - 1) < 1e-14
+
+
+# ------------------------------------------------------------ whole solve --
+
+TIGHT = dict(tol_cos=1e-10, tol_res=1e-9, max_gs=2000, max_pi=50, max_outer=20000)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 9, 16, 33, 64])
+def test_path_closed_form(orc, n):
+    g = gen.path(n)
+    h, r = orc.solve_graph(g, n_coarse=8, **TIGHT)
+    lam = 2.0 - 2.0 * math.cos(math.pi / n)
+    assert r.status == 0
+    assert abs(r.lam - lam) <= 1e-9 * lam
+    phi = np.cos(math.pi * (np.arange(n) + 0.5) / n)
+    phi /= np.linalg.norm(phi)
+    assert 1 - abs(r.x @ phi) <= 1e-8
+    assert r.x[0] > 0  # sign convention: first significant entry positive
+
+
+@pytest.mark.parametrize("m,k", [(32, 24), (12, 7), (20, 9)])
+def test_grid_closed_form(orc, m, k):
+    g = gen.grid(m, k)
+    h, r = orc.solve_graph(g, n_coarse=8, **TIGHT)
+    lam = 2.0 - 2.0 * math.cos(math.pi / max(m, k))
+    assert r.status == 0
+    assert abs(r.lam - lam) <= 1e-9 * lam
+    if (m, k) == (32, 24):
+        assert abs(lam - 0.009630546655606143) < 1e-17
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_graph_vs_eigh(orc, seed):
+    g = gen.random_connected(64, 900 + seed)
+    ev, V = np.linalg.eigh(dense_L(g.n, g.rowptr, g.col, g.w))
+    h, r = orc.solve_graph(g, n_coarse=8, **TIGHT)
+    assert r.status == 0
+    # residual bound (Kato-Temple): |rho - lambda_2| <= r^2 / (lambda_3 - rho)
+    assert abs(r.lam - ev[1]) <= r.residual ** 2 / (ev[2] - r.lam) + 1e-12
+    assert abs(r.lam - ev[1]) <= 1e-9 * ev[1]
+
+
+def test_large_grid_courant_fischer_vs_eigsh(orc):
+    from scipy.sparse.linalg import eigsh
+
+    g = gen.grid(200, 150, "uniform", seed=2)
+    A = csr_matrix((g.w, g.col, g.rowptr), shape=(g.n, g.n))
+    L = (csr_matrix(np.diag(np.asarray(A.sum(1)).ravel())) - A).tocsc()
+    vals = eigsh(L, k=3, sigma=-1e-3, which="LM", return_eigenvectors=False)
+    lam2, lam3 = sorted(vals)[1], sorted(vals)[2]
+    h, r = orc.solve_graph(g, n_coarse=25, tol_cos=1e-12, max_gs=2000, max_pi=5)
+    assert r.lam >= lam2 - 1e-15  # Courant-Fischer: x orthogonal to ones
+    assert r.lam - lam2 <= r.residual ** 2 / (lam3 - r.lam) + 1e-15
+    assert abs(r.x.sum()) < 1e-10 and abs(np.linalg.norm(r.x) - 1) < 1e-12
+
+
+# ------------------------------------------------------ hierarchy invariants --
+
+@pytest.mark.parametrize("which", ["grid", "rgg", "er", "rand"])
+def test_hierarchy_invariants(orc, which):
+    g = {"grid": gen.grid(40, 30, "uniform", seed=1), "rgg": gen.rgg(3000, 4),
+         "er": gen.erdos_renyi(2000, 6 / 1999, 6), "rand": gen.random_connected(500, 3)}[which]
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=10)
+    tot = g.w.sum()
+    for l in range(h.nlevels):
+        L = h.level(l)
+        W = csr_matrix((L.w, L.col, L.rowptr), shape=(L.n, L.n))
+        assert (W != W.T).nnz == 0 and np.all(L.w > 0)
+        assert connected_components(W, directed=False)[0] == 1
+        assert np.all(np.diff(L.rowptr) > 0)  # no isolated vertex
+        if l + 1 < h.nlevels:
+            assert h.level(l + 1).n <= L.n // 2
+            q = L.q
+            rows = np.repeat(np.arange(L.n), np.diff(L.rowptr))
+            inner = L.w[q[rows] == q[L.col]].sum()
+            assert abs(h.level(l + 1).w.sum() - (L.w.sum() - inner)) <= 1e-9 * tot
+    assert h.level(h.nlevels - 1).n <= 10
+
+
+def test_replay_reproduces_schedule_bitwise(orc):
+    g = gen.grid(30, 20, "uniform", seed=5)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=8)
+    r1 = h.solve(seed=3)
+    r2 = h.solve(seed=3, replay=r1.counts)
+    assert r2.counts == r1.counts
+    assert np.array_equal(r1.x, r2.x) and r1.lam == r2.lam
