@@ -1,0 +1,247 @@
+/*
+ * fiedler.h -- C ABI of the MI355X (gfx950) Fiedler-vector library: the
+ * Gauss-Seidel cascadic multigrid method (GS-CMG) of S. Gandhi, "Improvement of
+ * the Cascadic Multigrid Algorithm with a Gauss Seidel Smoother to Efficiently
+ * Compute the Fiedler Vector of a Graph Laplacian", arXiv 1602.04386 (2015).
+ *
+ * Problem (Section 3, Definitions 2.1 and 2.2, and the text before Algorithm
+ * 3): given the Laplacian L of a weighted undirected graph -- L_ii the weighted
+ * degree, L_ij = -w_ij -- return the eigenvector phi_2 of the second smallest
+ * eigenvalue lambda_2 (the algebraic connectivity) and lambda_2 itself, taken
+ * as the finest-level Rayleigh quotient.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns fv_status (or void for destructors); no C++
+ *    exception crosses this boundary.
+ *  - Sizes are int32 / int64 as declared; CSR indices are int32 with
+ *    0 <= nnz <= INT32_MAX.
+ *  - The caller owns every array it passes.  Inputs are copied (or only read
+ *    during the call); nothing the caller passes is retained after return,
+ *    except where fv_submit says otherwise.
+ *  - A context is not thread-safe; use one per thread.  Server entry points
+ *    (fv_submit, fv_poll) are thread-safe.
+ *  - Work runs on the context's HIP stream (or the stream in fv_solve_opts);
+ *    entry points return after the results are in the caller's buffers.
+ */
+#ifndef FIEDLER_H
+#define FIEDLER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FV_OK = 0,
+  FV_PENDING = 1,            /* fv_poll: request not finished yet */
+  FV_E_INVALID = -1,         /* null pointer, n < 2, row_ptr not starting at 0 / not
+                                non-decreasing / not ending at nnz, column out of range,
+                                columns not strictly ascending in a row, bad option */
+  FV_E_NOT_SYMMETRIC = -2,   /* entry (i,j) without a bitwise-equal entry (j,i) */
+  FV_E_NOT_LAPLACIAN = -3,   /* non-finite value; off-diagonal weight not > 0; L input:
+                                diagonal missing or |L_ii - sum_j w_ij| > 1e-12 max(1,|L_ii|);
+                                adjacency input: a diagonal entry present */
+  FV_E_ISOLATED = -4,        /* a vertex without edges: lambda_2 = 0, phi_2 not unique */
+  FV_E_NOMEM = -5,           /* device allocation failed */
+  FV_E_BUDGET = -6,          /* the request does not fit the HBM budget */
+  FV_E_NOT_CONVERGED = -7,   /* tol_res not met, or the coarsest solve hit its cap;
+                                x, lambda and stats are still filled */
+  FV_E_DEVICE = -8,          /* HIP runtime error */
+  FV_E_UNKNOWN_TICKET = -9,  /* fv_poll: ticket never issued or already collected */
+  FV_E_BUSY = -10            /* server queue full */
+} fv_status;
+
+typedef enum {
+  FV_PREC_FP64 = 0,       /* every vector and weight in FP64 */
+  FV_PREC_FP32_MIXED = 1  /* vectors and weights stored in FP32 for smoothing,
+                             power iteration and prolongation (half the bytes);
+                             reductions, shifts, projection, normalisation, the
+                             coarsest solve and the final Rayleigh quotient and
+                             residual (with FP64 weights) stay FP64 */
+} fv_precision;
+
+#define FV_MAX_LEVELS 64
+#define FV_SCHEDULE_CAP 1024
+
+typedef struct fv_context fv_context;
+typedef struct fv_hierarchy fv_hierarchy;
+typedef struct fv_server fv_server;
+
+/* A graph in CSR form.  is_adjacency = 0: the Laplacian L of Definition 2.1
+ * (diagonal present).  is_adjacency = 1: the weights W (no diagonal).  Columns
+ * must be strictly ascending inside each row and the matrix bitwise symmetric.
+ * on_device = 1: the three arrays are device pointers (for example torch
+ * tensors on the same GPU); 0: host pointers.  val is FP64. */
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* row_ptr; /* n + 1 */
+  const int32_t* col;     /* nnz */
+  const double* val;      /* nnz */
+  int32_t is_adjacency;
+  int32_t on_device;
+} fv_csr;
+
+/* Setup options (Algorithm 3, Step 1).  Coarsen while a level has more than
+ * n_coarse vertices (the text asks for about 25), for at most max_levels
+ * levels.  colour_seed seeds the smoother's colouring. */
+typedef struct {
+  int32_t n_coarse;     /* default 25 */
+  int32_t max_levels;   /* default and maximum FV_MAX_LEVELS */
+  uint64_t colour_seed; /* default 0 */
+} fv_hier_opts;
+
+/* Solve options (Algorithm 3, Steps 2 and 3; stopping rule of Section 4). */
+typedef struct {
+  int32_t prec;          /* fv_precision */
+  uint64_t seed;         /* SplitMix64 seed of the coarsest random start */
+  double tol_cos;        /* a phase ends when (x_k, x_{k-1}) > 1 - tol_cos; Section 4
+                            uses 1e-6 */
+  double tol_res;        /* > 0: repeat the finest-level phases until
+                            ||L x - lambda x|| / ||x|| <= tol_res; 0 = off */
+  double omega;          /* relaxation of the smoothing sweep; 1 = Gauss-Seidel */
+  int32_t max_gs;        /* sweeps per smoothing phase */
+  int32_t max_pi;        /* steps per power-iteration phase */
+  int32_t max_outer;     /* finest-level repeats for tol_res */
+  int32_t max_coarsest;  /* coarsest power-iteration steps */
+  const int32_t* replay; /* NULL, or a host array with the exact phase counts to run
+                            (layout of fv_solve_stats.schedule); for reproducing a
+                            schedule step for step */
+  int32_t replay_len;
+  void* stream;          /* hipStream_t to run on, or NULL for the context's stream */
+} fv_solve_opts;
+
+/* Per-solve statistics.  schedule = [coarsest steps, then (gs sweeps, pi steps)
+ * for levels J-1 down to 0, then (gs, pi) per extra finest-level round]. */
+typedef struct {
+  int32_t levels;
+  int32_t n[FV_MAX_LEVELS];
+  int64_t nnz[FV_MAX_LEVELS];
+  int32_t colours[FV_MAX_LEVELS];
+  int32_t schedule_len;
+  int32_t schedule[FV_SCHEDULE_CAP];
+  double lambda;
+  double residual;   /* ||L x - lambda x|| / ||x|| with FP64 weights */
+  double final_cos;
+  double t_solve_ms; /* device time of the solve (HIP events) */
+  int64_t alg_bytes; /* algorithmic HBM bytes of the refinement passes */
+} fv_solve_stats;
+
+/* Fills opts with the defaults named above (FP64, seed 1, tol_cos 1e-6, no
+ * tol_res, omega 1, 100 sweeps, 100 steps, 50 rounds, 100000 coarsest steps). */
+void fv_hier_opts_default(fv_hier_opts* opts);
+void fv_solve_opts_default(fv_solve_opts* opts);
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory that hierarchies and solves of this context may hold (0 = no bound).
+ * Errors: FV_E_INVALID (bad device, null out), FV_E_DEVICE. */
+fv_status fv_context_create(int device, size_t hbm_budget_bytes, fv_context** out);
+/* Every hierarchy and server made with ctx must be freed before this call. */
+void fv_context_destroy(fv_context* ctx);
+
+/* Setup phase (Algorithm 3, Step 1; Algorithm 1).  Validates the input
+ * (errors as listed in fv_status), copies it to the device and builds the level
+ * hierarchy there: heavy-edge matching under a strict total edge order
+ * (weight, then a pair hash, then the indices), attachment of unmatched
+ * vertices to their heaviest neighbour's aggregate, aggregates numbered by
+ * smallest member, Galerkin coarse graphs I L I^T summed in a fixed order, a
+ * first-fit colouring per level for the multicolour smoother, and the shift
+ * 2 max_i d_i per level.  The hierarchy is device-resident until
+ * fv_free_hierarchy.  Errors: input errors, FV_E_NOMEM, FV_E_BUDGET,
+ * FV_E_DEVICE. */
+fv_status fv_build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opts* opts,
+                             fv_hierarchy** out);
+
+/* Level count and per-level sizes (arrays of FV_MAX_LEVELS entries, any may be
+ * NULL): vertices, stored off-diagonal entries, colours, shift sigma. */
+fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz,
+                            int32_t* colours, double* sigma);
+
+/* Copies level `level` to host buffers in the canonical numbering (vertices of
+ * a coarse level numbered by their aggregate's smallest member): row_ptr[n+1],
+ * col[nnz], w[nnz] (off-diagonal weights), q[n] (aggregate of each vertex in
+ * the next level) and colour[n]; q and colour are left untouched on the
+ * coarsest level.  Any pointer may be NULL. */
+fv_status fv_hierarchy_export_level(const fv_hierarchy* h, int32_t level, int32_t* row_ptr,
+                                    int32_t* col, double* w, int32_t* q, int32_t* colour);
+
+void fv_free_hierarchy(fv_hierarchy* h);
+
+/* Coarsest solve and cascadic refinement (Algorithm 3, Steps 2-3), then the
+ * finest Rayleigh quotient.  Per level, coarse to fine: prolongation
+ * x = I^T y (Step 3), a smoothing phase of multicolour Gauss-Seidel sweeps on
+ * (L - rho I) x = 0 with rho the Rayleigh quotient of the current iterate
+ * (Algorithm 2), then a power-iteration phase on sigma I - L; after every sweep
+ * or step the iterate is projected against the all-ones vector and normalised
+ * and the phase ends on the cosine test or its cap.  x_out (n doubles; device
+ * pointer when x_on_device) receives phi_2, unit length, orthogonal to ones,
+ * signed so that its first entry with |x_i| >= 1e-3 max|x| is positive.
+ * lambda_out and stats may be NULL.  Errors: FV_E_INVALID, FV_E_NOMEM,
+ * FV_E_BUDGET, FV_E_NOT_CONVERGED (results still written), FV_E_DEVICE. */
+fv_status fv_fiedler_solve(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* opts,
+                           double* x_out, int32_t x_on_device, double* lambda_out,
+                           fv_solve_stats* stats);
+
+/* The same solve for `count` hierarchies in one persistent launch: one
+ * workgroup owns one graph at a time and takes the next from a
+ * largest-first queue.  x_out[k], lambda_out[k], stats[k] and item_status[k]
+ * belong to h[k]; lambda_out, stats and item_status may be NULL.  opts applies
+ * to every item (replay must be NULL).  Returns FV_OK when the launch ran; each
+ * item's own status is in item_status. */
+fv_status fv_fiedler_solve_batch(fv_context* ctx, int32_t count, const fv_hierarchy* const* h,
+                                 const fv_solve_opts* opts, double* const* x_out,
+                                 int32_t x_on_device, double* lambda_out, fv_solve_stats* stats,
+                                 fv_status* item_status);
+
+/* ---- Serving: continuous batching of Fiedler requests over one GPU ---- */
+
+typedef struct {
+  int32_t max_inflight;      /* requests on the device at once (slots) */
+  int32_t queue_capacity;    /* pending requests before FV_E_BUSY */
+  size_t hbm_budget_bytes;   /* device bytes for resident hierarchies plus in-flight work */
+  int32_t cache_hierarchies; /* 1: keep hierarchies resident by graph_id (LRU) */
+  fv_hier_opts hier;
+  fv_solve_opts solve;       /* replay and stream must be NULL */
+} fv_server_opts;
+
+typedef struct {
+  uint64_t graph_id;   /* cache key; used when the server caches hierarchies */
+  const fv_csr* graph; /* read during fv_submit only when the graph is not cached;
+                          the arrays must stay valid until fv_poll returns a final
+                          status */
+  double* x_out;       /* host buffer of n doubles; must stay valid until fv_poll
+                          returns a final status */
+} fv_request;
+
+typedef struct {
+  fv_status status;
+  double lambda;
+  double residual;
+  double queue_ms;   /* submit -> start of device work */
+  double latency_ms; /* submit -> completion */
+  int32_t cache_hit;
+} fv_result;
+
+fv_status fv_server_create(fv_context* ctx, const fv_server_opts* opts, fv_server** out);
+
+/* Queues a request and returns its ticket.  Errors: FV_E_INVALID, FV_E_BUSY
+ * (queue full), FV_E_BUDGET (the graph alone exceeds the budget). */
+fv_status fv_submit(fv_server* s, const fv_request* req, uint64_t* ticket);
+
+/* FV_PENDING while the request runs; otherwise fills *out and returns FV_OK,
+ * after which the ticket is forgotten.  FV_E_UNKNOWN_TICKET for an unknown or
+ * already collected ticket. */
+fv_status fv_poll(fv_server* s, uint64_t ticket, fv_result* out);
+
+/* Drains in-flight work, then frees the server and its cached hierarchies. */
+void fv_server_destroy(fv_server* s);
+
+const char* fv_status_str(fv_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIEDLER_H */

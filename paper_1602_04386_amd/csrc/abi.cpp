@@ -1,0 +1,243 @@
+// C entry points of include/fiedler.h: argument checks, exception-to-status
+// mapping, contexts and device-memory accounting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "fv_internal.h"
+
+namespace fv {
+
+void budget_reserve(fv_context* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+    throw Error(FV_E_BUDGET, "HBM budget exceeded");
+  ctx->in_use += bytes;
+}
+
+void budget_release(fv_context* ctx, size_t bytes) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->in_use -= std::min(ctx->in_use, bytes);
+}
+
+void* dev_alloc(fv_context* ctx, size_t bytes, size_t* counter) {
+  budget_reserve(ctx, bytes);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    budget_release(ctx, bytes);
+    throw Error(FV_E_NOMEM, "device allocation failed");
+  }
+  if (counter) *counter += bytes;
+  return p;
+}
+
+void dev_free(fv_context* ctx, void* p, size_t bytes, size_t* counter) {
+  if (!p) return;
+  (void)hipFree(p);
+  budget_release(ctx, bytes);
+  if (counter) *counter -= std::min(*counter, bytes);
+}
+
+}  // namespace fv
+
+using fv::Error;
+
+#define FV_GUARD(body)                                  \
+  try {                                                 \
+    body                                                \
+  } catch (const Error& e) {                            \
+    return e.st;                                        \
+  } catch (const std::bad_alloc&) {                     \
+    return FV_E_NOMEM;                                  \
+  } catch (...) {                                       \
+    return FV_E_DEVICE;                                 \
+  }
+
+extern "C" {
+
+void fv_hier_opts_default(fv_hier_opts* o) {
+  if (!o) return;
+  o->n_coarse = 25;
+  o->max_levels = FV_MAX_LEVELS;
+  o->colour_seed = 0;
+}
+
+void fv_solve_opts_default(fv_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->prec = FV_PREC_FP64;
+  o->seed = 1;
+  o->tol_cos = 1e-6;
+  o->tol_res = 0.0;
+  o->omega = 1.0;
+  o->max_gs = 100;
+  o->max_pi = 100;
+  o->max_outer = 50;
+  o->max_coarsest = 100000;
+  o->replay = nullptr;
+  o->replay_len = 0;
+  o->stream = nullptr;
+}
+
+const char* fv_status_str(fv_status st) {
+  switch (st) {
+    case FV_OK: return "ok";
+    case FV_PENDING: return "pending";
+    case FV_E_INVALID: return "invalid argument or CSR structure";
+    case FV_E_NOT_SYMMETRIC: return "matrix not symmetric";
+    case FV_E_NOT_LAPLACIAN: return "not a graph Laplacian / adjacency";
+    case FV_E_ISOLATED: return "isolated vertex";
+    case FV_E_NOMEM: return "out of device memory";
+    case FV_E_BUDGET: return "HBM budget exceeded";
+    case FV_E_NOT_CONVERGED: return "not converged";
+    case FV_E_DEVICE: return "device error";
+    case FV_E_UNKNOWN_TICKET: return "unknown ticket";
+    case FV_E_BUSY: return "server queue full";
+  }
+  return "unknown status";
+}
+
+fv_status fv_context_create(int device, size_t hbm_budget_bytes, fv_context** out) {
+  if (!out) return FV_E_INVALID;
+  *out = nullptr;
+  FV_GUARD({
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+      return FV_E_INVALID;
+    FV_HIP(hipSetDevice(device));
+    fv_context* c = new fv_context();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return FV_E_DEVICE;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 256, hipHostMallocDefault) !=
+        hipSuccess) {
+      (void)hipStreamDestroy(c->stream);
+      delete c;
+      return FV_E_DEVICE;
+    }
+    *out = c;
+    return FV_OK;
+  })
+}
+
+void fv_context_destroy(fv_context* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+fv_status fv_build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opts* opts,
+                             fv_hierarchy** out) {
+  if (!ctx || !L || !out) return FV_E_INVALID;
+  *out = nullptr;
+  FV_GUARD({
+    FV_HIP(hipSetDevice(ctx->device));
+    fv_hier_opts o;
+    fv_hier_opts_default(&o);
+    if (opts) o = *opts;
+    *out = fv::build_hierarchy(ctx, L, &o, ctx->stream);
+    return FV_OK;
+  })
+}
+
+fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz,
+                            int32_t* colours, double* sigma) {
+  if (!h) return FV_E_INVALID;
+  if (levels) *levels = h->levels;
+  for (int l = 0; l < h->levels; ++l) {
+    if (n) n[l] = h->lv[l].n;
+    if (nnz) nnz[l] = h->lv[l].m;
+    if (colours) colours[l] = l == h->levels - 1 ? 0 : h->lv[l].ncol;
+    if (sigma) sigma[l] = h->lv[l].sigma;
+  }
+  return FV_OK;
+}
+
+fv_status fv_hierarchy_export_level(const fv_hierarchy* h, int32_t level, int32_t* row_ptr,
+                                    int32_t* col, double* w, int32_t* q, int32_t* colour) {
+  if (!h || level < 0 || level >= h->levels) return FV_E_INVALID;
+  FV_GUARD({
+    const fv::Level& L = h->lv[level];
+    hipStream_t s = h->ctx->stream;
+    FV_HIP(hipSetDevice(h->ctx->device));
+    if (row_ptr)
+      FV_HIP(hipMemcpyAsync(row_ptr, L.rp_c, sizeof(int) * (L.n + 1), hipMemcpyDeviceToHost, s));
+    if (col && L.m)
+      FV_HIP(hipMemcpyAsync(col, L.col_c, sizeof(int) * L.m, hipMemcpyDeviceToHost, s));
+    if (w && L.m)
+      FV_HIP(hipMemcpyAsync(w, L.w_c, sizeof(double) * L.m, hipMemcpyDeviceToHost, s));
+    if (q && L.q_c)
+      FV_HIP(hipMemcpyAsync(q, L.q_c, sizeof(int) * L.n, hipMemcpyDeviceToHost, s));
+    if (colour && L.colour_c)
+      FV_HIP(hipMemcpyAsync(colour, L.colour_c, sizeof(int) * L.n, hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    return FV_OK;
+  })
+}
+
+void fv_free_hierarchy(fv_hierarchy* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->ctx->device);
+  (void)hipStreamSynchronize(h->ctx->stream);
+  fv::free_hierarchy(h);
+}
+
+static fv_status check_solve_opts(const fv_solve_opts* o) {
+  if (o->prec != FV_PREC_FP64 && o->prec != FV_PREC_FP32_MIXED) return FV_E_INVALID;
+  if (!(o->tol_cos >= 0.0) || !(o->tol_res >= 0.0)) return FV_E_INVALID;
+  if (!(o->omega > 0.0 && o->omega < 2.0)) return FV_E_INVALID;
+  if (o->max_gs < 0 || o->max_pi < 0 || o->max_outer < 0 || o->max_coarsest < 0)
+    return FV_E_INVALID;
+  if (o->replay && (o->replay_len < 0 || o->replay_len > FV_SCHEDULE_CAP)) return FV_E_INVALID;
+  for (int k = 0; o->replay && k < o->replay_len; ++k)
+    if (o->replay[k] < 0) return FV_E_INVALID;
+  return FV_OK;
+}
+
+fv_status fv_fiedler_solve(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* opts,
+                           double* x_out, int32_t x_on_device, double* lambda_out,
+                           fv_solve_stats* stats) {
+  if (!ctx || !h || !x_out || h->ctx != ctx) return FV_E_INVALID;
+  fv_solve_opts o;
+  fv_solve_opts_default(&o);
+  if (opts) o = *opts;
+  fv_status st = check_solve_opts(&o);
+  if (st != FV_OK) return st;
+  FV_GUARD({
+    FV_HIP(hipSetDevice(ctx->device));
+    return fv::solve_one(ctx, h, &o, x_out, x_on_device, lambda_out, stats);
+  })
+}
+
+fv_status fv_fiedler_solve_batch(fv_context* ctx, int32_t count, const fv_hierarchy* const* h,
+                                 const fv_solve_opts* opts, double* const* x_out,
+                                 int32_t x_on_device, double* lambda_out, fv_solve_stats* stats,
+                                 fv_status* item_status) {
+  if (!ctx || count < 0 || (count > 0 && (!h || !x_out))) return FV_E_INVALID;
+  for (int k = 0; k < count; ++k)
+    if (!h[k] || !x_out[k] || h[k]->ctx != ctx) return FV_E_INVALID;
+  fv_solve_opts o;
+  fv_solve_opts_default(&o);
+  if (opts) o = *opts;
+  fv_status st = check_solve_opts(&o);
+  if (st != FV_OK) return st;
+  if (o.replay) return FV_E_INVALID;
+  FV_GUARD({
+    FV_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = o.stream ? static_cast<hipStream_t>(o.stream) : ctx->stream;
+    return fv::solve_batch(ctx, count, h, &o, x_out, x_on_device, lambda_out, stats,
+                           item_status, s);
+  })
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Device helpers: hashes, SplitMix64, deterministic wave/block reductions and
+// the strict edge order of the heavy-edge matching.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fv_internal.h"
+
+namespace fv {
+
+// MurmurHash3 32-bit finaliser (Appleby, public domain).
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6BU;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35U;
+  h ^= h >> 16;
+  return h;
+}
+
+// Tie-break hash of an undirected vertex pair a < b.
+__host__ __device__ inline uint32_t pair_hash(int a, int b) {
+  return fmix32(fmix32((uint32_t)a) ^ (uint32_t)b);
+}
+
+// Colouring seed of level `level` and a vertex's colouring priority.
+__host__ __device__ inline uint32_t level_seed(unsigned long long colour_seed, int level) {
+  uint32_t lo = (uint32_t)colour_seed, hi = (uint32_t)(colour_seed >> 32);
+  return fmix32(lo ^ fmix32(hi + (uint32_t)level));
+}
+__host__ __device__ inline uint32_t colour_priority(int v, uint32_t seed) {
+  return fmix32((uint32_t)v ^ seed);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014), counter form: draw k >= 1 of the
+// stream seeded s is mix(s + k * 0x9E3779B97F4A7C15).
+__device__ inline double splitmix_uniform(unsigned long long seed, unsigned long long k) {
+  unsigned long long z = seed + k * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Strict total order on undirected edges: heavier first, then smaller pair
+// hash, then smaller first endpoint, then smaller second endpoint.
+__device__ inline bool edge_before(double w1, int u1, int v1, double w2, int u2, int v2) {
+  if (w1 != w2) return w1 > w2;
+  int a1 = u1 < v1 ? u1 : v1, b1 = u1 < v1 ? v1 : u1;
+  int a2 = u2 < v2 ? u2 : v2, b2 = u2 < v2 ? v2 : u2;
+  uint32_t h1 = pair_hash(a1, b1), h2 = pair_hash(a2, b2);
+  if (h1 != h2) return h1 < h2;
+  if (a1 != a2) return a1 < a2;
+  return b1 < b2;
+}
+
+// XCD-aware block order: workgroups are dealt to the 8 dies round-robin, so
+// logical block k of die d is the d-th contiguous chunk; neighbouring rows then
+// share one die's L2.
+__device__ inline int xcd_block(int b, int nb) {
+  int d = b % kXCD, k = b / kXCD;
+  int per = nb / kXCD, rem = nb % kXCD;
+  return d * per + (d < rem ? d : rem) + k;
+}
+
+// ---- deterministic reductions (fixed order; lane 0 / wave order) ----
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of NP values over the block; every thread receives the same totals.
+// lds must hold (blockDim/64) * NP doubles.
+template <int NP>
+__device__ inline void block_sum(double (&v)[NP], double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) lds[wid * NP + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += lds[w * NP + k];
+    v[k] = t;
+  }
+  __syncthreads();
+}
+
+__device__ inline long long block_sum_ll(long long v, long long* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum_ll(v);
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  long long t = 0;
+  for (int w = 0; w < nw; ++w) t += lds[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ inline double block_max(double v, double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double t = lds[0];
+  for (int w = 1; w < nw; ++w) t = fmax(t, lds[w]);
+  __syncthreads();
+  return t;
+}
+
+__device__ inline int block_min_int(int v, int* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  int t = lds[0];
+  for (int w = 1; w < nw; ++w) t = min(t, lds[w]);
+  __syncthreads();
+  return t;
+}
+
+// Inclusive scan over a wave of 64 lanes.
+__device__ inline int wave_inclusive_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// Last-block-done protocol: every block has written its partials; the block
+// that arrives last (agent-scope fences on both sides) returns true.
+__device__ inline bool arrive_last(unsigned* counter, unsigned nblocks, int* lds_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned old = atomicAdd(counter, 1u);
+    *lds_flag = (old == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  bool last = *lds_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+}  // namespace fv

@@ -1,0 +1,190 @@
+// Internal declarations shared by the library's translation units (host and
+// device).  Not part of the public ABI (include/fiedler.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fiedler.h"
+
+namespace fv {
+
+// ---------------------------------------------------------------------------
+// Errors: HIP failures and status-carrying errors are C++ exceptions inside
+// the library and become fv_status at the C boundary.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  fv_status st;
+  Error(fv_status s, const std::string& what) : std::runtime_error(what), st(s) {}
+};
+
+#define FV_HIP(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      throw ::fv::Error(e_ == hipErrorOutOfMemory ? FV_E_NOMEM : FV_E_DEVICE,        \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Launch geometry.
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;    // threads per block of the multi-workgroup row passes
+constexpr int kWG = 512;       // threads of the one-workgroup-per-graph engine
+constexpr int kNP = 5;         // FP64 partial sums carried by a refinement pass
+constexpr int kXCD = 8;        // accelerator complex dies on MI355X
+
+// Levels with at most this many vertices are refined by the one-workgroup
+// engine; larger levels by multi-workgroup passes.
+constexpr int kSmallLevel = 16384;
+
+// ---------------------------------------------------------------------------
+// Device-resident solve state of one graph (scalars of the current phase).
+// ---------------------------------------------------------------------------
+struct DevState {
+  double mu;      // pending normalisation of the stored vector: xhat = (x - mu) * inv_s
+  double inv_s;
+  double rho;     // shift of the next smoothing sweep
+  double cos;     // cosine of the last step
+  double tol;     // 1 - tol_cos threshold is (1 - tol)
+  double lambda;  // finest Rayleigh quotient
+  double res;     // finest residual
+  double sumsq;   // sum of xhat^2 in the Rayleigh pass
+  double xmax;    // max |xhat|
+  double sign;    // output sign
+  int done;       // current phase finished
+  int iters;      // steps executed in the current phase
+  int cap;        // step limit of the current phase
+  int forced;     // 1: run exactly cap steps
+  int cur;        // which ping-pong buffer holds the iterate
+  unsigned counter;  // last-block-done counter
+  int sign_idx;   // first (canonical) index with |x_i| >= 1e-3 max|x|
+  int err;
+};
+
+// Per-level descriptor as the kernels see it (solve order: rows of one colour
+// contiguous, ascending original index inside a colour).
+struct LevelDesc {
+  int n;
+  int ncol;
+  long long m;
+  const int* rp;
+  const int* col;
+  const double* w64;
+  const float* w32;
+  const int* cptr;   // colour row ranges, ncol + 1 entries
+  const int* qs;     // aggregate (solve order of the next level) of each row; null on coarsest
+  const int* perm;   // original index -> solve position
+  const int* iperm;  // solve position -> original index
+  double sigma;
+};
+
+// One graph's work for the one-workgroup engine.
+struct GraphTask {
+  const LevelDesc* lv;  // device array, levels 0..J
+  int J;                // coarsest level
+  int stop;             // finest level refined by the engine
+  int prec;             // fv_precision
+  int finalize;         // 1: stop == 0 and the engine also does the Rayleigh quotient,
+                        //    finest repeats and the output
+  void* xa;             // two vector buffers of nmax entries (8-byte capacity each)
+  void* xb;
+  double* lx;           // FP64 scratch of nmax entries
+  double* x_out;        // canonical FP64 output (finalize), device pointer
+  DevState* st;         // where the engine leaves its scalars
+  const int* replay;    // device array or null
+  int replay_len;
+  int* sched;           // device schedule output, FV_SCHEDULE_CAP entries
+  int* sched_len;
+  int out_buf;          // 0: iterate ends in xa, 1: in xb (written by the engine)
+  unsigned long long seed;
+  double tol_cos, tol_res, omega;
+  int max_gs, max_pi, max_outer, max_coarsest;
+  long long work;       // ordering key (bigger first)
+};
+
+// ---------------------------------------------------------------------------
+// Host-side level storage.
+// ---------------------------------------------------------------------------
+struct Level {
+  int n = 0;
+  long long m = 0;
+  int ncol = 0;
+  double sigma = 0.0;
+  // canonical numbering
+  int* rp_c = nullptr;
+  int* col_c = nullptr;
+  double* w_c = nullptr;
+  int* q_c = nullptr;
+  int* colour_c = nullptr;
+  // solve order
+  int* rp = nullptr;
+  int* col = nullptr;
+  double* w64 = nullptr;
+  float* w32 = nullptr;
+  int* cptr = nullptr;
+  std::vector<int> cptr_h;
+  int* perm = nullptr;
+  int* iperm = nullptr;
+  int* qs = nullptr;
+};
+
+}  // namespace fv
+
+// Opaque handles of the public ABI.
+struct fv_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;   // 0 = unbounded
+  size_t in_use = 0;   // bytes held by live hierarchies and workspaces
+  std::mutex mu;       // guards in_use (the server's threads share the context)
+  // reusable single-solve workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* pinned = nullptr;  // small pinned host buffer for flag readback
+};
+
+struct fv_hierarchy {
+  fv_context* ctx = nullptr;
+  int levels = 0;
+  fv::Level lv[FV_MAX_LEVELS];
+  fv::LevelDesc* d_desc = nullptr;  // device copy of the level descriptors
+  size_t bytes = 0;
+};
+
+namespace fv {
+
+// Device allocation accounted against the context budget.
+void* dev_alloc(fv_context* ctx, size_t bytes, size_t* counter);
+void dev_free(fv_context* ctx, void* p, size_t bytes, size_t* counter);
+void budget_reserve(fv_context* ctx, size_t bytes);
+void budget_release(fv_context* ctx, size_t bytes);
+
+// Setup (setup.hip).
+fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opts* o,
+                              hipStream_t s);
+void free_hierarchy(fv_hierarchy* h);
+size_t hierarchy_nmax(const fv_hierarchy* h);
+
+// Solve (solve.hip).
+fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
+                    double* x_out, int x_on_device, double* lambda_out, fv_solve_stats* stats);
+fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* h,
+                      const fv_solve_opts* o, double* const* x_out, int x_on_device,
+                      double* lambda_out, fv_solve_stats* stats, fv_status* item_status,
+                      hipStream_t s);
+size_t solve_workspace_bytes(size_t nmax, int maxcol);
+
+// Algorithmic bytes of one refinement pass over a level.
+inline long long pass_bytes(int n, long long m, int prec) {
+  return prec == FV_PREC_FP32_MIXED ? 8LL * m + 4LL * (n + 1) + 8LL * n
+                                    : 12LL * m + 4LL * (n + 1) + 16LL * n;
+}
+
+}  // namespace fv

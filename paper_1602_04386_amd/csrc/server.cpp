@@ -1,0 +1,306 @@
+// Serving: continuous batching of Fiedler requests on one GPU.
+//
+// Worker threads, each with its own HIP stream, take up to their share of the
+// in-flight slots from the request queue, build (or reuse from the cache) the
+// requests' hierarchies, and run them as one persistent batched launch.  A
+// request that arrives while others run on the device is admitted by the next
+// worker whose launch finishes, so launches from different workers overlap on
+// the device.  Device memory for hierarchies and launch workspaces comes out
+// of the context's HBM budget; cached hierarchies not in use are evicted
+// least-recently-used first when a reservation does not fit.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+#include "fv_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  fv_request req;
+  fv_csr graph;
+  bool has_graph = false;
+  int state = 0;  // 0 queued, 1 running, 2 done
+  fv_result res{};
+  Clock::time_point t_submit, t_start;
+};
+
+struct CacheEntry {
+  fv_hierarchy* h = nullptr;
+  int refs = 0;
+  uint64_t last_use = 0;
+  bool building = false;
+};
+
+}  // namespace
+
+struct fv_server {
+  fv_context* ctx = nullptr;
+  fv_server_opts opts{};
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Request> reqs;
+  std::unordered_map<uint64_t, CacheEntry> cache;
+  std::vector<std::thread> workers;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  uint64_t use_clock = 0;
+  int inflight = 0;
+};
+
+namespace {
+
+// Frees one unreferenced cached hierarchy (least recently used); returns false
+// when none can be freed.  Caller holds s->mu.
+bool evict_one(fv_server* s) {
+  auto victim = s->cache.end();
+  for (auto it = s->cache.begin(); it != s->cache.end(); ++it)
+    if (it->second.refs == 0 && !it->second.building && it->second.h &&
+        (victim == s->cache.end() || it->second.last_use < victim->second.last_use))
+      victim = it;
+  if (victim == s->cache.end()) return false;
+  fv::free_hierarchy(victim->second.h);
+  s->cache.erase(victim);
+  return true;
+}
+
+// Runs f(); on FV_E_BUDGET evicts cached hierarchies or waits for in-flight
+// work to release memory, then retries.  Gives up when nothing else holds
+// memory.
+template <class F>
+auto with_budget(fv_server* s, F f) -> decltype(f()) {
+  for (;;) {
+    try {
+      return f();
+    } catch (const fv::Error& e) {
+      if (e.st != FV_E_BUDGET) throw;
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (evict_one(s)) continue;
+      if (s->inflight <= 1) throw;  // only this work holds memory
+      s->cv.wait_for(lk, std::chrono::milliseconds(1));
+    }
+  }
+}
+
+void worker_main(fv_server* s, int share) {
+  (void)hipSetDevice(s->ctx->device);
+  hipStream_t stream = nullptr;
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
+  std::vector<uint64_t> batch;
+  for (;;) {
+    batch.clear();
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] {
+        return (!s->queue.empty() && s->inflight < s->opts.max_inflight) ||
+               (s->stop && s->queue.empty());
+      });
+      if (s->queue.empty()) break;
+      const int room = std::min(share, s->opts.max_inflight - s->inflight);
+      while ((int)batch.size() < room && !s->queue.empty()) {
+        uint64_t t = s->queue.front();
+        s->queue.pop_front();
+        Request& r = s->reqs[t];
+        r.state = 1;
+        r.t_start = Clock::now();
+        batch.push_back(t);
+      }
+      s->inflight += (int)batch.size();
+    }
+    // Hierarchies: cache hit, or build on this worker's stream.
+    std::vector<fv_hierarchy*> hs(batch.size(), nullptr);
+    std::vector<fv_status> st(batch.size(), FV_OK);
+    std::vector<int> owned(batch.size(), 0);
+    for (size_t k = 0; k < batch.size(); ++k) {
+      Request* r;
+      uint64_t gid;
+      {
+        std::unique_lock<std::mutex> lk(s->mu);
+        r = &s->reqs[batch[k]];
+        gid = r->req.graph_id;
+        if (s->opts.cache_hierarchies) {
+          for (;;) {
+            auto it = s->cache.find(gid);
+            if (it == s->cache.end()) {
+              CacheEntry ce;
+              ce.building = true;
+              s->cache[gid] = ce;
+              break;
+            }
+            if (!it->second.building) {
+              it->second.refs++;
+              it->second.last_use = ++s->use_clock;
+              hs[k] = it->second.h;
+              r->res.cache_hit = 1;
+              break;
+            }
+            s->cv.wait_for(lk, std::chrono::milliseconds(1));
+          }
+        }
+      }
+      if (hs[k]) continue;
+      if (!r->has_graph) {
+        st[k] = FV_E_INVALID;
+      } else {
+        try {
+          hs[k] = with_budget(s, [&] {
+            return fv::build_hierarchy(s->ctx, &r->graph, &s->opts.hier, stream);
+          });
+        } catch (const fv::Error& e) {
+          st[k] = e.st;
+        } catch (...) {
+          st[k] = FV_E_DEVICE;
+        }
+      }
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->opts.cache_hierarchies) {
+        CacheEntry& ce = s->cache[gid];
+        ce.building = false;
+        if (hs[k]) {
+          ce.h = hs[k];
+          ce.refs = 1;
+          ce.last_use = ++s->use_clock;
+        } else {
+          s->cache.erase(gid);
+        }
+        s->cv.notify_all();
+      } else {
+        owned[k] = hs[k] ? 1 : 0;
+      }
+    }
+    // One batched launch for the admitted requests that have a hierarchy.
+    std::vector<const fv_hierarchy*> run_h;
+    std::vector<double*> run_x;
+    std::vector<size_t> run_k;
+    for (size_t k = 0; k < batch.size(); ++k)
+      if (hs[k] && st[k] == FV_OK) {
+        run_h.push_back(hs[k]);
+        std::lock_guard<std::mutex> g(s->mu);
+        run_x.push_back(s->reqs[batch[k]].req.x_out);
+        run_k.push_back(k);
+      }
+    std::vector<double> lam(run_h.size(), 0.0);
+    std::vector<fv_solve_stats> stats(run_h.size());
+    std::vector<fv_status> ist(run_h.size(), FV_OK);
+    if (!run_h.empty()) {
+      try {
+        with_budget(s, [&] {
+          return fv::solve_batch(s->ctx, (int)run_h.size(), run_h.data(), &s->opts.solve,
+                                 run_x.data(), 0, lam.data(), stats.data(), ist.data(), stream);
+        });
+      } catch (const fv::Error& e) {
+        for (auto& v : ist) v = e.st;
+      } catch (...) {
+        for (auto& v : ist) v = FV_E_DEVICE;
+      }
+    }
+    for (size_t j = 0; j < run_k.size(); ++j) st[run_k[j]] = ist[j];
+    const auto t_done = Clock::now();
+    std::lock_guard<std::mutex> g(s->mu);
+    for (size_t j = 0; j < run_k.size(); ++j) {
+      Request& r = s->reqs[batch[run_k[j]]];
+      r.res.lambda = lam[j];
+      r.res.residual = stats[j].residual;
+    }
+    for (size_t k = 0; k < batch.size(); ++k) {
+      Request& r = s->reqs[batch[k]];
+      r.res.status = st[k];
+      r.res.queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
+      r.res.latency_ms = std::chrono::duration<double, std::milli>(t_done - r.t_submit).count();
+      r.state = 2;
+      if (s->opts.cache_hierarchies) {
+        auto it = s->cache.find(r.req.graph_id);
+        if (it != s->cache.end() && hs[k] == it->second.h) it->second.refs--;
+      } else if (owned[k]) {
+        fv::free_hierarchy(hs[k]);
+      }
+    }
+    s->inflight -= (int)batch.size();
+    s->cv.notify_all();
+  }
+  (void)hipStreamDestroy(stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+fv_status fv_server_create(fv_context* ctx, const fv_server_opts* opts, fv_server** out) {
+  if (!ctx || !opts || !out) return FV_E_INVALID;
+  *out = nullptr;
+  if (opts->max_inflight < 1 || opts->queue_capacity < 1) return FV_E_INVALID;
+  if (opts->solve.replay || opts->solve.stream) return FV_E_INVALID;
+  try {
+    fv_server* s = new fv_server();
+    s->ctx = ctx;
+    s->opts = *opts;
+    if (opts->hbm_budget_bytes) ctx->budget = opts->hbm_budget_bytes;
+    const int nworkers = std::max(1, std::min(4, opts->max_inflight));
+    const int share = std::max(1, opts->max_inflight / nworkers);
+    for (int w = 0; w < nworkers; ++w) s->workers.emplace_back(worker_main, s, share);
+    *out = s;
+    return FV_OK;
+  } catch (...) {
+    return FV_E_DEVICE;
+  }
+}
+
+fv_status fv_submit(fv_server* s, const fv_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket || !req->x_out) return FV_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  if ((int)s->queue.size() >= s->opts.queue_capacity) return FV_E_BUSY;
+  if (!req->graph && !(s->opts.cache_hierarchies && s->cache.count(req->graph_id)))
+    return FV_E_INVALID;
+  if (req->graph && s->ctx->budget) {
+    // A graph whose input alone exceeds the budget can never be admitted.
+    const size_t in_bytes = (size_t)req->graph->nnz * 12 + (size_t)(req->graph->n + 1) * 4;
+    if (in_bytes > s->ctx->budget) return FV_E_BUDGET;
+  }
+  Request r;
+  r.req = *req;
+  if (req->graph) {
+    r.graph = *req->graph;
+    r.has_graph = true;
+  }
+  r.t_submit = Clock::now();
+  const uint64_t t = s->next_ticket++;
+  s->reqs.emplace(t, r);
+  s->queue.push_back(t);
+  *ticket = t;
+  s->cv.notify_all();
+  return FV_OK;
+}
+
+fv_status fv_poll(fv_server* s, uint64_t ticket, fv_result* out) {
+  if (!s || !out) return FV_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return FV_E_UNKNOWN_TICKET;
+  if (it->second.state != 2) return FV_PENDING;
+  *out = it->second.res;
+  s->reqs.erase(it);
+  return FV_OK;
+}
+
+void fv_server_destroy(fv_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& t : s->workers) t.join();
+  (void)hipSetDevice(s->ctx->device);
+  for (auto& kv : s->cache)
+    if (kv.second.h) fv::free_hierarchy(kv.second.h);
+  delete s;
+}
+
+}  // extern "C"

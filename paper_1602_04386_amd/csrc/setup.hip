@@ -1,0 +1,875 @@
+// Setup phase on the device (Algorithm 3, Step 1; Algorithm 1): input
+// validation, heavy-edge matching, aggregation, Galerkin coarse graphs,
+// first-fit colouring for the multicolour smoother and the colour-ordered copy
+// of every level that the refinement kernels read.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "fv_device.h"
+#include "fv_internal.h"
+
+namespace fv {
+
+// ---------------------------------------------------------------------------
+// Temporary device buffers of one build (not counted against the budget).
+// ---------------------------------------------------------------------------
+struct Tmp {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* get(size_t count) {
+    void* p = nullptr;
+    FV_HIP(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~Tmp() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+static inline int nblk(long long n, int b = kBlock) { return (int)std::max<long long>(1, (n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of f(0..n-1) (int64 accumulation).
+// ---------------------------------------------------------------------------
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__device__ inline long long block_inclusive_scan_ll(long long v, long long* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    long long t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  if (lane == 63) lds[wid] = v;
+  __syncthreads();
+  long long pre = 0;
+  for (int w = 0; w < wid; ++w) pre += lds[w];
+  __syncthreads();
+  return v + pre;
+}
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(F f, int n, long long* bsum) {
+  __shared__ long long lds[kBlock / 64];
+  long long s = 0;
+  const int base = blockIdx.x * kScanTile;
+  for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+    int i = base + k;
+    if (i < n) s += f(i);
+  }
+  s = block_sum_ll(s, lds);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(long long* bsum, int nb) {
+  __shared__ long long lds[kBlock / 64];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += kBlock) {
+    int i = base + threadIdx.x;
+    long long v = i < nb ? bsum[i] : 0;
+    long long inc = block_inclusive_scan_ll(v, lds);
+    long long c = carry;
+    if (i < nb) bsum[i] = c + inc - v;
+    __syncthreads();
+    if (threadIdx.x == kBlock - 1) carry = c + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+template <class F, class OUT>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(F f, int n, const long long* boff, OUT* out) {
+  __shared__ long long lds[kBlock / 64];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  long long vals[kScanPer];
+  long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    int i = base + k;
+    vals[k] = i < n ? (long long)f(i) : 0;
+    s += vals[k];
+  }
+  long long inc = block_inclusive_scan_ll(s, lds);
+  long long run = boff[blockIdx.x] + inc - s;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    int i = base + k;
+    if (i < n) out[i] = (OUT)run;
+    run += vals[k];
+  }
+}
+
+__global__ void k_write_total(const long long* src, int* dst) { *dst = (int)*src; }
+
+struct Scanner {
+  long long* bsum = nullptr;
+  int cap = 0;
+  hipStream_t s = nullptr;
+  long long* host = nullptr;  // pinned
+  // Writes the exclusive scan of f over [0, n) to out (if non-null), and the
+  // total to out[n] when write_total; returns the total.
+  template <class F>
+  long long run(F f, int n, int* out, bool write_total) {
+    int nb = std::max(1, (n + kScanTile - 1) / kScanTile);
+    if (nb + 1 > cap) throw Error(FV_E_INVALID, "scan scratch too small");
+    k_scan_reduce<<<nb, kBlock, 0, s>>>(f, n, bsum);
+    k_scan_blocks<<<1, kBlock, 0, s>>>(bsum, nb);
+    if (out) {
+      k_scan_apply<<<nb, kBlock, 0, s>>>(f, n, bsum, out);
+      if (write_total) k_write_total<<<1, 1, 0, s>>>(bsum + nb, out + n);
+    }
+    FV_HIP(hipGetLastError());
+    FV_HIP(hipMemcpyAsync(host, bsum + nb, sizeof(long long), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    return *host;
+  }
+};
+
+struct FromArray {
+  const int* a;
+  __device__ int operator()(int i) const { return a[i]; }
+};
+struct FlagEq {
+  const int* a;
+  int c;
+  __device__ int operator()(int i) const { return a[i] == c ? 1 : 0; }
+};
+struct LeaderFlag {
+  const int* root;
+  const int* minmem;
+  __device__ int operator()(int v) const { return minmem[root[v]] == v ? 1 : 0; }
+};
+struct PermDeg {
+  const int* rp;
+  const int* iperm;
+  __device__ int operator()(int i) const {
+    int v = iperm[i];
+    return rp[v + 1] - rp[v];
+  }
+};
+struct BigRow {
+  const int* tstart;
+  __device__ int operator()(int i) const { return (tstart[i + 1] - tstart[i]) > 64 ? 1 : 0; }
+};
+
+// ---------------------------------------------------------------------------
+// Small utility kernels.
+// ---------------------------------------------------------------------------
+__global__ void k_fill_int(int* a, long long n, int v) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+__global__ void k_iota(int* a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+__global__ void k_f64_to_f32(const double* a, float* b, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Input validation (Definition 2.1) and extraction of the weights W.
+// flags: 1 structure, 2 values / Laplacian form, 4 symmetry, 8 isolated vertex.
+// ---------------------------------------------------------------------------
+__global__ void k_val_structure(int n, int nnz, const int* rp, const int* col, int* flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = rp[i], b = rp[i + 1];
+  if (i == 0 && a != 0) atomicOr(flags, 1);
+  if (i == n - 1 && b != nnz) atomicOr(flags, 1);
+  if (a < 0 || b < a || b > nnz) {
+    atomicOr(flags, 1);
+    return;
+  }
+  for (int p = a; p < b; ++p) {
+    int c = col[p];
+    if (c < 0 || c >= n || (p > a && c <= col[p - 1])) {
+      atomicOr(flags, 1);
+      return;
+    }
+  }
+}
+
+__device__ inline int find_col(const int* rp, const int* col, int i, int j) {
+  int lo = rp[i], hi = rp[i + 1] - 1;
+  while (lo <= hi) {
+    int mid = lo + ((hi - lo) >> 1);
+    int c = col[mid];
+    if (c == j) return mid;
+    if (c < j) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+__global__ void k_val_values(int n, const int* rp, const int* col, const double* val, int adj,
+                             int* offdeg, int* flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = rp[i], b = rp[i + 1];
+  bool has_diag = false;
+  double diag = 0.0, deg = 0.0;
+  int nd = 0;
+  int f = 0;
+  for (int p = a; p < b; ++p) {
+    double v = val[p];
+    int j = col[p];
+    if (!isfinite(v)) f |= 2;
+    if (j == i) {
+      if (adj) f |= 2;
+      has_diag = true;
+      diag = v;
+    } else {
+      double wij = adj ? v : -v;
+      if (!(wij > 0.0)) f |= 2;
+      deg += wij;
+      ++nd;
+      int t = find_col(rp, col, j, i);
+      if (t < 0 || __double_as_longlong(val[t]) != __double_as_longlong(v)) f |= 4;
+    }
+  }
+  if (!adj && b > a) {
+    if (!has_diag) {
+      f |= 2;
+    } else {
+      double tol = 1e-12 * (fabs(diag) > 1.0 ? fabs(diag) : 1.0);
+      if (fabs(diag - deg) > tol) f |= 2;
+    }
+  }
+  if (nd == 0) f |= 8;
+  offdeg[i] = nd;
+  if (f) atomicOr(flags, f);
+}
+
+__global__ void k_extract(int n, const int* rp, const int* col, const double* val, int adj,
+                          const int* rpw, int* colw, double* ww) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int k = rpw[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    int j = col[p];
+    if (j == i) continue;
+    colw[k] = j;
+    ww[k] = adj ? val[p] : -val[p];
+    ++k;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Shift sigma = 2 max_i d_i, d_i summed in row order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, const double* w,
+                                                     unsigned long long* dmax) {
+  __shared__ double lds[kBlock / 64];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (i < n)
+    for (int p = rp[i]; p < rp[i + 1]; ++p) d += w[p];
+  d = block_max(d, lds);
+  if (threadIdx.x == 0) atomicMax(dmax, (unsigned long long)__double_as_longlong(d));
+}
+
+// ---------------------------------------------------------------------------
+// Heavy-edge matching by locally dominant rounds: every free vertex points at
+// its best free neighbour in the strict edge order; mutual pointers match.
+// Under a strict total order this yields the greedy matching that takes the
+// edges from heaviest down.  mate: -1 free, -2 free without free neighbours.
+// ---------------------------------------------------------------------------
+__global__ void k_match_pick(int n, const int* rp, const int* col, const double* w,
+                             const int* mate, int* ptr) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || mate[v] != -1) return;
+  int best = -1;
+  double bw = 0.0;
+  for (int p = rp[v]; p < rp[v + 1]; ++p) {
+    int u = col[p];
+    if (mate[u] != -1) continue;
+    double wu = w[p];
+    if (best < 0 || edge_before(wu, v, u, bw, v, best)) {
+      best = u;
+      bw = wu;
+    }
+  }
+  ptr[v] = best;
+}
+
+__global__ void k_match_commit(int n, int* mate, const int* ptr, int* active) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || mate[v] != -1) return;
+  int u = ptr[v];
+  if (u < 0) {
+    mate[v] = -2;
+  } else if (ptr[u] == v) {
+    mate[v] = u;
+  } else {
+    atomicOr(active, 1);
+  }
+}
+
+// Aggregates (Algorithm 1): pairs; an unmatched vertex joins the aggregate of
+// its best neighbour; aggregates numbered by smallest member.
+__global__ void k_agg_root(int n, const int* rp, const int* col, const double* w,
+                           const int* mate, int* root, int* err) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int m = mate[v];
+  if (m >= 0) {
+    root[v] = v < m ? v : m;
+    return;
+  }
+  int a = rp[v], b = rp[v + 1];
+  if (a == b) {
+    root[v] = v;
+    return;
+  }
+  int best = col[a];
+  double bw = w[a];
+  for (int p = a + 1; p < b; ++p)
+    if (edge_before(w[p], v, col[p], bw, v, best)) {
+      best = col[p];
+      bw = w[p];
+    }
+  int mb = mate[best];
+  if (mb < 0) {
+    atomicOr(err, 1);
+    root[v] = v;
+    return;
+  }
+  root[v] = best < mb ? best : mb;
+}
+
+__global__ void k_agg_minmem(int n, const int* root, int* minmem) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicMin(&minmem[root[v]], v);
+}
+
+__global__ void k_agg_q(int n, const int* root, const int* minmem, const int* id, int* q) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) q[v] = id[minmem[root[v]]];
+}
+
+// ---------------------------------------------------------------------------
+// Jones-Plassmann rounds: a vertex takes the smallest colour absent among its
+// neighbours once every neighbour of higher priority is coloured.  This equals
+// sequential first-fit in priority order.
+// ---------------------------------------------------------------------------
+__global__ void k_colour_round(int n, const int* rp, const int* col, uint32_t seed, int* colour,
+                               int* active, int* maxc) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || colour[v] >= 0) return;
+  uint32_t pv = colour_priority(v, seed);
+  int a = rp[v], b = rp[v + 1];
+  for (int p = a; p < b; ++p) {
+    int u = col[p];
+    if (colour[u] < 0) {
+      uint32_t pu = colour_priority(u, seed);
+      if (pu > pv || (pu == pv && u < v)) {
+        atomicOr(active, 1);
+        return;
+      }
+    }
+  }
+  for (int base = 0;; base += 64) {
+    unsigned long long mask = 0;
+    for (int p = a; p < b; ++p) {
+      int c = colour[col[p]];
+      if (c >= base && c < base + 64) mask |= 1ULL << (c - base);
+    }
+    if (mask != ~0ULL) {
+      int c = base + __builtin_ctzll(~mask);
+      colour[v] = c;
+      atomicMax(maxc, c);
+      return;
+    }
+  }
+}
+
+__global__ void k_count_colours(int n, const int* colour, int* cnt) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicAdd(&cnt[colour[v]], 1);
+}
+
+__global__ void k_perm_fill(int n, const int* colour, int c, int start, const int* pos, int* perm,
+                            int* iperm) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || colour[v] != c) return;
+  int p = start + pos[v];
+  perm[v] = p;
+  iperm[p] = v;
+}
+
+// Colour-ordered copy: row i of the solve order is original row iperm[i];
+// columns are relabelled but keep their original order (so row sums add in
+// the same order as in the original numbering).
+__global__ void k_solve_fill(int n, const int* rp_c, const int* col_c, const double* w_c,
+                             const int* iperm, const int* perm, const int* rp, int* col,
+                             double* w64, float* w32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int v = iperm[i];
+  int k = rp[i];
+  for (int p = rp_c[v]; p < rp_c[v + 1]; ++p, ++k) {
+    col[k] = perm[col_c[p]];
+    double wv = w_c[p];
+    w64[k] = wv;
+    w32[k] = (float)wv;
+  }
+}
+
+__global__ void k_qs(int n, const int* perm, const int* q, const int* perm_next, int* qs) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int c = q[v];
+  qs[perm[v]] = perm_next ? perm_next[c] : c;
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin coarse graph I L I^T.  For coarse row I the terms are the fine
+// edges (v, j) with q(v) = I != q(j) = J; they are ordered by (J, min(v,j),
+// max(v,j)) and each run of equal J is summed sequentially in that order, so
+// W_c(I,J) and W_c(J,I) add the same fine weights in the same order.
+// ---------------------------------------------------------------------------
+__global__ void k_gal_count(int n, const int* rp, const int* col, const int* q, int* tcount) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int I = q[v], c = 0;
+  for (int p = rp[v]; p < rp[v + 1]; ++p) c += q[col[p]] != I;
+  if (c) atomicAdd(&tcount[I], c);
+}
+
+__global__ void k_gal_fill(int n, const int* rp, const int* col, const double* w, const int* q,
+                           const int* tstart, int* tfill, int* tJ, int* ta, int* tb, double* tw) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int I = q[v], c = 0;
+  for (int p = rp[v]; p < rp[v + 1]; ++p) c += q[col[p]] != I;
+  if (!c) return;
+  int k = tstart[I] + atomicAdd(&tfill[I], c);
+  for (int p = rp[v]; p < rp[v + 1]; ++p) {
+    int j = col[p];
+    int J = q[j];
+    if (J == I) continue;
+    tJ[k] = J;
+    ta[k] = v < j ? v : j;
+    tb[k] = v < j ? j : v;
+    tw[k] = w[p];
+    ++k;
+  }
+}
+
+__device__ inline bool term_less(int J1, int a1, int b1, int J2, int a2, int b2) {
+  if (J1 != J2) return J1 < J2;
+  if (a1 != a2) return a1 < a2;
+  return b1 < b2;
+}
+
+// Rows with at most 64 terms: one wavefront per row, rank sort in registers.
+__global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, const int* tstart,
+                                                         const int* tJ, const int* ta,
+                                                         const int* tb, const double* tw,
+                                                         int* cJ, double* cw, int* uniq) {
+  __shared__ int sJ[kBlock / 64][64];
+  __shared__ double sw[kBlock / 64][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int I = blockIdx.x * (kBlock / 64) + wave;
+  int s = 0, T = 0;
+  if (I < nc) {
+    s = tstart[I];
+    T = tstart[I + 1] - s;
+  }
+  const bool active = I < nc && T <= 64;
+  int myJ = INT_MAX, mya = 0, myb = 0;
+  double myw = 0.0;
+  if (active && lane < T) {
+    myJ = tJ[s + lane];
+    mya = ta[s + lane];
+    myb = tb[s + lane];
+    myw = tw[s + lane];
+  }
+  int rank = 0;
+  const int Tl = active ? T : 0;
+  for (int l = 0; l < 64; ++l) {
+    int J2 = __shfl(myJ, l, 64), a2 = __shfl(mya, l, 64), b2 = __shfl(myb, l, 64);
+    if (l < Tl && term_less(J2, a2, b2, myJ, mya, myb)) ++rank;
+  }
+  if (active && lane < T) {
+    sJ[wave][rank] = myJ;
+    sw[wave][rank] = myw;
+  }
+  __syncthreads();
+  bool head = false;
+  if (active && lane < T) head = lane == 0 || sJ[wave][lane] != sJ[wave][lane - 1];
+  unsigned long long mask = __ballot(head);
+  if (head) {
+    int pos = __popcll(mask & ((1ULL << lane) - 1ULL));
+    int J = sJ[wave][lane];
+    double sum = 0.0;
+    for (int p = lane; p < T && sJ[wave][p] == J; ++p) sum += sw[wave][p];
+    cJ[s + pos] = J;
+    cw[s + pos] = sum;
+  }
+  if (active && lane == 0) uniq[I] = __popcll(mask);
+}
+
+// Rows with more than 64 terms: one workgroup per listed row, rank sort into
+// global scratch, then a sequential collapse.
+__global__ __launch_bounds__(kBlock) void k_gal_rows_big(const int* list, const int* tstart,
+                                                       const int* tJ, const int* ta,
+                                                       const int* tb, const double* tw,
+                                                       int* sJ, double* sw, int* cJ,
+                                                       double* cw, int* uniq) {
+  const int I = list[blockIdx.x];
+  const int s = tstart[I], T = tstart[I + 1] - s;
+  for (int k = threadIdx.x; k < T; k += blockDim.x) {
+    int J = tJ[s + k], a = ta[s + k], b = tb[s + k];
+    int rank = 0;
+    for (int l = 0; l < T; ++l)
+      if (term_less(tJ[s + l], ta[s + l], tb[s + l], J, a, b)) ++rank;
+    sJ[s + rank] = J;
+    sw[s + rank] = tw[s + k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int u = 0;
+    int p = 0;
+    while (p < T) {
+      int J = sJ[s + p];
+      double sum = 0.0;
+      while (p < T && sJ[s + p] == J) sum += sw[s + p++];
+      cJ[s + u] = J;
+      cw[s + u] = sum;
+      ++u;
+    }
+    uniq[I] = u;
+  }
+}
+
+__global__ void k_list_fill(int n, const int* tstart, const int* pos, int* list) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (tstart[i + 1] - tstart[i]) > 64) list[pos[i]] = i;
+}
+
+__global__ void k_gal_compact(int nc, const int* tstart, const int* uniq, const int* crp,
+                              const int* cJ, const double* cw, int* col, double* w) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int s = tstart[I], d = crp[I], u = uniq[I];
+  for (int k = 0; k < u; ++k) {
+    col[d + k] = cJ[s + k];
+    w[d + k] = cw[s + k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host orchestration.
+// ---------------------------------------------------------------------------
+template <class T>
+static T* halloc(fv_hierarchy* h, size_t count) {
+  return static_cast<T*>(dev_alloc(h->ctx, std::max<size_t>(count, 1) * sizeof(T), &h->bytes));
+}
+
+static int read_int(const int* d, hipStream_t s, int* pinned) {
+  FV_HIP(hipMemcpyAsync(pinned, d, sizeof(int), hipMemcpyDeviceToHost, s));
+  FV_HIP(hipStreamSynchronize(s));
+  return *pinned;
+}
+
+static double level_sigma(const Level& L, unsigned long long* dmax, hipStream_t s,
+                          unsigned long long* pinned) {
+  FV_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned long long), s));
+  k_degree_max<<<nblk(L.n), kBlock, 0, s>>>(L.n, L.rp_c, L.w_c, dmax);
+  FV_HIP(hipGetLastError());
+  FV_HIP(hipMemcpyAsync(pinned, dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  FV_HIP(hipStreamSynchronize(s));
+  double d;
+  std::memcpy(&d, pinned, sizeof(double));
+  return 2.0 * d;
+}
+
+static void free_level(fv_hierarchy* h, Level& L) {
+  auto f = [&](void* p, size_t bytes) {
+    if (p) dev_free(h->ctx, p, bytes, &h->bytes);
+  };
+  size_t n = std::max(L.n, 1), m = std::max<long long>(L.m, 1), c = std::max(L.ncol + 1, 1);
+  f(L.rp_c, (L.n + 1) * sizeof(int));
+  f(L.col_c, m * sizeof(int));
+  f(L.w_c, m * sizeof(double));
+  f(L.q_c, n * sizeof(int));
+  f(L.colour_c, n * sizeof(int));
+  f(L.rp, (L.n + 1) * sizeof(int));
+  f(L.col, m * sizeof(int));
+  f(L.w64, m * sizeof(double));
+  f(L.w32, m * sizeof(float));
+  f(L.cptr, c * sizeof(int));
+  f(L.perm, n * sizeof(int));
+  f(L.iperm, n * sizeof(int));
+  f(L.qs, n * sizeof(int));
+  L = Level();
+}
+
+void free_hierarchy(fv_hierarchy* h) {
+  if (!h) return;
+  for (int l = 0; l < FV_MAX_LEVELS; ++l) free_level(h, h->lv[l]);
+  if (h->d_desc) dev_free(h->ctx, h->d_desc, sizeof(LevelDesc) * FV_MAX_LEVELS, &h->bytes);
+  delete h;
+}
+
+size_t hierarchy_nmax(const fv_hierarchy* h) { return h->levels ? (size_t)h->lv[0].n : 0; }
+
+fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_opts* o,
+                              hipStream_t s) {
+  if (!Lin) throw Error(FV_E_INVALID, "null graph");
+  const int n = Lin->n;
+  const int nnz = Lin->nnz;
+  if (n < 2 || nnz < 0 || !Lin->row_ptr || (nnz > 0 && (!Lin->col || !Lin->val)))
+    throw Error(FV_E_INVALID, "bad CSR header");
+  int n_coarse = o ? o->n_coarse : 25;
+  int max_levels = o ? o->max_levels : FV_MAX_LEVELS;
+  unsigned long long cseed = o ? o->colour_seed : 0ULL;
+  if (n_coarse < 1) throw Error(FV_E_INVALID, "n_coarse < 1");
+  if (max_levels < 1 || max_levels > FV_MAX_LEVELS) max_levels = FV_MAX_LEVELS;
+
+  Tmp tmp;
+  int* pin_i = nullptr;
+  unsigned long long* pin_u = nullptr;
+  long long* pin_ll = nullptr;
+  FV_HIP(hipHostMalloc((void**)&pin_i, 64, hipHostMallocDefault));
+  struct PinGuard {
+    int* p;
+    ~PinGuard() { (void)hipHostFree(p); }
+  } pg{pin_i};
+  pin_u = reinterpret_cast<unsigned long long*>(pin_i + 4);
+  pin_ll = reinterpret_cast<long long*>(pin_i + 8);
+
+  // Stage the input on the device.
+  const int* rp_in = Lin->row_ptr;
+  const int* col_in = Lin->col;
+  const double* val_in = Lin->val;
+  if (!Lin->on_device) {
+    int* r = tmp.get<int>(n + 1);
+    int* c = tmp.get<int>(nnz);
+    double* v = tmp.get<double>(nnz);
+    FV_HIP(hipMemcpyAsync(r, Lin->row_ptr, sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+    if (nnz) {
+      FV_HIP(hipMemcpyAsync(c, Lin->col, sizeof(int) * nnz, hipMemcpyHostToDevice, s));
+      FV_HIP(hipMemcpyAsync(v, Lin->val, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+    }
+    rp_in = r;
+    col_in = c;
+    val_in = v;
+  }
+
+  Scanner sc;
+  sc.cap = n / kScanTile + 4;
+  sc.bsum = tmp.get<long long>(sc.cap);
+  sc.s = s;
+  sc.host = pin_ll;
+
+  int* flags = tmp.get<int>(4);
+  FV_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
+  k_val_structure<<<nblk(n), kBlock, 0, s>>>(n, nnz, rp_in, col_in, flags);
+  FV_HIP(hipGetLastError());
+  if (read_int(flags, s, pin_i) & 1) throw Error(FV_E_INVALID, "CSR structure invalid");
+  int* offdeg = tmp.get<int>(n);
+  k_val_values<<<nblk(n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, Lin->is_adjacency ? 1 : 0,
+                                          offdeg, flags);
+  FV_HIP(hipGetLastError());
+  int f = read_int(flags, s, pin_i);
+  if (f & 2) throw Error(FV_E_NOT_LAPLACIAN, "not a graph Laplacian / adjacency");
+  if (f & 4) throw Error(FV_E_NOT_SYMMETRIC, "not symmetric");
+  if (f & 8) throw Error(FV_E_ISOLATED, "isolated vertex");
+
+  fv_hierarchy* h = new fv_hierarchy();
+  h->ctx = ctx;
+  try {
+    Level& L0 = h->lv[0];
+    L0.n = n;
+    L0.rp_c = halloc<int>(h, n + 1);
+    long long m0 = sc.run(FromArray{offdeg}, n, L0.rp_c, true);
+    L0.m = m0;
+    L0.col_c = halloc<int>(h, m0);
+    L0.w_c = halloc<double>(h, m0);
+    k_extract<<<nblk(n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, Lin->is_adjacency ? 1 : 0,
+                                         L0.rp_c, L0.col_c, L0.w_c);
+    FV_HIP(hipGetLastError());
+
+    // Scratch sized by level 0 and reused on every level.
+    const long long mcap = std::max<long long>(m0, 1);
+    int* mate = tmp.get<int>(n);
+    int* ptr = tmp.get<int>(n);
+    int* root = tmp.get<int>(n);
+    int* minmem = tmp.get<int>(n);
+    int* id = tmp.get<int>(n);
+    int* tcount = tmp.get<int>(n + 1);
+    int* tstart = tmp.get<int>(n + 1);
+    int* tfill = tmp.get<int>(n);
+    int* uniq = tmp.get<int>(n + 1);
+    int* list = tmp.get<int>(n);
+    int* lpos = tmp.get<int>(n);
+    int* tJ = tmp.get<int>(mcap);
+    int* ta = tmp.get<int>(mcap);
+    int* tb = tmp.get<int>(mcap);
+    double* tw = tmp.get<double>(mcap);
+    int* cJ = tmp.get<int>(mcap);
+    double* cw = tmp.get<double>(mcap);
+    int* sJ = tmp.get<int>(mcap);
+    double* sw = tmp.get<double>(mcap);
+    int* pos = tmp.get<int>(n);
+    int* cnt = tmp.get<int>(n + 1);
+    unsigned long long* dmax = tmp.get<unsigned long long>(1);
+
+    int l = 0;
+    for (;;) {
+      Level& F = h->lv[l];
+      F.sigma = level_sigma(F, dmax, s, pin_u);
+      if (F.n <= n_coarse || l + 1 >= max_levels) break;
+      const int fn = F.n;
+      // matching rounds
+      k_fill_int<<<nblk(fn), kBlock, 0, s>>>(mate, fn, -1);
+      for (int round = 0;; ++round) {
+        k_match_pick<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr);
+        FV_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
+        k_match_commit<<<nblk(fn), kBlock, 0, s>>>(fn, mate, ptr, flags);
+        FV_HIP(hipGetLastError());
+        if (!read_int(flags, s, pin_i)) break;
+        if (round > fn) throw Error(FV_E_DEVICE, "matching did not terminate");
+      }
+      // aggregates
+      FV_HIP(hipMemsetAsync(flags + 1, 0, sizeof(int), s));
+      k_agg_root<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, root, flags + 1);
+      k_fill_int<<<nblk(fn), kBlock, 0, s>>>(minmem, fn, INT_MAX);
+      k_agg_minmem<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem);
+      FV_HIP(hipGetLastError());
+      if (read_int(flags + 1, s, pin_i)) throw Error(FV_E_DEVICE, "matching not maximal");
+      const int nc = (int)sc.run(LeaderFlag{root, minmem}, fn, id, false);
+      if (nc < 2 || nc >= fn) break;
+      F.q_c = halloc<int>(h, fn);
+      k_agg_q<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem, id, F.q_c);
+      // colouring of this level for the smoother
+      F.colour_c = halloc<int>(h, fn);
+      k_fill_int<<<nblk(fn), kBlock, 0, s>>>(F.colour_c, fn, -1);
+      FV_HIP(hipMemsetAsync(flags + 2, 0, sizeof(int), s));
+      const uint32_t lseed = level_seed(cseed, l);
+      for (int round = 0;; ++round) {
+        FV_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
+        k_colour_round<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed, F.colour_c, flags,
+                                                   flags + 2);
+        FV_HIP(hipGetLastError());
+        if (!read_int(flags, s, pin_i)) break;
+        if (round > fn) throw Error(FV_E_DEVICE, "colouring did not terminate");
+      }
+      F.ncol = read_int(flags + 2, s, pin_i) + 1;
+      // Galerkin coarse graph
+      Level& Cl = h->lv[l + 1];
+      Cl.n = nc;
+      FV_HIP(hipMemsetAsync(tcount, 0, sizeof(int) * (nc + 1), s));
+      FV_HIP(hipMemsetAsync(tfill, 0, sizeof(int) * nc, s));
+      k_gal_count<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.q_c, tcount);
+      FV_HIP(hipGetLastError());
+      sc.run(FromArray{tcount}, nc, tstart, true);
+      k_gal_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, F.q_c, tstart, tfill, tJ,
+                                             ta, tb, tw);
+      k_gal_rows_small<<<nblk(nc, kBlock / 64), kBlock, 0, s>>>(nc, tstart, tJ, ta, tb, tw, cJ, cw,
+                                                                 uniq);
+      FV_HIP(hipGetLastError());
+      const int nbig = (int)sc.run(BigRow{tstart}, nc, lpos, false);
+      if (nbig > 0) {
+        k_list_fill<<<nblk(nc), kBlock, 0, s>>>(nc, tstart, lpos, list);
+        k_gal_rows_big<<<nbig, kBlock, 0, s>>>(list, tstart, tJ, ta, tb, tw, sJ, sw, cJ, cw, uniq);
+        FV_HIP(hipGetLastError());
+      }
+      Cl.rp_c = halloc<int>(h, nc + 1);
+      const long long mc = sc.run(FromArray{uniq}, nc, Cl.rp_c, true);
+      Cl.m = mc;
+      Cl.col_c = halloc<int>(h, mc);
+      Cl.w_c = halloc<double>(h, mc);
+      k_gal_compact<<<nblk(nc), kBlock, 0, s>>>(nc, tstart, uniq, Cl.rp_c, cJ, cw, Cl.col_c,
+                                                Cl.w_c);
+      FV_HIP(hipGetLastError());
+      ++l;
+    }
+    const int J = l;
+    h->levels = J + 1;
+
+    // Solve-order copies, coarsest first so that q can use the next perm.
+    for (int k = J; k >= 0; --k) {
+      Level& F = h->lv[k];
+      const int fn = F.n;
+      F.perm = halloc<int>(h, fn);
+      F.iperm = halloc<int>(h, fn);
+      if (k == J) {
+        F.ncol = 1;
+        F.cptr_h = {0, fn};
+        k_iota<<<nblk(fn), kBlock, 0, s>>>(F.perm, fn);
+        k_iota<<<nblk(fn), kBlock, 0, s>>>(F.iperm, fn);
+      } else {
+        FV_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (F.ncol + 1), s));
+        k_count_colours<<<nblk(fn), kBlock, 0, s>>>(fn, F.colour_c, cnt);
+        std::vector<int> ch(F.ncol);
+        FV_HIP(hipMemcpyAsync(ch.data(), cnt, sizeof(int) * F.ncol, hipMemcpyDeviceToHost, s));
+        FV_HIP(hipStreamSynchronize(s));
+        F.cptr_h.assign(F.ncol + 1, 0);
+        for (int c = 0; c < F.ncol; ++c) F.cptr_h[c + 1] = F.cptr_h[c] + ch[c];
+        for (int c = 0; c < F.ncol; ++c) {
+          sc.run(FlagEq{F.colour_c, c}, fn, pos, false);
+          k_perm_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.colour_c, c, F.cptr_h[c], pos, F.perm,
+                                                  F.iperm);
+        }
+        FV_HIP(hipGetLastError());
+      }
+      F.cptr = halloc<int>(h, F.ncol + 1);
+      FV_HIP(hipMemcpyAsync(F.cptr, F.cptr_h.data(), sizeof(int) * (F.ncol + 1),
+                            hipMemcpyHostToDevice, s));
+      F.rp = halloc<int>(h, fn + 1);
+      sc.run(PermDeg{F.rp_c, F.iperm}, fn, F.rp, true);
+      F.col = halloc<int>(h, F.m);
+      F.w64 = halloc<double>(h, F.m);
+      F.w32 = halloc<float>(h, F.m);
+      k_solve_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, F.iperm, F.perm, F.rp,
+                                               F.col, F.w64, F.w32);
+      FV_HIP(hipGetLastError());
+      if (k < J) {
+        F.qs = halloc<int>(h, fn);
+        k_qs<<<nblk(fn), kBlock, 0, s>>>(fn, F.perm, F.q_c, h->lv[k + 1].perm, F.qs);
+        FV_HIP(hipGetLastError());
+      }
+    }
+    // Device descriptors.
+    std::vector<LevelDesc> d(FV_MAX_LEVELS);
+    std::memset(d.data(), 0, sizeof(LevelDesc) * FV_MAX_LEVELS);
+    for (int k = 0; k <= J; ++k) {
+      const Level& F = h->lv[k];
+      d[k].n = F.n;
+      d[k].ncol = F.ncol;
+      d[k].m = F.m;
+      d[k].rp = F.rp;
+      d[k].col = F.col;
+      d[k].w64 = F.w64;
+      d[k].w32 = F.w32;
+      d[k].cptr = F.cptr;
+      d[k].qs = F.qs;
+      d[k].perm = F.perm;
+      d[k].iperm = F.iperm;
+      d[k].sigma = F.sigma;
+    }
+    h->d_desc = static_cast<LevelDesc*>(
+        dev_alloc(ctx, sizeof(LevelDesc) * FV_MAX_LEVELS, &h->bytes));
+    FV_HIP(hipMemcpyAsync(h->d_desc, d.data(), sizeof(LevelDesc) * FV_MAX_LEVELS,
+                          hipMemcpyHostToDevice, s));
+    FV_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    free_hierarchy(h);
+    throw;
+  }
+  return h;
+}
+
+}  // namespace fv

@@ -1,0 +1,1252 @@
+// Refinement on the device (Algorithm 3, Steps 2-3, and the finest Rayleigh
+// quotient): coarsest power iteration, prolongation, multicolour Gauss-Seidel
+// smoothing on (L - rho I) x = 0, power iteration on sigma I - L, the
+// cosine stopping test, and the finest-level Rayleigh quotient and residual.
+//
+// Two engines share the per-row arithmetic below:
+//  * multi-workgroup passes (one launch per colour / step) for large levels,
+//    reductions closed by the last block to finish, decisions kept on device;
+//  * a one-workgroup-per-graph engine that runs whole levels (all phases, all
+//    sweeps) inside one launch, used for the small levels of a big graph and
+//    for every graph of a batch (a persistent grid with a work queue).
+//
+// The stored iterate x carries a pending normalisation (mu, inv_s): the unit,
+// mean-free iterate is xhat = (x - mu) * inv_s.  Every pass applies it on the
+// fly and returns the sums that define the next one, so projection and
+// normalisation never need a pass of their own.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+
+#include "fv_device.h"
+#include "fv_internal.h"
+
+namespace fv {
+
+template <class VT>
+struct WSel;
+template <>
+struct WSel<float> {
+  __device__ static const float* w(const LevelDesc& L) { return L.w32; }
+};
+template <>
+struct WSel<double> {
+  __device__ static const double* w(const LevelDesc& L) { return L.w64; }
+};
+
+// ---------------------------------------------------------------------------
+// Per-row arithmetic.
+// ---------------------------------------------------------------------------
+
+// Shifted Gauss-Seidel update of row i (Algorithm 2 on (L - rho I) x = 0):
+// x_i <- sum_j w_ij x_j / (d_i - rho), relaxed by omega, for rows whose shifted
+// diagonal d_i - rho is at least d_i / 2; other rows keep their value (the
+// eigenvector stays a fixed point).  Rows below lower_end were already updated
+// in this sweep and are read as stored; the others are read through the
+// pending normalisation.  Accumulates
+// {sum u, sum u^2, sum u xhat_i, sum xhat_i, sum over already-updated
+// neighbours of w (u - x_j)^2} where u is the stored new value; the last term
+// adds up to u^T L u over the sweep (each edge counted by its later colour).
+template <class VT>
+__device__ inline void row_gs(int i, const LevelDesc& L, VT* __restrict__ x, int lower_end,
+                              double mu, double inv_s, double rho, double omega,
+                              double (&acc)[kNP]) {
+  const auto* __restrict__ w = WSel<VT>::w(L);
+  const int* __restrict__ col = L.col;
+  const int p0 = L.rp[i], p1 = L.rp[i + 1];
+  const double xo = ((double)x[i] - mu) * inv_s;
+  double num = 0.0, den = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    const int j = col[p];
+    const double wj = (double)w[p];
+    const double xj = (double)x[j];
+    num += wj * (j < lower_end ? xj : (xj - mu) * inv_s);
+    den += wj;
+  }
+  double u = xo;
+  const double a = den - rho;
+  if (den > 0.0 && a >= 0.5 * den) {
+    const double g = num / a;
+    u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
+  }
+  const VT us = (VT)u;
+  x[i] = us;
+  const double ud = (double)us;
+  double e = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    const int j = col[p];
+    if (j < lower_end) {
+      const double d = ud - (double)x[j];
+      e += (double)w[p] * d * d;
+    }
+  }
+  acc[0] += ud;
+  acc[1] += ud * ud;
+  acc[2] += ud * xo;
+  acc[3] += xo;
+  acc[4] += e;
+}
+
+// Power-iteration step of row i: y_i = sigma xhat_i - (L xhat)_i with
+// (L x)_i = sum_j w_ij (x_i - x_j).  Accumulates {sum y, sum y^2,
+// sum y xhat_i, sum xhat_i}.
+template <class VT>
+__device__ inline void row_pi(int i, const LevelDesc& L, const VT* __restrict__ x,
+                              VT* __restrict__ y, double mu, double inv_s, double sigma,
+                              double (&acc)[kNP]) {
+  const auto* __restrict__ w = WSel<VT>::w(L);
+  const int* __restrict__ col = L.col;
+  const double xi = (double)x[i];
+  double lx = 0.0;
+  for (int p = L.rp[i]; p < L.rp[i + 1]; ++p) lx += (double)w[p] * (xi - (double)x[col[p]]);
+  const double xo = (xi - mu) * inv_s;
+  const VT ys = (VT)(sigma * xo - lx * inv_s);
+  y[i] = ys;
+  const double yd = (double)ys;
+  acc[0] += yd;
+  acc[1] += yd * yd;
+  acc[2] += yd * xo;
+  acc[3] += xo;
+}
+
+// Prolongation of row i (Algorithm 3, Step 3): v_i = xhat_c[q(i)], plus the
+// row's share of v^T L v (half of sum_j w_ij (v_i - v_j)^2) for the first
+// shift.  Accumulates {sum v, sum v^2, -, -, energy}.
+template <class SRC, class VT>
+__device__ inline void row_prolong(int i, const LevelDesc& L, const SRC* __restrict__ xc,
+                                   VT* __restrict__ xf, double muc, double inv_sc,
+                                   double (&acc)[kNP]) {
+  const auto* __restrict__ w = WSel<VT>::w(L);
+  const int* __restrict__ col = L.col;
+  const int* __restrict__ qs = L.qs;
+  const VT vs = (VT)(((double)xc[qs[i]] - muc) * inv_sc);
+  xf[i] = vs;
+  const double v = (double)vs;
+  double e = 0.0;
+  for (int p = L.rp[i]; p < L.rp[i + 1]; ++p) {
+    const double vj = (double)(VT)(((double)xc[qs[col[p]]] - muc) * inv_sc);
+    const double d = v - vj;
+    e += (double)w[p] * d * d;
+  }
+  acc[0] += v;
+  acc[1] += v * v;
+  acc[4] += 0.5 * e;
+}
+
+// Rayleigh-quotient row (FP64 weights): lx_i = (L xhat)_i, half edge energy,
+// xhat_i^2 and |xhat_i|.
+template <class VT>
+__device__ inline void row_rq(int i, const LevelDesc& L, const VT* __restrict__ x, double mu,
+                              double inv_s, double* __restrict__ lxo, double (&acc)[3]) {
+  const double* __restrict__ w = L.w64;
+  const int* __restrict__ col = L.col;
+  const double xi = ((double)x[i] - mu) * inv_s;
+  double lx = 0.0, e = 0.0;
+  for (int p = L.rp[i]; p < L.rp[i + 1]; ++p) {
+    const double d = xi - ((double)x[col[p]] - mu) * inv_s;
+    lx += w[p] * d;
+    e += w[p] * d * d;
+  }
+  lxo[i] = lx;
+  acc[0] += xi * xi;
+  acc[1] += 0.5 * e;
+  acc[2] = fmax(acc[2], fabs(xi));
+}
+
+// ---------------------------------------------------------------------------
+// Scalar updates after a pass (sums -> next pending normalisation).
+// ---------------------------------------------------------------------------
+struct Scal {
+  double mu, inv_s, cos, rho;
+};
+
+__device__ inline Scal after_gs(const double (&S)[kNP], int n) {
+  Scal r;
+  r.mu = S[0] / n;
+  double var = S[1] - S[0] * r.mu;
+  r.inv_s = var > 0.0 ? 1.0 / sqrt(var) : 1.0;
+  r.cos = (S[2] - r.mu * S[3]) * r.inv_s;
+  r.rho = var > 0.0 ? S[4] / var : 0.0;
+  return r;
+}
+
+__device__ inline Scal after_prolong(const double (&S)[kNP], int n) {
+  Scal r;
+  r.mu = S[0] / n;
+  double var = S[1] - S[0] * r.mu;
+  r.inv_s = var > 0.0 ? 1.0 / sqrt(var) : 1.0;
+  r.cos = 1.0;
+  r.rho = var > 0.0 ? S[4] / var : 0.0;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Multi-workgroup passes.
+// ---------------------------------------------------------------------------
+__global__ void k_phase_begin(DevState* st, int cap, int forced, double tol) {
+  st->done = cap <= 0 ? 1 : 0;
+  st->iters = 0;
+  st->cap = cap;
+  st->forced = forced;
+  st->tol = tol;
+}
+
+// Final reduction of nslots partial slots (layout part[k * stride + slot]).
+__device__ inline void reduce_slots(const double* part, int stride, int nslots,
+                                    double (&S)[kNP], double* lds) {
+#pragma unroll
+  for (int k = 0; k < kNP; ++k) S[k] = 0.0;
+  for (int s = threadIdx.x; s < nslots; s += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + s];
+  block_sum<kNP>(S, lds);
+}
+
+__device__ inline void write_slot(double* part, int stride, int slot, const double (&S)[kNP]) {
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < kNP; ++k) part[k * stride + slot] = S[k];
+}
+
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_gs_colour(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
+                                                    DevState* st, double* part, int stride,
+                                                    int slot_base, int last, int nslots,
+                                                    double omega) {
+  __shared__ double lds[(kBlock / 64) * kNP];
+  __shared__ int flag;
+  if (st->done) return;
+  VT* x = st->cur ? xb : xa;
+  const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = r0 + b * kBlock + threadIdx.x;
+  if (i < r1) row_gs<VT>(i, L, x, r0, mu, inv_s, rho, omega, acc);
+  block_sum<kNP>(acc, lds);
+  write_slot(part, stride, slot_base + blockIdx.x, acc);
+  if (!last) return;
+  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
+  double S[kNP];
+  reduce_slots(part, stride, nslots, S, lds);
+  if (threadIdx.x == 0) {
+    Scal r = after_gs(S, L.n);
+    st->mu = r.mu;
+    st->inv_s = r.inv_s;
+    st->cos = r.cos;
+    st->rho = r.rho;
+    int it = st->iters + 1;
+    st->iters = it;
+    st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+    st->counter = 0;
+  }
+}
+
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_pi_step(LevelDesc L, VT* xa, VT* xb, DevState* st,
+                                                  double* part, int stride) {
+  __shared__ double lds[(kBlock / 64) * kNP];
+  __shared__ int flag;
+  if (st->done) return;
+  const int cur = st->cur;
+  const VT* x = cur ? xb : xa;
+  VT* y = cur ? xa : xb;
+  const double mu = st->mu, inv_s = st->inv_s;
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * kBlock + threadIdx.x;
+  if (i < L.n) row_pi<VT>(i, L, x, y, mu, inv_s, L.sigma, acc);
+  block_sum<kNP>(acc, lds);
+  write_slot(part, stride, blockIdx.x, acc);
+  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
+  double S[kNP];
+  reduce_slots(part, stride, gridDim.x, S, lds);
+  if (threadIdx.x == 0) {
+    Scal r = after_gs(S, L.n);  // same formulas; rho unused
+    st->mu = r.mu;
+    st->inv_s = r.inv_s;
+    st->cos = r.cos;
+    st->cur = 1 - cur;
+    int it = st->iters + 1;
+    st->iters = it;
+    st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+    st->counter = 0;
+  }
+}
+
+template <class SRC, class VT>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelDesc L, const SRC* xc_a,
+                                                  const SRC* xc_b, VT* xf_a, VT* xf_b,
+                                                  DevState* st, double* part, int stride) {
+  __shared__ double lds[(kBlock / 64) * kNP];
+  __shared__ int flag;
+  const int cur = st->cur;
+  const SRC* xc = cur ? xc_b : xc_a;
+  VT* xf = cur ? xf_a : xf_b;
+  const double mu = st->mu, inv_s = st->inv_s;
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * kBlock + threadIdx.x;
+  if (i < L.n) row_prolong<SRC, VT>(i, L, xc, xf, mu, inv_s, acc);
+  block_sum<kNP>(acc, lds);
+  write_slot(part, stride, blockIdx.x, acc);
+  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
+  double S[kNP];
+  reduce_slots(part, stride, gridDim.x, S, lds);
+  if (threadIdx.x == 0) {
+    Scal r = after_prolong(S, L.n);
+    st->mu = r.mu;
+    st->inv_s = r.inv_s;
+    st->rho = r.rho;
+    st->cur = 1 - cur;
+    st->counter = 0;
+  }
+}
+
+// Rayleigh quotient lambda = xhat^T L xhat / xhat^T xhat (FP64 weights).
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_rq(LevelDesc L, const VT* xa, const VT* xb,
+                                             DevState* st, double* lx, double* part,
+                                             int stride) {
+  __shared__ double lds[(kBlock / 64) * kNP];
+  __shared__ int flag;
+  const VT* x = st->cur ? xb : xa;
+  const double mu = st->mu, inv_s = st->inv_s;
+  double acc3[3] = {0.0, 0.0, 0.0};
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * kBlock + threadIdx.x;
+  if (i < L.n) row_rq<VT>(i, L, x, mu, inv_s, lx, acc3);
+  const double mx = block_max(acc3[2], lds);
+  double acc[kNP] = {acc3[0], acc3[1], mx, 0.0, 0.0};
+  double t2[2] = {acc[0], acc[1]};
+  block_sum<2>(t2, lds);
+  acc[0] = t2[0];
+  acc[1] = t2[1];
+  write_slot(part, stride, blockIdx.x, acc);
+  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
+  double s0 = 0.0, s1 = 0.0, m = 0.0;
+  for (int s = threadIdx.x; s < (int)gridDim.x; s += blockDim.x) {
+    s0 += part[s];
+    s1 += part[stride + s];
+    m = fmax(m, part[2 * stride + s]);
+  }
+  double t[2] = {s0, s1};
+  block_sum<2>(t, lds);
+  m = block_max(m, lds);
+  if (threadIdx.x == 0) {
+    st->sumsq = t[0];
+    st->lambda = t[1] / t[0];
+    st->xmax = m;
+    st->rho = st->lambda;
+    st->counter = 0;
+  }
+}
+
+// Residual ||L xhat - lambda xhat|| / ||xhat|| and the first original index
+// with |xhat_i| >= 1e-3 max|xhat| (output sign).
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_residual(LevelDesc L, const VT* xa, const VT* xb,
+                                                   DevState* st, const double* lx,
+                                                   double* part, int* ipart, int stride) {
+  __shared__ double lds[(kBlock / 64) * kNP];
+  __shared__ int ilds[kBlock / 64];
+  __shared__ int flag;
+  const VT* x = st->cur ? xb : xa;
+  const double mu = st->mu, inv_s = st->inv_s, lam = st->lambda, thr = 1e-3 * st->xmax;
+  double r2 = 0.0;
+  int cand = INT_MAX;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = b * kBlock + threadIdx.x;
+  if (i < L.n) {
+    const double xh = ((double)x[i] - mu) * inv_s;
+    const double r = lx[i] - lam * xh;
+    r2 = r * r;
+    if (fabs(xh) >= thr) cand = L.iperm[i];
+  }
+  double t[1] = {r2};
+  block_sum<1>(t, lds);
+  cand = block_min_int(cand, ilds);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = t[0];
+    ipart[blockIdx.x] = cand;
+  }
+  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
+  double s = 0.0;
+  int c = INT_MAX;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
+    s += part[k];
+    c = min(c, ipart[k]);
+  }
+  double tt[1] = {s};
+  block_sum<1>(tt, lds);
+  c = block_min_int(c, ilds);
+  if (threadIdx.x == 0) {
+    st->res = sqrt(tt[0] / st->sumsq);
+    st->sign_idx = c;
+    double xv = c < INT_MAX ? ((double)x[L.perm[c]] - mu) * inv_s : 1.0;
+    st->sign = xv < 0.0 ? -1.0 : 1.0;
+    st->counter = 0;
+  }
+}
+
+template <class VT>
+__global__ void k_output(LevelDesc L, const VT* xa, const VT* xb, const DevState* st,
+                         double* out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= L.n) return;
+  const VT* x = st->cur ? xb : xa;
+  out[v] = st->sign * (((double)x[L.perm[v]] - st->mu) * st->inv_s);
+}
+
+// ---------------------------------------------------------------------------
+// One-workgroup engine.
+// ---------------------------------------------------------------------------
+struct EngineCtx {
+  double* lds;  // (kWG / 64) * kNP doubles
+  int* ilds;
+};
+
+// Coarsest solve in FP64 (Algorithm 3, Step 2): power iteration on
+// sigma I - L with projection, from the seeded start, stopping when
+// ||L x - rho x|| <= 1e-13 sigma or at the cap (forced >= 0: exactly forced
+// steps).  Writes the unit iterate to out; returns steps, sets *conv.
+__device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int max_it,
+                               int forced, double* out, double* lx, int* conv, EngineCtx& E) {
+  const int n = L.n;
+  const double sigma = L.sigma;
+  const double* __restrict__ w = L.w64;
+  const int* __restrict__ col = L.col;
+  int it = 0;
+  if (n <= 64) {
+    // One wavefront: lane i owns row i; neighbours read by lane shuffles.
+    __shared__ int s_it, s_conv;
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      const bool has = lane < n;
+      const int p0 = has ? L.rp[lane] : 0, p1 = has ? L.rp[lane + 1] : 0;
+      int deg = p1 - p0, maxdeg = deg;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, off, 64));
+      double x = has ? 2.0 * splitmix_uniform(seed, (unsigned long long)lane + 1ULL) - 1.0 : 0.0;
+      double m = wave_sum(x) / n;
+      x = has ? x - m : 0.0;
+      x *= 1.0 / sqrt(wave_sum(x * x));
+      int cv = 0;
+      for (;;) {
+        double l = 0.0;
+        for (int k = 0; k < maxdeg; ++k) {
+          const int j = k < deg ? col[p0 + k] : lane;
+          const double xj = __shfl(x, j, 64);
+          if (k < deg) l += w[p0 + k] * (x - xj);
+        }
+        if (forced >= 0) {
+          if (it >= forced) {
+            cv = 1;
+            break;
+          }
+        } else {
+          const double rho = wave_sum(x * l);
+          const double r = l - rho * x;
+          if (sqrt(wave_sum(r * r)) <= 1e-13 * sigma) {
+            cv = 1;
+            break;
+          }
+          if (it >= max_it) break;
+        }
+        double y = sigma * x - l;
+        const double my = wave_sum(y) / n;
+        y = has ? y - my : 0.0;
+        x = y * (1.0 / sqrt(wave_sum(y * y)));
+        ++it;
+      }
+      if (has) out[lane] = x;
+      if (lane == 0) {
+        s_it = it;
+        s_conv = cv;
+      }
+    }
+    __syncthreads();
+    it = s_it;
+    *conv = s_conv;
+    __syncthreads();
+    return it;
+  }
+  // General size: rows strided over the workgroup.
+  double* x = out;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    x[i] = 2.0 * splitmix_uniform(seed, (unsigned long long)i + 1ULL) - 1.0;
+  __syncthreads();
+  auto project_normalise = [&](double* v) {
+    double t[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t[0] += v[i];
+    block_sum<1>(t, E.lds);
+    const double m = t[0] / n;
+    double q[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      v[i] -= m;
+      q[0] += v[i] * v[i];
+    }
+    block_sum<1>(q, E.lds);
+    const double inv = 1.0 / sqrt(q[0]);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] *= inv;
+    __syncthreads();
+  };
+  project_normalise(x);
+  int cv = 0;
+  for (;;) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double l = 0.0;
+      for (int p = L.rp[i]; p < L.rp[i + 1]; ++p) l += w[p] * (x[i] - x[col[p]]);
+      lx[i] = l;
+    }
+    __syncthreads();
+    if (forced >= 0) {
+      if (it >= forced) {
+        cv = 1;
+        break;
+      }
+    } else {
+      double t[1] = {0.0};
+      for (int i = threadIdx.x; i < n; i += blockDim.x) t[0] += x[i] * lx[i];
+      block_sum<1>(t, E.lds);
+      double r[1] = {0.0};
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double d = lx[i] - t[0] * x[i];
+        r[0] += d * d;
+      }
+      block_sum<1>(r, E.lds);
+      if (sqrt(r[0]) <= 1e-13 * sigma) {
+        cv = 1;
+        break;
+      }
+      if (it >= max_it) break;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = sigma * x[i] - lx[i];
+    __syncthreads();
+    project_normalise(x);
+    ++it;
+  }
+  *conv = cv;
+  return it;
+}
+
+template <class VT>
+__device__ Scal engine_gs_sweep(const LevelDesc& L, VT* x, Scal s, double omega, EngineCtx& E) {
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < L.ncol; ++c) {
+    const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+      row_gs<VT>(i, L, x, r0, s.mu, s.inv_s, s.rho, omega, acc);
+    __syncthreads();
+  }
+  block_sum<kNP>(acc, E.lds);
+  return after_gs(acc, L.n);
+}
+
+template <class VT>
+__device__ Scal engine_pi_step(const LevelDesc& L, const VT* x, VT* y, Scal s, EngineCtx& E) {
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x)
+    row_pi<VT>(i, L, x, y, s.mu, s.inv_s, L.sigma, acc);
+  __syncthreads();
+  block_sum<kNP>(acc, E.lds);
+  Scal r = after_gs(acc, L.n);
+  r.rho = s.rho;
+  return r;
+}
+
+template <class SRC, class VT>
+__device__ Scal engine_prolong(const LevelDesc& L, const SRC* xc, VT* xf, Scal s, EngineCtx& E) {
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x)
+    row_prolong<SRC, VT>(i, L, xc, xf, s.mu, s.inv_s, acc);
+  __syncthreads();
+  block_sum<kNP>(acc, E.lds);
+  return after_prolong(acc, L.n);
+}
+
+// Phase counts: forced (replay) or free with the cosine test.
+struct PhaseCfg {
+  int forced;  // -1 = free
+  int cap;
+  double tol;
+};
+
+template <class VT>
+__device__ int engine_gs_phase(const LevelDesc& L, VT* x, Scal& s, double omega, PhaseCfg P,
+                               EngineCtx& E) {
+  const int lim = P.forced >= 0 ? P.forced : P.cap;
+  int k = 0;
+  while (k < lim) {
+    s = engine_gs_sweep<VT>(L, x, s, omega, E);
+    ++k;
+    if (P.forced < 0 && s.cos > 1.0 - P.tol) break;
+  }
+  return k;
+}
+
+template <class VT>
+__device__ int engine_pi_phase(const LevelDesc& L, VT* xa, VT* xb, int& cur, Scal& s,
+                               PhaseCfg P, EngineCtx& E) {
+  const int lim = P.forced >= 0 ? P.forced : P.cap;
+  int k = 0;
+  while (k < lim) {
+    VT* x = cur ? xb : xa;
+    VT* y = cur ? xa : xb;
+    s = engine_pi_step<VT>(L, x, y, s, E);
+    cur = 1 - cur;
+    ++k;
+    if (P.forced < 0 && s.cos > 1.0 - P.tol) break;
+  }
+  return k;
+}
+
+// Rayleigh quotient, residual and sign index on the finest level.
+template <class VT>
+__device__ void engine_rq_residual(const LevelDesc& L, const VT* x, const Scal& s, double* lx,
+                                   double& lam, double& res, double& sign, EngineCtx& E) {
+  double a3[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x) row_rq<VT>(i, L, x, s.mu, s.inv_s, lx, a3);
+  __syncthreads();
+  const double mx = block_max(a3[2], E.lds);
+  double t[2] = {a3[0], a3[1]};
+  block_sum<2>(t, E.lds);
+  lam = t[1] / t[0];
+  const double thr = 1e-3 * mx;
+  double r[1] = {0.0};
+  int cand = INT_MAX;
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+    const double xh = ((double)x[i] - s.mu) * s.inv_s;
+    const double d = lx[i] - lam * xh;
+    r[0] += d * d;
+    if (fabs(xh) >= thr) cand = min(cand, L.iperm[i]);
+  }
+  block_sum<1>(r, E.lds);
+  cand = block_min_int(cand, E.ilds);
+  res = sqrt(r[0] / t[0]);
+  const double xv = cand < INT_MAX ? ((double)x[L.perm[cand]] - s.mu) * s.inv_s : 1.0;
+  sign = xv < 0.0 ? -1.0 : 1.0;
+}
+
+template <class VT>
+__device__ void engine_run(const GraphTask& T, EngineCtx& E) {
+  const LevelDesc* lv = T.lv;
+  const int J = T.J;
+  int si = 0;  // replay cursor
+  auto next_forced = [&]() -> int { return (T.replay && si < T.replay_len) ? T.replay[si++] : -1; };
+  int slen = 0;
+  auto push = [&](int v) {
+    if (threadIdx.x == 0 && slen < FV_SCHEDULE_CAP) T.sched[slen] = v;
+    ++slen;
+  };
+  double* xa64 = static_cast<double*>(T.xa);
+  VT* xa = static_cast<VT*>(T.xa);
+  VT* xb = static_cast<VT*>(T.xb);
+  int conv = 0;
+  const int cit = engine_coarsest(lv[J], T.seed, T.max_coarsest, next_forced(), xa64, T.lx, &conv, E);
+  push(cit);
+  __syncthreads();
+  int cur = 0;
+  Scal s{0.0, 1.0, 1.0, 0.0};
+  bool coarse64 = true;
+  for (int l = J - 1; l >= T.stop; --l) {
+    const LevelDesc& L = lv[l];
+    if (coarse64) {
+      s = engine_prolong<double, VT>(L, xa64, xb, s, E);
+      coarse64 = false;
+    } else {
+      s = engine_prolong<VT, VT>(L, cur ? xb : xa, cur ? xa : xb, s, E);
+    }
+    cur = 1 - cur;
+    PhaseCfg pg{next_forced(), T.max_gs, T.tol_cos};
+    const int g = engine_gs_phase<VT>(L, cur ? xb : xa, s, T.omega, pg, E);
+    PhaseCfg pp{next_forced(), T.max_pi, T.tol_cos};
+    const int p = engine_pi_phase<VT>(L, xa, xb, cur, s, pp, E);
+    push(g);
+    push(p);
+    __syncthreads();
+  }
+  if (coarse64 && J == 0) {
+    // One-level hierarchy: the coarsest iterate is the answer; store it in the
+    // working precision of the finest level.
+    double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < lv[0].n; i += blockDim.x) {
+      const VT v = (VT)xa64[i];
+      xb[i] = v;
+      acc[0] += (double)v;
+      acc[1] += (double)v * (double)v;
+    }
+    __syncthreads();
+    block_sum<kNP>(acc, E.lds);
+    cur = 1;
+    s = after_prolong(acc, lv[0].n);
+  }
+  if (!T.finalize) {
+    if (threadIdx.x == 0) {
+      T.st->mu = s.mu;
+      T.st->inv_s = s.inv_s;
+      T.st->rho = s.rho;
+      T.st->cos = s.cos;
+      T.st->cur = cur;
+      T.st->err = conv ? 0 : 1;
+      *T.sched_len = slen;
+    }
+    return;
+  }
+  const LevelDesc& L0 = lv[0];
+  double lam = 0.0, res = 0.0, sign = 1.0;
+  engine_rq_residual<VT>(L0, cur ? xb : xa, s, T.lx, lam, res, sign, E);
+  int outer = 0;
+  if (J > 0) {
+    for (;;) {
+      int fg, fp;
+      if (T.replay) {
+        if (si >= T.replay_len) break;
+        fg = next_forced();
+        fp = next_forced();
+      } else {
+        if (!(T.tol_res > 0.0) || res <= T.tol_res || outer >= T.max_outer) break;
+        fg = fp = -1;
+      }
+      s.rho = lam;
+      PhaseCfg pg{fg, T.max_gs, T.tol_cos};
+      const int g = engine_gs_phase<VT>(L0, cur ? xb : xa, s, T.omega, pg, E);
+      PhaseCfg pp{fp, T.max_pi, T.tol_cos};
+      const int p = engine_pi_phase<VT>(L0, xa, xb, cur, s, pp, E);
+      push(g);
+      push(p);
+      ++outer;
+      __syncthreads();
+      engine_rq_residual<VT>(L0, cur ? xb : xa, s, T.lx, lam, res, sign, E);
+    }
+  }
+  const VT* x = cur ? xb : xa;
+  for (int v = threadIdx.x; v < L0.n; v += blockDim.x)
+    T.x_out[v] = sign * (((double)x[L0.perm[v]] - s.mu) * s.inv_s);
+  if (threadIdx.x == 0) {
+    T.st->lambda = lam;
+    T.st->res = res;
+    T.st->cos = s.cos;
+    T.st->mu = s.mu;
+    T.st->inv_s = s.inv_s;
+    T.st->cur = cur;
+    bool nc = !conv || (!T.replay && T.tol_res > 0.0 && res > T.tol_res);
+    T.st->err = nc ? 1 : 0;
+    *T.sched_len = slen;
+  }
+}
+
+template <class VT>
+__global__ __launch_bounds__(kWG) void k_engine(const GraphTask* tasks, int ntasks,
+                                              unsigned* queue) {
+  __shared__ double lds[(kWG / 64) * kNP];
+  __shared__ int ilds[kWG / 64];
+  __shared__ int s_task;
+  EngineCtx E{lds, ilds};
+  for (;;) {
+    if (threadIdx.x == 0) s_task = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= ntasks) break;
+    engine_run<VT>(tasks[t], E);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+static inline int nblk(long long n, int b = kBlock) {
+  return (int)std::max<long long>(1, (n + b - 1) / b);
+}
+
+struct Workspace {
+  void* xa;
+  void* xb;
+  double* lx;
+  double* part;
+  int* ipart;
+  DevState* st;
+  GraphTask* task;
+  int* sched;
+  int* sched_len;
+  int* replay;
+  unsigned* queue;
+  int stride;
+};
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Partial-sum slots: a sweep launches ceil(rows_c / kBlock) blocks per colour,
+// at most n / kBlock + ncolours in total.
+static size_t slot_count(size_t nmax, int maxcol) {
+  return nmax / kBlock + (size_t)maxcol + 2 * FV_MAX_LEVELS + 1024;
+}
+
+size_t solve_workspace_bytes(size_t nmax, int maxcol) {
+  const size_t slots = slot_count(nmax, maxcol);
+  return 3 * align_up(8 * std::max<size_t>(nmax, 1)) + align_up(8 * kNP * slots) +
+         align_up(4 * slots) + align_up(sizeof(DevState)) + align_up(sizeof(GraphTask)) +
+         2 * align_up(4 * FV_SCHEDULE_CAP) + align_up(64);
+}
+
+static Workspace carve(void* base, size_t nmax, int maxcol) {
+  Workspace w;
+  char* p = static_cast<char*>(base);
+  const size_t slots = slot_count(nmax, maxcol);
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += align_up(b);
+    return r;
+  };
+  w.xa = take(8 * std::max<size_t>(nmax, 1));
+  w.xb = take(8 * std::max<size_t>(nmax, 1));
+  w.lx = reinterpret_cast<double*>(take(8 * std::max<size_t>(nmax, 1)));
+  w.part = reinterpret_cast<double*>(take(8 * kNP * slots));
+  w.ipart = reinterpret_cast<int*>(take(4 * slots));
+  w.st = reinterpret_cast<DevState*>(take(sizeof(DevState)));
+  w.task = reinterpret_cast<GraphTask*>(take(sizeof(GraphTask)));
+  w.sched = reinterpret_cast<int*>(take(4 * FV_SCHEDULE_CAP));
+  w.replay = reinterpret_cast<int*>(take(4 * FV_SCHEDULE_CAP));
+  w.queue = reinterpret_cast<unsigned*>(take(64));
+  w.sched_len = reinterpret_cast<int*>(w.queue + 4);
+  w.stride = (int)slots;
+  return w;
+}
+
+struct HostState {
+  int done;
+  int iters;
+};
+
+template <class VT>
+static int run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const Workspace& W,
+                           int forced, int cap, double tol, double omega, hipStream_t s,
+                           int* pinned) {
+  const int lim = forced >= 0 ? forced : cap;
+  k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol);
+  VT* xa = static_cast<VT*>(W.xa);
+  VT* xb = static_cast<VT*>(W.xb);
+  std::vector<int> nbs(L.ncol);
+  int nslots = 0;
+  for (int c = 0; c < L.ncol; ++c) {
+    nbs[c] = nblk(Lh.cptr_h[c + 1] - Lh.cptr_h[c]);
+    nslots += nbs[c];
+  }
+  if (nslots > W.stride) throw Error(FV_E_DEVICE, "partial-sum slots exceeded");
+  auto enqueue = [&](int k) {
+    for (int it = 0; it < k; ++it) {
+      if (gs) {
+        int base = 0;
+        for (int c = 0; c < L.ncol; ++c) {
+          k_gs_colour<VT><<<nbs[c], kBlock, 0, s>>>(L, Lh.cptr_h[c], Lh.cptr_h[c + 1], xa, xb,
+                                                    W.st, W.part, W.stride, base,
+                                                    c == L.ncol - 1 ? 1 : 0, nslots, omega);
+          base += nbs[c];
+        }
+      } else {
+        k_pi_step<VT><<<nblk(L.n), kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
+      }
+    }
+    FV_HIP(hipGetLastError());
+  };
+  if (forced >= 0) {
+    enqueue(forced);
+    return forced;
+  }
+  int enq = 0, chunk = 2;
+  while (enq < lim) {
+    const int k = std::min(chunk, lim - enq);
+    enqueue(k);
+    enq += k;
+    FV_HIP(hipMemcpyAsync(pinned, &W.st->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    if (pinned[0]) break;
+    chunk = std::min(chunk * 2, 64);
+  }
+  FV_HIP(hipMemcpyAsync(pinned, &W.st->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  FV_HIP(hipStreamSynchronize(s));
+  return pinned[1];
+}
+
+static LevelDesc host_desc(const Level& F) {
+  LevelDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.n = F.n;
+  d.ncol = F.ncol;
+  d.m = F.m;
+  d.rp = F.rp;
+  d.col = F.col;
+  d.w64 = F.w64;
+  d.w32 = F.w32;
+  d.cptr = F.cptr;
+  d.qs = F.qs;
+  d.perm = F.perm;
+  d.iperm = F.iperm;
+  d.sigma = F.sigma;
+  return d;
+}
+
+static void fill_task(GraphTask& T, const fv_hierarchy* h, const fv_solve_opts* o, int stop,
+                      void* xa, void* xb, double* lx, double* x_out, DevState* st,
+                      const int* replay, int replay_len, int* sched, int* sched_len) {
+  std::memset(&T, 0, sizeof(T));
+  T.lv = h->d_desc;
+  T.J = h->levels - 1;
+  T.stop = stop;
+  T.prec = o->prec;
+  T.finalize = stop == 0 ? 1 : 0;
+  T.xa = xa;
+  T.xb = xb;
+  T.lx = lx;
+  T.x_out = x_out;
+  T.st = st;
+  T.replay = replay;
+  T.replay_len = replay_len;
+  T.sched = sched;
+  T.sched_len = sched_len;
+  T.seed = o->seed;
+  T.tol_cos = o->tol_cos;
+  T.tol_res = o->tol_res;
+  T.omega = o->omega;
+  T.max_gs = o->max_gs;
+  T.max_pi = o->max_pi;
+  T.max_outer = o->max_outer;
+  T.max_coarsest = o->max_coarsest;
+}
+
+static long long schedule_bytes(const fv_hierarchy* h, const int* sched, int len, int prec) {
+  const int J = h->levels - 1;
+  long long b = 0;
+  int k = 1;
+  for (int l = J - 1; l >= 0 && k + 1 < len; --l, k += 2) {
+    const Level& F = h->lv[l];
+    b += (long long)(sched[k] + sched[k + 1] + 1) * pass_bytes(F.n, F.m, prec);
+  }
+  const Level& F0 = h->lv[0];
+  for (; k + 1 < len; k += 2)
+    b += (long long)(sched[k] + sched[k + 1]) * pass_bytes(F0.n, F0.m, prec);
+  return b;
+}
+
+template <class VT>
+static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
+                             double* x_out, int x_on_device, double* lambda_out,
+                             fv_solve_stats* stats, hipStream_t s) {
+  const int J = h->levels - 1;
+  const size_t nmax = hierarchy_nmax(h);
+  int maxcol = 1;
+  for (int l = 0; l < h->levels; ++l) maxcol = std::max(maxcol, h->lv[l].ncol);
+  const size_t need = solve_workspace_bytes(nmax, maxcol);
+  if (ctx->ws_bytes < need) {
+    if (ctx->ws) {
+      budget_release(ctx, ctx->ws_bytes);
+      (void)hipFree(ctx->ws);
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    budget_reserve(ctx, need);
+    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
+      budget_release(ctx, need);
+      ctx->ws = nullptr;
+      throw Error(FV_E_NOMEM, "workspace allocation failed");
+    }
+    ctx->ws_bytes = need;
+  }
+  Workspace W = carve(ctx->ws, nmax, maxcol);
+  int* pinned = ctx->pinned;
+
+  // Split: levels with at most kSmallLevel vertices go to the one-workgroup
+  // engine; the rest to multi-workgroup passes.
+  int t = J;
+  while (t > 0 && h->lv[t - 1].n <= kSmallLevel) --t;
+
+  int replay_len = 0;
+  if (o->replay) {
+    replay_len = std::min(o->replay_len, FV_SCHEDULE_CAP);
+    FV_HIP(hipMemcpyAsync(W.replay, o->replay, sizeof(int) * replay_len, hipMemcpyHostToDevice, s));
+  }
+  // Output staging for a host x_out: lx, free once the residual is done.
+  double* out_dev = x_on_device ? x_out : W.lx;
+  hipEvent_t e0, e1;
+  FV_HIP(hipEventCreate(&e0));
+  FV_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eg{e0, e1};
+  FV_HIP(hipEventRecord(e0, s));
+
+  GraphTask T;
+  // The engine gets the replay prefix covering its levels.
+  const int eng_len = !o->replay ? 0 : (t == 0 ? replay_len : std::min(replay_len, 1 + 2 * (J - t)));
+  fill_task(T, h, o, t, W.xa, W.xb, W.lx, t == 0 ? out_dev : nullptr, W.st,
+            o->replay ? W.replay : nullptr, eng_len, W.sched, W.sched_len);
+  FV_HIP(hipMemcpyAsync(W.task, &T, sizeof(T), hipMemcpyHostToDevice, s));
+  FV_HIP(hipMemsetAsync(W.queue, 0, sizeof(unsigned), s));
+  FV_HIP(hipMemsetAsync(&W.st->counter, 0, sizeof(unsigned), s));
+  k_engine<VT><<<1, kWG, 0, s>>>(W.task, 1, W.queue);
+  FV_HIP(hipGetLastError());
+
+  std::vector<int> sched;
+  fv_status status = FV_OK;
+  double lam = 0.0, res = 0.0, fcos = 0.0;
+  if (t == 0) {
+    FV_HIP(hipEventRecord(e1, s));
+    int slen = 0;
+    FV_HIP(hipMemcpyAsync(pinned, W.sched_len, sizeof(int), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    slen = std::min(pinned[0], FV_SCHEDULE_CAP);
+    sched.resize(slen);
+    DevState hs;
+    FV_HIP(hipMemcpyAsync(sched.data(), W.sched, sizeof(int) * slen, hipMemcpyDeviceToHost, s));
+    FV_HIP(hipMemcpyAsync(&hs, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    if (!x_on_device)
+      FV_HIP(hipMemcpyAsync(x_out, W.lx, sizeof(double) * h->lv[0].n, hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    lam = hs.lambda;
+    res = hs.res;
+    fcos = hs.cos;
+    if (hs.err) status = FV_E_NOT_CONVERGED;
+  } else {
+    // Engine part of the schedule.
+    FV_HIP(hipMemcpyAsync(pinned, W.sched_len, sizeof(int), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    const int elen = std::min(pinned[0], FV_SCHEDULE_CAP);
+    sched.resize(elen);
+    FV_HIP(hipMemcpyAsync(sched.data(), W.sched, sizeof(int) * elen, hipMemcpyDeviceToHost, s));
+    DevState hs0;
+    FV_HIP(hipMemcpyAsync(&hs0, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    if (hs0.err) status = FV_E_NOT_CONVERGED;
+    int ri = elen;  // replay cursor continues after the engine's entries
+    auto next_forced = [&]() -> int { return (o->replay && ri < replay_len) ? o->replay[ri++] : -1; };
+    // Multi-workgroup levels t-1 .. 0.
+    for (int l = t - 1; l >= 0; --l) {
+      const Level& F = h->lv[l];
+      const LevelDesc L = host_desc(F);
+      if (l == J - 1) {
+        k_prolong<double, VT><<<nblk(F.n), kBlock, 0, s>>>(
+            L, static_cast<const double*>(W.xa), static_cast<const double*>(W.xb),
+            static_cast<VT*>(W.xa), static_cast<VT*>(W.xb), W.st, W.part, W.stride);
+      } else {
+        k_prolong<VT, VT><<<nblk(F.n), kBlock, 0, s>>>(
+            L, static_cast<const VT*>(W.xa), static_cast<const VT*>(W.xb), static_cast<VT*>(W.xa),
+            static_cast<VT*>(W.xb), W.st, W.part, W.stride);
+      }
+      FV_HIP(hipGetLastError());
+      const int g = run_phase_multi<VT>(true, F, L, W, next_forced(), o->max_gs, o->tol_cos,
+                                        o->omega, s, pinned);
+      const int p = run_phase_multi<VT>(false, F, L, W, next_forced(), o->max_pi, o->tol_cos,
+                                        o->omega, s, pinned);
+      sched.push_back(g);
+      sched.push_back(p);
+    }
+    const Level& F0 = h->lv[0];
+    const LevelDesc L0 = host_desc(F0);
+    auto rq_res = [&]() {
+      k_rq<VT><<<nblk(F0.n), kBlock, 0, s>>>(L0, static_cast<const VT*>(W.xa),
+                                             static_cast<const VT*>(W.xb), W.st, W.lx, W.part,
+                                             W.stride);
+      k_residual<VT><<<nblk(F0.n), kBlock, 0, s>>>(L0, static_cast<const VT*>(W.xa),
+                                                   static_cast<const VT*>(W.xb), W.st, W.lx,
+                                                   W.part, W.ipart, W.stride);
+      FV_HIP(hipGetLastError());
+    };
+    rq_res();
+    int outer = 0;
+    for (;;) {
+      int fg, fp;
+      if (o->replay) {
+        if (ri >= replay_len) break;
+        fg = next_forced();
+        fp = next_forced();
+      } else {
+        if (!(o->tol_res > 0.0) || outer >= o->max_outer) break;
+        DevState hs;
+        FV_HIP(hipMemcpyAsync(&hs, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        FV_HIP(hipStreamSynchronize(s));
+        if (hs.res <= o->tol_res) break;
+        fg = fp = -1;
+      }
+      const int g = run_phase_multi<VT>(true, F0, L0, W, fg, o->max_gs, o->tol_cos, o->omega, s,
+                                        pinned);
+      const int p = run_phase_multi<VT>(false, F0, L0, W, fp, o->max_pi, o->tol_cos, o->omega, s,
+                                        pinned);
+      sched.push_back(g);
+      sched.push_back(p);
+      ++outer;
+      rq_res();
+    }
+    k_output<VT><<<nblk(F0.n), kBlock, 0, s>>>(L0, static_cast<const VT*>(W.xa),
+                                               static_cast<const VT*>(W.xb), W.st, out_dev);
+    FV_HIP(hipGetLastError());
+    FV_HIP(hipEventRecord(e1, s));
+    if (!x_on_device)
+      FV_HIP(hipMemcpyAsync(x_out, W.lx, sizeof(double) * F0.n, hipMemcpyDeviceToHost, s));
+    DevState hs;
+    FV_HIP(hipMemcpyAsync(&hs, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
+    lam = hs.lambda;
+    res = hs.res;
+    fcos = hs.cos;
+    if (!o->replay && o->tol_res > 0.0 && res > o->tol_res) status = FV_E_NOT_CONVERGED;
+  }
+  float ms = 0.0f;
+  FV_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (lambda_out) *lambda_out = lam;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->levels = h->levels;
+    for (int l = 0; l < h->levels; ++l) {
+      stats->n[l] = h->lv[l].n;
+      stats->nnz[l] = h->lv[l].m;
+      stats->colours[l] = l == J ? 0 : h->lv[l].ncol;
+    }
+    stats->schedule_len = (int)std::min<size_t>(sched.size(), FV_SCHEDULE_CAP);
+    for (int k = 0; k < stats->schedule_len; ++k) stats->schedule[k] = sched[k];
+    stats->lambda = lam;
+    stats->residual = res;
+    stats->final_cos = fcos;
+    stats->t_solve_ms = ms;
+    stats->alg_bytes = schedule_bytes(h, sched.data(), (int)sched.size(), o->prec);
+  }
+  return status;
+}
+
+fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
+                    double* x_out, int x_on_device, double* lambda_out, fv_solve_stats* stats) {
+  hipStream_t s = o->stream ? static_cast<hipStream_t>(o->stream) : ctx->stream;
+  if (o->prec == FV_PREC_FP32_MIXED)
+    return solve_one_t<float>(ctx, h, o, x_out, x_on_device, lambda_out, stats, s);
+  return solve_one_t<double>(ctx, h, o, x_out, x_on_device, lambda_out, stats, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batch: one persistent launch, one workgroup per graph, largest first.
+// ---------------------------------------------------------------------------
+fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
+                      const fv_solve_opts* o, double* const* x_out, int x_on_device,
+                      double* lambda_out, fv_solve_stats* stats, fv_status* item_status,
+                      hipStream_t s) {
+  if (count <= 0) return FV_OK;
+  // Per-item device memory: xa, xb, lx (8 bytes each per vertex), output,
+  // state and schedule.
+  std::vector<size_t> off(count + 1, 0);
+  for (int k = 0; k < count; ++k) {
+    const size_t n = hierarchy_nmax(hs[k]);
+    off[k + 1] = off[k] + align_up(8 * n) * (x_on_device ? 3 : 4) + align_up(sizeof(DevState)) +
+                 align_up(4 * FV_SCHEDULE_CAP) + align_up(64);
+  }
+  const size_t bytes = off[count] + align_up(sizeof(GraphTask) * count) + 256;
+  budget_reserve(ctx, bytes);
+  char* base = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess) {
+    budget_release(ctx, bytes);
+    throw Error(FV_E_NOMEM, "batch workspace allocation failed");
+  }
+  struct Guard {
+    fv_context* c;
+    void* p;
+    size_t b;
+    ~Guard() {
+      (void)hipFree(p);
+      budget_release(c, b);
+    }
+  } guard{ctx, base, bytes};
+  std::vector<GraphTask> tasks(count);
+  std::vector<int> order(count);
+  std::vector<double*> outs(count);
+  for (int k = 0; k < count; ++k) {
+    char* p = base + off[k];
+    const size_t n = hierarchy_nmax(hs[k]);
+    void* xa = p;
+    void* xb = p + align_up(8 * n);
+    double* lx = reinterpret_cast<double*>(p + 2 * align_up(8 * n));
+    char* q = p + 3 * align_up(8 * n);
+    double* xo = x_on_device ? x_out[k] : reinterpret_cast<double*>(q);
+    if (!x_on_device) q += align_up(8 * n);
+    outs[k] = xo;
+    DevState* st = reinterpret_cast<DevState*>(q);
+    q += align_up(sizeof(DevState));
+    int* sched = reinterpret_cast<int*>(q);
+    q += align_up(4 * FV_SCHEDULE_CAP);
+    int* slen = reinterpret_cast<int*>(q);
+    fill_task(tasks[k], hs[k], o, 0, xa, xb, lx, xo, st, nullptr, 0, sched, slen);
+    long long work = 0;
+    for (int l = 0; l < hs[k]->levels; ++l) work += hs[k]->lv[l].m + hs[k]->lv[l].n;
+    tasks[k].work = work;
+    order[k] = k;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return tasks[a].work > tasks[b].work; });
+  std::vector<GraphTask> sorted(count);
+  for (int k = 0; k < count; ++k) sorted[k] = tasks[order[k]];
+  GraphTask* d_tasks = reinterpret_cast<GraphTask*>(base + off[count]);
+  unsigned* queue = reinterpret_cast<unsigned*>(base + off[count] + align_up(sizeof(GraphTask) * count));
+  FV_HIP(hipMemcpyAsync(d_tasks, sorted.data(), sizeof(GraphTask) * count, hipMemcpyHostToDevice, s));
+  FV_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned), s));
+  int dev = 0, ncu = 256;
+  FV_HIP(hipGetDevice(&dev));
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int grid = std::min(count, std::max(1, ncu * 4));
+  hipEvent_t e0, e1;
+  FV_HIP(hipEventCreate(&e0));
+  FV_HIP(hipEventCreate(&e1));
+  FV_HIP(hipEventRecord(e0, s));
+  if (o->prec == FV_PREC_FP32_MIXED)
+    k_engine<float><<<grid, kWG, 0, s>>>(d_tasks, count, queue);
+  else
+    k_engine<double><<<grid, kWG, 0, s>>>(d_tasks, count, queue);
+  FV_HIP(hipGetLastError());
+  FV_HIP(hipEventRecord(e1, s));
+  std::vector<DevState> hst(count);
+  std::vector<int> hsched(count * (size_t)FV_SCHEDULE_CAP);
+  std::vector<int> hslen(count);
+  for (int k = 0; k < count; ++k) {
+    FV_HIP(hipMemcpyAsync(&hst[k], tasks[k].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipMemcpyAsync(&hslen[k], tasks[k].sched_len, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (stats)
+      FV_HIP(hipMemcpyAsync(&hsched[(size_t)k * FV_SCHEDULE_CAP], tasks[k].sched,
+                            sizeof(int) * FV_SCHEDULE_CAP, hipMemcpyDeviceToHost, s));
+    if (!x_on_device)
+      FV_HIP(hipMemcpyAsync(x_out[k], outs[k], sizeof(double) * hierarchy_nmax(hs[k]),
+                            hipMemcpyDeviceToHost, s));
+  }
+  FV_HIP(hipStreamSynchronize(s));
+  float ms = 0.0f;
+  FV_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int k = 0; k < count; ++k) {
+    if (lambda_out) lambda_out[k] = hst[k].lambda;
+    if (item_status) item_status[k] = hst[k].err ? FV_E_NOT_CONVERGED : FV_OK;
+    if (stats) {
+      fv_solve_stats& S = stats[k];
+      std::memset(&S, 0, sizeof(S));
+      const fv_hierarchy* h = hs[k];
+      S.levels = h->levels;
+      for (int l = 0; l < h->levels; ++l) {
+        S.n[l] = h->lv[l].n;
+        S.nnz[l] = h->lv[l].m;
+        S.colours[l] = l == h->levels - 1 ? 0 : h->lv[l].ncol;
+      }
+      S.schedule_len = std::min(hslen[k], FV_SCHEDULE_CAP);
+      for (int i = 0; i < S.schedule_len; ++i) S.schedule[i] = hsched[(size_t)k * FV_SCHEDULE_CAP + i];
+      S.lambda = hst[k].lambda;
+      S.residual = hst[k].res;
+      S.final_cos = hst[k].cos;
+      S.t_solve_ms = ms;  // the whole launch
+      S.alg_bytes = schedule_bytes(h, S.schedule, S.schedule_len, o->prec);
+    }
+  }
+  return FV_OK;
+}
+
+}  // namespace fv

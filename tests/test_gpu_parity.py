@@ -1,0 +1,247 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Bars:
+* integer and structural results (matching, aggregates, colouring, coarse
+  graphs, shifts) are bit-exact, coarse weights included;
+* FP64: lambda within 1e-10 relative and 1 - |cos(x_gpu, x_oracle)| <= 1e-10
+  when the GPU runs the oracle's schedule (replay);
+* FP32-mixed: lambda within 1e-5 relative of the FP64 oracle;
+* free-running schedules equal the oracle's on these inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "c1_grid32x24": (lambda: gen.grid_32x24(), 8),
+    "path64": (lambda: gen.path(64), 8),
+    "path2": (lambda: gen.path(2), 8),
+    "rand200": (lambda: gen.random_connected(200, 7), 8),
+    "grid64x48u": (lambda: gen.grid(64, 48, "uniform", seed=3), 25),
+    "er3000": (lambda: gen.erdos_renyi(3000, 6 / 2999, 11), 25),
+    "rgg20k": (lambda: gen.rgg(20000, 5), 25),
+    "grid256x250u": (lambda: gen.grid(256, 250, "uniform", seed=2), 25),
+}
+_graphs = {}
+
+
+def graph(name):
+    if name not in _graphs:
+        f, nc = CASES[name]
+        _graphs[name] = (f(), nc)
+    return _graphs[name]
+
+
+def compare_structure(h, oh):
+    assert h.levels == oh.nlevels
+    for l in range(h.levels):
+        a, b = h.export_level(l), oh.level(l)
+        assert (a.n, a.m) == (b.n, b.m), l
+        assert np.array_equal(a.rowptr, b.rowptr) and np.array_equal(a.col, b.col), l
+        assert a.w.tobytes() == b.w.tobytes(), l
+        assert a.sigma == b.sigma, l
+        if l + 1 < h.levels:
+            assert np.array_equal(a.q, b.q), l
+            assert np.array_equal(a.colour, b.colour) and a.ncolours == b.ncolours, l
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structure_bit_exact(fv, ctx, orc, name):
+    g, nc = graph(name)
+    print(f"case {name} n={g.n}", flush=True)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    compare_structure(h, oh)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_replay_parity(fv, ctx, orc, name, prec):
+    g, nc = graph(name)
+    print(f"case {name} {prec}", flush=True)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    ro = oh.solve(seed=1)
+    r = fv.fiedler_solve(ctx, h, prec=prec, seed=1, replay=ro.counts)
+    assert r.schedule == ro.counts
+    rel = abs(r.lam - ro.lam) / abs(ro.lam)
+    if prec == "fp64":
+        assert rel <= 1e-10
+        assert 1 - abs(float(r.x @ ro.x)) <= 1e-10
+        assert abs(r.residual - ro.residual) <= 1e-9 * max(ro.residual, 1e-12) + 1e-14
+    else:
+        assert rel <= 1e-5
+    assert abs(np.linalg.norm(r.x) - 1) < 1e-12 and abs(r.x.sum()) < 1e-9 * math.sqrt(g.n)
+
+
+@pytest.mark.parametrize("name", ["c1_grid32x24", "grid64x48u", "rgg20k", "grid256x250u"])
+def test_free_run_schedule(fv, ctx, orc, name):
+    g, nc = graph(name)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    ro = oh.solve(seed=1)
+    r = fv.fiedler_solve(ctx, h, prec="fp64", seed=1)
+    assert r.schedule == ro.counts
+    assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+
+
+def test_c1_closed_form_tight(fv, ctx):
+    """32x24 unit grid: lambda_2 = 2 - 2 cos(pi/32) (the small FP64 workload)."""
+    g = gen.grid_32x24()
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=8)
+    r = fv.fiedler_solve(ctx, h, prec="fp64", tol_cos=1e-10, tol_res=1e-9, max_gs=2000,
+                         max_pi=50, max_outer=5000)
+    lam = 2 - 2 * math.cos(math.pi / 32)
+    assert r.status == 0 and r.residual <= 1e-9
+    assert abs(r.lam - lam) <= 1e-10 * lam
+    phi = np.repeat(np.cos(math.pi * (np.arange(32) + 0.5) / 32), 24)
+    phi /= np.linalg.norm(phi)
+    assert 1 - abs(float(r.x @ phi)) <= 1e-8
+
+
+def test_tol_res_loop_matches_oracle(fv, ctx, orc):
+    g, nc = graph("grid64x48u")
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    kw = dict(seed=1, tol_cos=1e-12, tol_res=1e-6, max_gs=2000, max_pi=2, max_outer=400,
+              omega=1.8)
+    ro = oh.solve(**kw)
+    r = fv.fiedler_solve(ctx, h, prec="fp64", replay=ro.counts, **kw)
+    assert r.residual <= 1.01e-6 and ro.residual <= 1e-6
+    assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+    rf = fv.fiedler_solve(ctx, h, prec="fp32", **kw)
+    assert abs(rf.lam - ro.lam) <= 1e-5 * ro.lam
+
+
+def test_sor_relaxation_replay(fv, ctx, orc):
+    g, nc = graph("grid64x48u")
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    ro = oh.solve(seed=1, omega=1.7, tol_cos=1e-10, max_gs=300)
+    r = fv.fiedler_solve(ctx, h, prec="fp64", seed=1, omega=1.7, replay=ro.counts)
+    assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+
+
+def test_laplacian_and_device_inputs(fv, ctx):
+    from paper_1602_04386_amd.devmem import DeviceArray
+
+    g = gen.grid(40, 33, "uniform", seed=8)
+    h1 = fv.build_hierarchy_graph(ctx, g, n_coarse=10)
+    rp, col, val = g.laplacian()
+    h2 = fv.build_hierarchy(ctx, g.n, rp, col, val, is_adjacency=False, n_coarse=10)
+    h3 = fv.build_hierarchy(ctx, g.n, DeviceArray(g.rowptr), DeviceArray(g.col),
+                            DeviceArray(g.w), is_adjacency=True, n_coarse=10)
+    for h in (h2, h3):
+        assert h.levels == h1.levels
+        for l in range(h.levels):
+            a, b = h.export_level(l), h1.export_level(l)
+            assert np.array_equal(a.col, b.col) and a.w.tobytes() == b.w.tobytes()
+    r1 = fv.fiedler_solve(ctx, h1)
+    xd = DeviceArray(dtype=np.float64, count=g.n)
+    fv.fiedler_solve(ctx, h3, x_out=xd)
+    assert np.array_equal(r1.x, xd.numpy())
+
+
+def test_repeatable_bitwise(fv, ctx):
+    g, nc = graph("grid256x250u")
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    a = fv.fiedler_solve(ctx, h, prec="fp32")
+    b = fv.fiedler_solve(ctx, h, prec="fp32")
+    assert np.array_equal(a.x, b.x) and a.lam == b.lam and a.schedule == b.schedule
+
+
+def _bad_inputs():
+    g = gen.random_connected(12, 3)
+    rp, col, w = g.rowptr.copy(), g.col.copy(), g.w.copy()
+    w2 = w.copy()
+    w2[0] += 1e-3
+    w3 = w.copy()
+    w3[1] = -w3[1]
+    c2 = col.copy()
+    c2[rp[0]], c2[rp[0] + 1] = c2[rp[0] + 1], c2[rp[0]]
+    c3 = col.copy()
+    c3[-1] = g.n
+    return [
+        ("asym", g.n, rp, col, w2, True),
+        ("negative", g.n, rp, col, w3, True),
+        ("unsorted", g.n, rp, c2, w, True),
+        ("col_range", g.n, rp, c3, w, True),
+        ("isolated", 3, np.array([0, 1, 2, 2], np.int32), np.array([1, 0], np.int32),
+         np.array([1.0, 1.0]), True),
+    ]
+
+
+@pytest.mark.parametrize("case", _bad_inputs(), ids=lambda c: c[0])
+def test_input_errors_match_oracle(fv, ctx, orc, case):
+    name, n, rp, col, w, adj = case
+    expect = orc.input_to_adjacency(n, rp, col, w, adj)[0]
+    with pytest.raises(fv.FiedlerError) as e:
+        fv.build_hierarchy(ctx, n, rp, col, w, is_adjacency=adj)
+    assert e.value.status == expect
+
+
+def test_degenerate_graphs(fv, ctx, orc):
+    # star: every leaf joins the centre's aggregate -> one level, big coarsest
+    k = 100
+    a = np.zeros(k, np.int64)
+    b = np.arange(1, k + 1)
+    g = gen._csr_from_undirected(k + 1, a, b, np.ones(k))
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=8)
+    assert h.levels == 1
+    r = fv.fiedler_solve(ctx, h)
+    assert abs(r.lam - 1.0) < 1e-9 and r.residual < 1e-9
+    # two components (no isolated vertex): lambda_2 = 0
+    a = np.array([0, 2])
+    b = np.array([1, 3])
+    g2 = gen._csr_from_undirected(4, a, b, np.ones(2))
+    h2 = fv.build_hierarchy_graph(ctx, g2, n_coarse=8)
+    r2 = fv.fiedler_solve(ctx, h2)
+    assert abs(r2.lam) < 1e-12
+
+
+def test_batch_matches_oracle_and_is_mix_independent(fv, ctx, orc):
+    gs = [gen.grid(30 + k, 20, "uniform", seed=k) for k in range(3)] + \
+         [gen.random_connected(300, 50 + k) for k in range(3)] + [gen.path(64), gen.grid_32x24()]
+    hs = [fv.build_hierarchy_graph(ctx, g, n_coarse=8) for g in gs]
+    res = fv.fiedler_solve_batch(ctx, hs, prec="fp64")
+    for g, r in zip(gs, res):
+        ro = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=8).solve(seed=1)
+        assert r.schedule == ro.counts
+        assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+        assert 1 - abs(float(r.x @ ro.x)) <= 1e-10
+    alone = fv.fiedler_solve_batch(ctx, [hs[4]], prec="fp64")[0]
+    assert np.array_equal(alone.x, res[4].x) and alone.lam == res[4].lam
+
+
+def test_server_results_equal_batch(fv, ctx):
+    import time
+
+    gs = [gen.grid(20 + k, 15, "uniform", seed=k) for k in range(6)]
+    srv = fv.Server(ctx, max_inflight=4, n_coarse=8, prec="fp32")
+    tickets = [srv.submit(k, g) for k, g in enumerate(gs)]
+    tickets += [srv.submit(0, gs[0])]  # second request for a cached graph
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 60:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.001)
+    srv.close()
+    assert len(out) == len(tickets)
+    hs = [fv.build_hierarchy_graph(ctx, g, n_coarse=8) for g in gs]
+    ref = fv.fiedler_solve_batch(ctx, hs, prec="fp32")
+    for k, t in enumerate(tickets):
+        info, x = out[t]
+        gi = k if k < len(gs) else 0
+        assert info["status"] == 0
+        assert np.array_equal(x, ref[gi].x)
+    assert out[tickets[-1]][0]["cache_hit"]
