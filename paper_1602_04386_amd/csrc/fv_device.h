@@ -67,10 +67,34 @@ __device__ inline int xcd_block(int b, int nb) {
 
 // ---- deterministic reductions (fixed order; lane 0 / wave order) ----
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// DPP move of a double (both 32-bit halves) with a constant control word.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over a full wave of 64 lanes, the same value in every lane.  Butterfly
+// inside each row of 16 lanes with DPP (quad permutes, half-row and row
+// mirrors: each step adds a lane to its partner, so partners stay equal), then
+// the four row sums are read out and added in a fixed order.  Every lane must
+// be active.
+__device__ inline double row_sum16(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
   return v;
+}
+
+__device__ inline double wave_sum(double v) {
+  v = row_sum16(v);
+  auto lane_val = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  return (lane_val(0) + lane_val(16)) + (lane_val(32) + lane_val(48));
 }
 
 __device__ inline long long wave_sum_ll(long long v) {
@@ -79,23 +103,35 @@ __device__ inline long long wave_sum_ll(long long v) {
   return v;
 }
 
+// Doubles of LDS that block_sum<kNP> needs for a block of `threads`.
+__host__ __device__ constexpr int block_sum_lds(int threads) { return (4 * (threads / 64) + 1) * kNP; }
+
 // Sum of NP values over the block; every thread receives the same totals.
-// lds must hold (blockDim/64) * NP doubles.
+// Each wave sums its rows of 16 lanes with DPP and stores the 4 row sums;
+// wave 0 sums those (at most 64, one per lane) and publishes the totals.  The
+// order is fixed, so the result is reproducible.  lds must hold
+// (4 * blockDim/64 + 1) * NP doubles; every thread must call.
 template <int NP>
 __device__ inline void block_sum(double (&v)[NP], double* lds) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0)
+  for (int k = 0; k < NP; ++k) v[k] = row_sum16(v[k]);
+  if ((lane & 15) == 0)
 #pragma unroll
-    for (int k = 0; k < NP; ++k) lds[wid * NP + k] = v[k];
+    for (int k = 0; k < NP; ++k) lds[(wid * 4 + (lane >> 4)) * NP + k] = v[k];
+  __syncthreads();
+  const int nr = nw * 4;
+  if (wid == 0) {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      double t = lane < nr ? lds[lane * NP + k] : 0.0;
+      t = wave_sum(t);
+      if (lane == 0) lds[nr * NP + k] = t;
+    }
+  }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += lds[w * NP + k];
-    v[k] = t;
-  }
+  for (int k = 0; k < NP; ++k) v[k] = lds[nr * NP + k];
   __syncthreads();
 }
 

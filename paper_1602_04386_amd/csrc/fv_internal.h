@@ -36,13 +36,13 @@ struct Error : std::runtime_error {
 // Launch geometry.
 // ---------------------------------------------------------------------------
 constexpr int kBlock = 256;    // threads per block of the multi-workgroup row passes
-constexpr int kWG = 512;       // threads of the one-workgroup-per-graph engine
+constexpr int kWGSolo = 1024;  // engine threads for the small levels of one graph
+constexpr int kWGBatch = 512;  // engine threads per graph of a batch
+constexpr size_t kSoloLds = 144 * 1024;  // engine LDS for one graph's level vector
+constexpr size_t kBatchLds = 64 * 1024;  // per graph of a batch
 constexpr int kNP = 5;         // FP64 partial sums carried by a refinement pass
 constexpr int kXCD = 8;        // accelerator complex dies on MI355X
 
-// Levels with at most this many vertices are refined by the one-workgroup
-// engine; larger levels by multi-workgroup passes.
-constexpr int kSmallLevel = 16384;
 
 // ---------------------------------------------------------------------------
 // Device-resident solve state of one graph (scalars of the current phase).

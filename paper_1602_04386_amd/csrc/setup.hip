@@ -391,9 +391,20 @@ __global__ void k_colour_round(int n, const int* rp, const int* col, uint32_t se
   }
 }
 
-__global__ void k_count_colours(int n, const int* colour, int* cnt) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicAdd(&cnt[colour[v]], 1);
+// Colour histogram: per-block counts in LDS, one global add per colour.
+__global__ __launch_bounds__(kBlock) void k_count_colours(int n, const int* colour, int ncol,
+                                                        int* cnt) {
+  __shared__ int hist[kBlock];
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ncol > kBlock) {
+    if (v < n) atomicAdd(&cnt[colour[v]], 1);
+    return;
+  }
+  if (threadIdx.x < ncol) hist[threadIdx.x] = 0;
+  __syncthreads();
+  if (v < n) atomicAdd(&hist[colour[v]], 1);
+  __syncthreads();
+  if (threadIdx.x < ncol && hist[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], hist[threadIdx.x]);
 }
 
 __global__ void k_perm_fill(int n, const int* colour, int c, int start, const int* pos, int* perm,
@@ -811,7 +822,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         k_iota<<<nblk(fn), kBlock, 0, s>>>(F.iperm, fn);
       } else {
         FV_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (F.ncol + 1), s));
-        k_count_colours<<<nblk(fn), kBlock, 0, s>>>(fn, F.colour_c, cnt);
+        k_count_colours<<<nblk(fn), kBlock, 0, s>>>(fn, F.colour_c, F.ncol, cnt);
         std::vector<int> ch(F.ncol);
         FV_HIP(hipMemcpyAsync(ch.data(), cnt, sizeof(int) * F.ncol, hipMemcpyDeviceToHost, s));
         FV_HIP(hipStreamSynchronize(s));

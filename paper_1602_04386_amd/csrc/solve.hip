@@ -20,6 +20,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 
 #include "fv_device.h"
 #include "fv_internal.h"
@@ -183,229 +184,17 @@ __device__ inline Scal after_prolong(const double (&S)[kNP], int n) {
   return r;
 }
 
-// ---------------------------------------------------------------------------
-// Multi-workgroup passes.
-// ---------------------------------------------------------------------------
-__global__ void k_phase_begin(DevState* st, int cap, int forced, double tol) {
-  st->done = cap <= 0 ? 1 : 0;
-  st->iters = 0;
-  st->cap = cap;
-  st->forced = forced;
-  st->tol = tol;
-}
-
-// Final reduction of nslots partial slots (layout part[k * stride + slot]).
-__device__ inline void reduce_slots(const double* part, int stride, int nslots,
-                                    double (&S)[kNP], double* lds) {
-#pragma unroll
-  for (int k = 0; k < kNP; ++k) S[k] = 0.0;
-  for (int s = threadIdx.x; s < nslots; s += blockDim.x)
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + s];
-  block_sum<kNP>(S, lds);
-}
-
-__device__ inline void write_slot(double* part, int stride, int slot, const double (&S)[kNP]) {
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) part[k * stride + slot] = S[k];
-}
-
-template <class VT>
-__global__ __launch_bounds__(kBlock) void k_gs_colour(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
-                                                    DevState* st, double* part, int stride,
-                                                    int slot_base, int last, int nslots,
-                                                    double omega) {
-  __shared__ double lds[(kBlock / 64) * kNP];
-  __shared__ int flag;
-  if (st->done) return;
-  VT* x = st->cur ? xb : xa;
-  const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = r0 + b * kBlock + threadIdx.x;
-  if (i < r1) row_gs<VT>(i, L, x, r0, mu, inv_s, rho, omega, acc);
-  block_sum<kNP>(acc, lds);
-  write_slot(part, stride, slot_base + blockIdx.x, acc);
-  if (!last) return;
-  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
-  double S[kNP];
-  reduce_slots(part, stride, nslots, S, lds);
-  if (threadIdx.x == 0) {
-    Scal r = after_gs(S, L.n);
-    st->mu = r.mu;
-    st->inv_s = r.inv_s;
-    st->cos = r.cos;
-    st->rho = r.rho;
-    int it = st->iters + 1;
-    st->iters = it;
-    st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
-    st->counter = 0;
-  }
-}
-
-template <class VT>
-__global__ __launch_bounds__(kBlock) void k_pi_step(LevelDesc L, VT* xa, VT* xb, DevState* st,
-                                                  double* part, int stride) {
-  __shared__ double lds[(kBlock / 64) * kNP];
-  __shared__ int flag;
-  if (st->done) return;
-  const int cur = st->cur;
-  const VT* x = cur ? xb : xa;
-  VT* y = cur ? xa : xb;
-  const double mu = st->mu, inv_s = st->inv_s;
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * kBlock + threadIdx.x;
-  if (i < L.n) row_pi<VT>(i, L, x, y, mu, inv_s, L.sigma, acc);
-  block_sum<kNP>(acc, lds);
-  write_slot(part, stride, blockIdx.x, acc);
-  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
-  double S[kNP];
-  reduce_slots(part, stride, gridDim.x, S, lds);
-  if (threadIdx.x == 0) {
-    Scal r = after_gs(S, L.n);  // same formulas; rho unused
-    st->mu = r.mu;
-    st->inv_s = r.inv_s;
-    st->cos = r.cos;
-    st->cur = 1 - cur;
-    int it = st->iters + 1;
-    st->iters = it;
-    st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
-    st->counter = 0;
-  }
-}
-
-template <class SRC, class VT>
-__global__ __launch_bounds__(kBlock) void k_prolong(LevelDesc L, const SRC* xc_a,
-                                                  const SRC* xc_b, VT* xf_a, VT* xf_b,
-                                                  DevState* st, double* part, int stride) {
-  __shared__ double lds[(kBlock / 64) * kNP];
-  __shared__ int flag;
-  const int cur = st->cur;
-  const SRC* xc = cur ? xc_b : xc_a;
-  VT* xf = cur ? xf_a : xf_b;
-  const double mu = st->mu, inv_s = st->inv_s;
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * kBlock + threadIdx.x;
-  if (i < L.n) row_prolong<SRC, VT>(i, L, xc, xf, mu, inv_s, acc);
-  block_sum<kNP>(acc, lds);
-  write_slot(part, stride, blockIdx.x, acc);
-  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
-  double S[kNP];
-  reduce_slots(part, stride, gridDim.x, S, lds);
-  if (threadIdx.x == 0) {
-    Scal r = after_prolong(S, L.n);
-    st->mu = r.mu;
-    st->inv_s = r.inv_s;
-    st->rho = r.rho;
-    st->cur = 1 - cur;
-    st->counter = 0;
-  }
-}
-
-// Rayleigh quotient lambda = xhat^T L xhat / xhat^T xhat (FP64 weights).
-template <class VT>
-__global__ __launch_bounds__(kBlock) void k_rq(LevelDesc L, const VT* xa, const VT* xb,
-                                             DevState* st, double* lx, double* part,
-                                             int stride) {
-  __shared__ double lds[(kBlock / 64) * kNP];
-  __shared__ int flag;
-  const VT* x = st->cur ? xb : xa;
-  const double mu = st->mu, inv_s = st->inv_s;
-  double acc3[3] = {0.0, 0.0, 0.0};
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * kBlock + threadIdx.x;
-  if (i < L.n) row_rq<VT>(i, L, x, mu, inv_s, lx, acc3);
-  const double mx = block_max(acc3[2], lds);
-  double acc[kNP] = {acc3[0], acc3[1], mx, 0.0, 0.0};
-  double t2[2] = {acc[0], acc[1]};
-  block_sum<2>(t2, lds);
-  acc[0] = t2[0];
-  acc[1] = t2[1];
-  write_slot(part, stride, blockIdx.x, acc);
-  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
-  double s0 = 0.0, s1 = 0.0, m = 0.0;
-  for (int s = threadIdx.x; s < (int)gridDim.x; s += blockDim.x) {
-    s0 += part[s];
-    s1 += part[stride + s];
-    m = fmax(m, part[2 * stride + s]);
-  }
-  double t[2] = {s0, s1};
-  block_sum<2>(t, lds);
-  m = block_max(m, lds);
-  if (threadIdx.x == 0) {
-    st->sumsq = t[0];
-    st->lambda = t[1] / t[0];
-    st->xmax = m;
-    st->rho = st->lambda;
-    st->counter = 0;
-  }
-}
-
-// Residual ||L xhat - lambda xhat|| / ||xhat|| and the first original index
-// with |xhat_i| >= 1e-3 max|xhat| (output sign).
-template <class VT>
-__global__ __launch_bounds__(kBlock) void k_residual(LevelDesc L, const VT* xa, const VT* xb,
-                                                   DevState* st, const double* lx,
-                                                   double* part, int* ipart, int stride) {
-  __shared__ double lds[(kBlock / 64) * kNP];
-  __shared__ int ilds[kBlock / 64];
-  __shared__ int flag;
-  const VT* x = st->cur ? xb : xa;
-  const double mu = st->mu, inv_s = st->inv_s, lam = st->lambda, thr = 1e-3 * st->xmax;
-  double r2 = 0.0;
-  int cand = INT_MAX;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int i = b * kBlock + threadIdx.x;
-  if (i < L.n) {
-    const double xh = ((double)x[i] - mu) * inv_s;
-    const double r = lx[i] - lam * xh;
-    r2 = r * r;
-    if (fabs(xh) >= thr) cand = L.iperm[i];
-  }
-  double t[1] = {r2};
-  block_sum<1>(t, lds);
-  cand = block_min_int(cand, ilds);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = t[0];
-    ipart[blockIdx.x] = cand;
-  }
-  if (!arrive_last(&st->counter, gridDim.x, &flag)) return;
-  double s = 0.0;
-  int c = INT_MAX;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
-    s += part[k];
-    c = min(c, ipart[k]);
-  }
-  double tt[1] = {s};
-  block_sum<1>(tt, lds);
-  c = block_min_int(c, ilds);
-  if (threadIdx.x == 0) {
-    st->res = sqrt(tt[0] / st->sumsq);
-    st->sign_idx = c;
-    double xv = c < INT_MAX ? ((double)x[L.perm[c]] - mu) * inv_s : 1.0;
-    st->sign = xv < 0.0 ? -1.0 : 1.0;
-    st->counter = 0;
-  }
-}
-
-template <class VT>
-__global__ void k_output(LevelDesc L, const VT* xa, const VT* xb, const DevState* st,
-                         double* out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= L.n) return;
-  const VT* x = st->cur ? xb : xa;
-  out[v] = st->sign * (((double)x[L.perm[v]] - st->mu) * st->inv_s);
-}
+#include "passes.h"
 
 // ---------------------------------------------------------------------------
 // One-workgroup engine.
 // ---------------------------------------------------------------------------
 struct EngineCtx {
-  double* lds;  // (kWG / 64) * kNP doubles
+  double* lds;  // (threads / 64) * kNP doubles
   int* ilds;
+  void* xl;     // dynamic LDS: one level vector, then optionally its CSR
+  int cap;      // capacity in vector entries
+  int bytes;    // size in bytes
 };
 
 // Coarsest solve in FP64 (Algorithm 3, Step 2): power iteration on
@@ -630,137 +419,24 @@ __device__ void engine_rq_residual(const LevelDesc& L, const VT* x, const Scal& 
   sign = xv < 0.0 ? -1.0 : 1.0;
 }
 
-template <class VT>
-__device__ void engine_run(const GraphTask& T, EngineCtx& E) {
-  const LevelDesc* lv = T.lv;
-  const int J = T.J;
-  int si = 0;  // replay cursor
-  auto next_forced = [&]() -> int { return (T.replay && si < T.replay_len) ? T.replay[si++] : -1; };
-  int slen = 0;
-  auto push = [&](int v) {
-    if (threadIdx.x == 0 && slen < FV_SCHEDULE_CAP) T.sched[slen] = v;
-    ++slen;
-  };
-  double* xa64 = static_cast<double*>(T.xa);
-  VT* xa = static_cast<VT*>(T.xa);
-  VT* xb = static_cast<VT*>(T.xb);
-  int conv = 0;
-  const int cit = engine_coarsest(lv[J], T.seed, T.max_coarsest, next_forced(), xa64, T.lx, &conv, E);
-  push(cit);
-  __syncthreads();
-  int cur = 0;
-  Scal s{0.0, 1.0, 1.0, 0.0};
-  bool coarse64 = true;
-  for (int l = J - 1; l >= T.stop; --l) {
-    const LevelDesc& L = lv[l];
-    if (coarse64) {
-      s = engine_prolong<double, VT>(L, xa64, xb, s, E);
-      coarse64 = false;
-    } else {
-      s = engine_prolong<VT, VT>(L, cur ? xb : xa, cur ? xa : xb, s, E);
-    }
-    cur = 1 - cur;
-    PhaseCfg pg{next_forced(), T.max_gs, T.tol_cos};
-    const int g = engine_gs_phase<VT>(L, cur ? xb : xa, s, T.omega, pg, E);
-    PhaseCfg pp{next_forced(), T.max_pi, T.tol_cos};
-    const int p = engine_pi_phase<VT>(L, xa, xb, cur, s, pp, E);
-    push(g);
-    push(p);
-    __syncthreads();
-  }
-  if (coarse64 && J == 0) {
-    // One-level hierarchy: the coarsest iterate is the answer; store it in the
-    // working precision of the finest level.
-    double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < lv[0].n; i += blockDim.x) {
-      const VT v = (VT)xa64[i];
-      xb[i] = v;
-      acc[0] += (double)v;
-      acc[1] += (double)v * (double)v;
-    }
-    __syncthreads();
-    block_sum<kNP>(acc, E.lds);
-    cur = 1;
-    s = after_prolong(acc, lv[0].n);
-  }
-  if (!T.finalize) {
-    if (threadIdx.x == 0) {
-      T.st->mu = s.mu;
-      T.st->inv_s = s.inv_s;
-      T.st->rho = s.rho;
-      T.st->cos = s.cos;
-      T.st->cur = cur;
-      T.st->err = conv ? 0 : 1;
-      *T.sched_len = slen;
-    }
-    return;
-  }
-  const LevelDesc& L0 = lv[0];
-  double lam = 0.0, res = 0.0, sign = 1.0;
-  engine_rq_residual<VT>(L0, cur ? xb : xa, s, T.lx, lam, res, sign, E);
-  int outer = 0;
-  if (J > 0) {
-    for (;;) {
-      int fg, fp;
-      if (T.replay) {
-        if (si >= T.replay_len) break;
-        fg = next_forced();
-        fp = next_forced();
-      } else {
-        if (!(T.tol_res > 0.0) || res <= T.tol_res || outer >= T.max_outer) break;
-        fg = fp = -1;
-      }
-      s.rho = lam;
-      PhaseCfg pg{fg, T.max_gs, T.tol_cos};
-      const int g = engine_gs_phase<VT>(L0, cur ? xb : xa, s, T.omega, pg, E);
-      PhaseCfg pp{fp, T.max_pi, T.tol_cos};
-      const int p = engine_pi_phase<VT>(L0, xa, xb, cur, s, pp, E);
-      push(g);
-      push(p);
-      ++outer;
-      __syncthreads();
-      engine_rq_residual<VT>(L0, cur ? xb : xa, s, T.lx, lam, res, sign, E);
-    }
-  }
-  const VT* x = cur ? xb : xa;
-  for (int v = threadIdx.x; v < L0.n; v += blockDim.x)
-    T.x_out[v] = sign * (((double)x[L0.perm[v]] - s.mu) * s.inv_s);
-  if (threadIdx.x == 0) {
-    T.st->lambda = lam;
-    T.st->res = res;
-    T.st->cos = s.cos;
-    T.st->mu = s.mu;
-    T.st->inv_s = s.inv_s;
-    T.st->cur = cur;
-    bool nc = !conv || (!T.replay && T.tol_res > 0.0 && res > T.tol_res);
-    T.st->err = nc ? 1 : 0;
-    *T.sched_len = slen;
-  }
-}
-
-template <class VT>
-__global__ __launch_bounds__(kWG) void k_engine(const GraphTask* tasks, int ntasks,
-                                              unsigned* queue) {
-  __shared__ double lds[(kWG / 64) * kNP];
-  __shared__ int ilds[kWG / 64];
-  __shared__ int s_task;
-  EngineCtx E{lds, ilds};
-  for (;;) {
-    if (threadIdx.x == 0) s_task = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    const int t = s_task;
-    __syncthreads();
-    if (t >= ntasks) break;
-    engine_run<VT>(tasks[t], E);
-    __syncthreads();
-  }
-}
+#include "engine.h"
 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 static inline int nblk(long long n, int b = kBlock) {
   return (int)std::max<long long>(1, (n + b - 1) / b);
+}
+
+// Allows an engine instantiation the dynamic LDS it is launched with (more
+// than the 64 KiB default); done once per instantiation and process.
+template <class VT, int NT>
+static void enable_engine_lds(size_t bytes) {
+  static std::once_flag once;
+  std::call_once(once, [&] {
+    FV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_engine<VT, NT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  });
 }
 
 struct Workspace {
@@ -842,13 +518,15 @@ static int run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const W
       if (gs) {
         int base = 0;
         for (int c = 0; c < L.ncol; ++c) {
-          k_gs_colour<VT><<<nbs[c], kBlock, 0, s>>>(L, Lh.cptr_h[c], Lh.cptr_h[c + 1], xa, xb,
-                                                    W.st, W.part, W.stride, base,
-                                                    c == L.ncol - 1 ? 1 : 0, nslots, omega);
+          k_gs_tile<VT><<<nbs[c], kBlock, 0, s>>>(L, Lh.cptr_h[c], Lh.cptr_h[c + 1], xa, xb,
+                                                  W.st, W.part, W.stride, base, omega);
           base += nbs[c];
         }
+        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS);
       } else {
-        k_pi_step<VT><<<nblk(L.n), kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
+        const int nb = nblk(L.n);
+        k_pi_tile<VT><<<nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
+        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, L.n, kFinPI);
       }
     }
     FV_HIP(hipGetLastError());
@@ -959,10 +637,16 @@ static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_so
   Workspace W = carve(ctx->ws, nmax, maxcol);
   int* pinned = ctx->pinned;
 
-  // Split: levels with at most kSmallLevel vertices go to the one-workgroup
+  // Split: levels whose vector fits the engine's LDS go to the one-workgroup
   // engine; the rest to multi-workgroup passes.
+  const int lds_cap = (int)(kSoloLds / sizeof(VT));
+  static const int engine_max = [] {
+    const char* e = std::getenv("FV_ENGINE_MAX_N");
+    return e ? std::atoi(e) : 8192;
+  }();
+  const int split = std::min(lds_cap, engine_max);
   int t = J;
-  while (t > 0 && h->lv[t - 1].n <= kSmallLevel) --t;
+  while (t > 0 && h->lv[t - 1].n <= split) --t;
 
   int replay_len = 0;
   if (o->replay) {
@@ -991,7 +675,8 @@ static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_so
   FV_HIP(hipMemcpyAsync(W.task, &T, sizeof(T), hipMemcpyHostToDevice, s));
   FV_HIP(hipMemsetAsync(W.queue, 0, sizeof(unsigned), s));
   FV_HIP(hipMemsetAsync(&W.st->counter, 0, sizeof(unsigned), s));
-  k_engine<VT><<<1, kWG, 0, s>>>(W.task, 1, W.queue);
+  enable_engine_lds<VT, kWGSolo>(kSoloLds);
+  k_engine<VT, kWGSolo><<<1, kWGSolo, kSoloLds, s>>>(W.task, 1, W.queue, lds_cap);
   FV_HIP(hipGetLastError());
 
   std::vector<int> sched;
@@ -1031,15 +716,17 @@ static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_so
     for (int l = t - 1; l >= 0; --l) {
       const Level& F = h->lv[l];
       const LevelDesc L = host_desc(F);
+      const int nb = nblk(F.n);
       if (l == J - 1) {
-        k_prolong<double, VT><<<nblk(F.n), kBlock, 0, s>>>(
+        k_prolong_tile<double, VT><<<nb, kBlock, 0, s>>>(
             L, static_cast<const double*>(W.xa), static_cast<const double*>(W.xb),
             static_cast<VT*>(W.xa), static_cast<VT*>(W.xb), W.st, W.part, W.stride);
       } else {
-        k_prolong<VT, VT><<<nblk(F.n), kBlock, 0, s>>>(
+        k_prolong_tile<VT, VT><<<nb, kBlock, 0, s>>>(
             L, static_cast<const VT*>(W.xa), static_cast<const VT*>(W.xb), static_cast<VT*>(W.xa),
             static_cast<VT*>(W.xb), W.st, W.part, W.stride);
       }
+      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F.n, kFinProlong);
       FV_HIP(hipGetLastError());
       const int g = run_phase_multi<VT>(true, F, L, W, next_forced(), o->max_gs, o->tol_cos,
                                         o->omega, s, pinned);
@@ -1051,12 +738,13 @@ static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_so
     const Level& F0 = h->lv[0];
     const LevelDesc L0 = host_desc(F0);
     auto rq_res = [&]() {
-      k_rq<VT><<<nblk(F0.n), kBlock, 0, s>>>(L0, static_cast<const VT*>(W.xa),
-                                             static_cast<const VT*>(W.xb), W.st, W.lx, W.part,
-                                             W.stride);
-      k_residual<VT><<<nblk(F0.n), kBlock, 0, s>>>(L0, static_cast<const VT*>(W.xa),
-                                                   static_cast<const VT*>(W.xb), W.st, W.lx,
-                                                   W.part, W.ipart, W.stride);
+      const int nb = nblk(F0.n);
+      const VT* xa = static_cast<const VT*>(W.xa);
+      const VT* xb = static_cast<const VT*>(W.xb);
+      k_rq_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.stride);
+      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F0.n, kFinRQ);
+      k_res_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.ipart);
+      k_finish_res<VT><<<1, kBlock, 0, s>>>(L0, xa, xb, W.st, W.part, W.ipart, nb);
       FV_HIP(hipGetLastError());
     };
     rq_res();
@@ -1195,15 +883,22 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
   int dev = 0, ncu = 256;
   FV_HIP(hipGetDevice(&dev));
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int grid = std::min(count, std::max(1, ncu * 4));
+  // Two 512-thread workgroups per CU (register-limited), each with its own
+  // slice of LDS for the level vector.
+  const int grid = std::min(count, std::max(1, ncu * 2));
   hipEvent_t e0, e1;
   FV_HIP(hipEventCreate(&e0));
   FV_HIP(hipEventCreate(&e1));
   FV_HIP(hipEventRecord(e0, s));
-  if (o->prec == FV_PREC_FP32_MIXED)
-    k_engine<float><<<grid, kWG, 0, s>>>(d_tasks, count, queue);
-  else
-    k_engine<double><<<grid, kWG, 0, s>>>(d_tasks, count, queue);
+  if (o->prec == FV_PREC_FP32_MIXED) {
+    enable_engine_lds<float, kWGBatch>(kBatchLds);
+    k_engine<float, kWGBatch><<<grid, kWGBatch, kBatchLds, s>>>(
+        d_tasks, count, queue, (int)(kBatchLds / sizeof(float)));
+  } else {
+    enable_engine_lds<double, kWGBatch>(kBatchLds);
+    k_engine<double, kWGBatch><<<grid, kWGBatch, kBatchLds, s>>>(
+        d_tasks, count, queue, (int)(kBatchLds / sizeof(double)));
+  }
   FV_HIP(hipGetLastError());
   FV_HIP(hipEventRecord(e1, s));
   std::vector<DevState> hst(count);
