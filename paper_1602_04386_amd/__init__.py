@@ -7,6 +7,7 @@ missing; there is no fallback.  Device arrays may be passed as torch tensors
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import weakref
@@ -149,6 +150,22 @@ def _ptr(a):
 
 # --- context and hierarchy ------------------------------------------------------
 
+_live_contexts: "weakref.WeakSet[Context]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all_contexts():
+    # Runs before the interpreter tears objects down in arbitrary order and
+    # before the HIP runtime's own exit handlers: a context (and the
+    # hierarchies and servers it owns) left open by the program is released
+    # while the runtime still works.
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A device context (one per thread)."""
 
@@ -157,6 +174,7 @@ class Context:
         _check(lib().fv_context_create(device, hbm_budget_bytes, C.byref(h)), "fv_context_create")
         self._h = h
         self._children = weakref.WeakSet()  # hierarchies and servers of this context
+        _live_contexts.add(self)
 
     @property
     def handle(self):

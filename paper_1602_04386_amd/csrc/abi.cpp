@@ -23,12 +23,77 @@ void budget_release(fv_context* ctx, size_t bytes) {
   ctx->in_use -= std::min(ctx->in_use, bytes);
 }
 
+// Cached blocks are reused for requests up to 1/8 smaller than the block; new
+// blocks are rounded up to 256 B (4 KiB above 64 KiB).  At most kCacheCap
+// bytes stay cached; beyond that a released block goes back to HIP.
+constexpr size_t kCacheCap = size_t(8) << 30;
+
+static size_t block_round(size_t bytes) {
+  const size_t g = bytes >= (size_t(64) << 10) ? 4096 : 256;
+  return (std::max<size_t>(bytes, 1) + g - 1) / g * g;
+}
+
+void* block_get(fv_context* ctx, size_t bytes) {
+  const size_t want = block_round(bytes);
+  {
+    std::lock_guard<std::mutex> g(ctx->cache_mu);
+    auto it = ctx->cache.lower_bound(want);
+    if (it != ctx->cache.end() && it->first <= want + want / 8) {
+      void* p = it->second;
+      ctx->live[p] = it->first;
+      ctx->cached -= it->first;
+      ctx->cache.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    block_trim(ctx);
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(FV_E_NOMEM, "device allocation failed");
+    }
+  }
+  std::lock_guard<std::mutex> g(ctx->cache_mu);
+  ctx->live[p] = want;
+  return p;
+}
+
+void block_put(fv_context* ctx, void* p) {
+  if (!p) return;
+  std::unique_lock<std::mutex> g(ctx->cache_mu);
+  auto it = ctx->live.find(p);
+  if (it == ctx->live.end()) return;
+  const size_t sz = it->second;
+  ctx->live.erase(it);
+  if (ctx->cached + sz > kCacheCap) {
+    g.unlock();
+    (void)hipFree(p);
+    return;
+  }
+  ctx->cache.emplace(sz, p);
+  ctx->cached += sz;
+}
+
+void block_trim(fv_context* ctx) {
+  std::multimap<size_t, void*> drop;
+  {
+    std::lock_guard<std::mutex> g(ctx->cache_mu);
+    drop.swap(ctx->cache);
+    ctx->cached = 0;
+  }
+  for (auto& kv : drop) (void)hipFree(kv.second);
+}
+
 void* dev_alloc(fv_context* ctx, size_t bytes, size_t* counter) {
   budget_reserve(ctx, bytes);
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  try {
+    p = block_get(ctx, bytes);
+  } catch (...) {
     budget_release(ctx, bytes);
-    throw Error(FV_E_NOMEM, "device allocation failed");
+    throw;
   }
   if (counter) *counter += bytes;
   return p;
@@ -36,7 +101,7 @@ void* dev_alloc(fv_context* ctx, size_t bytes, size_t* counter) {
 
 void dev_free(fv_context* ctx, void* p, size_t bytes, size_t* counter) {
   if (!p) return;
-  (void)hipFree(p);
+  block_put(ctx, p);
   budget_release(ctx, bytes);
   if (counter) *counter -= std::min(*counter, bytes);
 }
@@ -131,6 +196,7 @@ void fv_context_destroy(fv_context* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   if (c->ws) (void)hipFree(c->ws);
+  fv::block_trim(c);
   if (c->pinned) (void)hipHostFree(c->pinned);
   (void)hipStreamDestroy(c->stream);
   delete c;

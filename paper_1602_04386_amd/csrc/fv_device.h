@@ -170,6 +170,18 @@ __device__ inline int block_min_int(int v, int* lds) {
   return t;
 }
 
+__device__ inline int block_max_int(int v, int* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  int t = lds[0];
+  for (int w = 1; w < nw; ++w) t = max(t, lds[w]);
+  __syncthreads();
+  return t;
+}
+
 // Inclusive scan over a wave of 64 lanes.
 __device__ inline int wave_inclusive_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -179,21 +191,6 @@ __device__ inline int wave_inclusive_scan(int v) {
     if (lane >= off) v += t;
   }
   return v;
-}
-
-// Last-block-done protocol: every block has written its partials; the block
-// that arrives last (agent-scope fences on both sides) returns true.
-__device__ inline bool arrive_last(unsigned* counter, unsigned nblocks, int* lds_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned old = atomicAdd(counter, 1u);
-    *lds_flag = (old == nblocks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  bool last = *lds_flag != 0;
-  if (last) __threadfence();
-  return last;
 }
 
 }  // namespace fv

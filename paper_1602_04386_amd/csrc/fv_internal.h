@@ -6,9 +6,11 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "fiedler.h"
@@ -148,6 +150,12 @@ struct fv_context {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int* pinned = nullptr;  // small pinned host buffer for flag readback
+  // Device blocks released by finished work, kept for reuse so that building
+  // and freeing hierarchies does not pay hipMalloc / hipFree every time.
+  std::multimap<size_t, void*> cache;      // block size -> block
+  std::unordered_map<void*, size_t> live;  // block handed out -> block size
+  size_t cached = 0;
+  std::mutex cache_mu;
 };
 
 struct fv_hierarchy {
@@ -160,7 +168,15 @@ struct fv_hierarchy {
 
 namespace fv {
 
-// Device allocation accounted against the context budget.
+// Device blocks from the context's cache (not counted against the budget).
+// block_put requires that no queued or running device work still uses the
+// block: the caller has synchronised the streams that used it.
+void* block_get(fv_context* ctx, size_t bytes);
+void block_put(fv_context* ctx, void* p);
+void block_trim(fv_context* ctx);  // hipFree every cached block
+
+// Device allocation accounted against the context budget (blocks from the
+// cache; dev_free has block_put's precondition).
 void* dev_alloc(fv_context* ctx, size_t bytes, size_t* counter);
 void dev_free(fv_context* ctx, void* p, size_t bytes, size_t* counter);
 void budget_reserve(fv_context* ctx, size_t bytes);

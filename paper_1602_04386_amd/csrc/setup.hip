@@ -17,20 +17,36 @@ namespace fv {
 // Temporary device buffers of one build (not counted against the budget).
 // ---------------------------------------------------------------------------
 struct Tmp {
+  fv_context* ctx;
+  hipStream_t s;
   std::vector<void*> ptrs;
   template <class T>
   T* get(size_t count) {
-    void* p = nullptr;
-    FV_HIP(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
-    ptrs.push_back(p);
-    return static_cast<T*>(p);
+    ptrs.push_back(block_get(ctx, std::max<size_t>(count, 1) * sizeof(T)));
+    return static_cast<T*>(ptrs.back());
   }
   ~Tmp() {
-    for (void* p : ptrs) (void)hipFree(p);
+    (void)hipStreamSynchronize(s);  // the build's work is the only user
+    for (void* p : ptrs) block_put(ctx, p);
   }
 };
 
 static inline int nblk(long long n, int b = kBlock) { return (int)std::max<long long>(1, (n + b - 1) / b); }
+
+// Sets *flag to 1: one plain store per wave, by the lowest of the lanes that
+// reach this call.  Every writer stores the same value, so no read-modify-write
+// is needed; same-address atomics from thousands of waves serialise and made a
+// round over a million vertices take ~180 us.
+__device__ inline void wave_flag(int* flag) {
+  const unsigned long long m = __ballot(1);
+  if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) *flag = 1;
+}
+
+// Round kernels walk the vertices with a grid-stride loop over at most
+// kRoundGrid blocks, so that rounds which exit at once stay cheap.
+constexpr int kRoundGrid = 1024;
+static inline int round_grid(int n) { return std::min(nblk(n), kRoundGrid); }
+
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of f(0..n-1) (int64 accumulation).
@@ -109,16 +125,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(F f, int n, const long lo
 __global__ void k_write_total(const long long* src, int* dst) { *dst = (int)*src; }
 
 struct Scanner {
+  Tmp* tmp = nullptr;
   long long* bsum = nullptr;
   int cap = 0;
   hipStream_t s = nullptr;
   long long* host = nullptr;  // pinned
-  // Writes the exclusive scan of f over [0, n) to out (if non-null), and the
-  // total to out[n] when write_total; returns the total.
+  const long long* last = nullptr;
+  // Queues the exclusive scan of f over [0, n) into out (if non-null) and,
+  // when write_total, the total into out[n].  Nothing is read back.
   template <class F>
-  long long run(F f, int n, int* out, bool write_total) {
-    int nb = std::max(1, (n + kScanTile - 1) / kScanTile);
-    if (nb + 1 > cap) throw Error(FV_E_INVALID, "scan scratch too small");
+  void enqueue(F f, int n, int* out, bool write_total) {
+    const int nb = std::max(1, (n + kScanTile - 1) / kScanTile);
+    if (nb + 1 > cap) {
+      cap = nb + 4;
+      bsum = tmp->get<long long>(cap);
+    }
     k_scan_reduce<<<nb, kBlock, 0, s>>>(f, n, bsum);
     k_scan_blocks<<<1, kBlock, 0, s>>>(bsum, nb);
     if (out) {
@@ -126,7 +147,13 @@ struct Scanner {
       if (write_total) k_write_total<<<1, 1, 0, s>>>(bsum + nb, out + n);
     }
     FV_HIP(hipGetLastError());
-    FV_HIP(hipMemcpyAsync(host, bsum + nb, sizeof(long long), hipMemcpyDeviceToHost, s));
+    last = bsum + nb;
+  }
+  // enqueue, then waits for the stream and returns the total.
+  template <class F>
+  long long run(F f, int n, int* out, bool write_total) {
+    enqueue(f, n, out, write_total);
+    FV_HIP(hipMemcpyAsync(host, last, sizeof(long long), hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
     return *host;
   }
@@ -135,11 +162,6 @@ struct Scanner {
 struct FromArray {
   const int* a;
   __device__ int operator()(int i) const { return a[i]; }
-};
-struct FlagEq {
-  const int* a;
-  int c;
-  __device__ int operator()(int i) const { return a[i] == c ? 1 : 0; }
 };
 struct LeaderFlag {
   const int* root;
@@ -282,35 +304,44 @@ __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, con
 // Under a strict total order this yields the greedy matching that takes the
 // edges from heaviest down.  mate: -1 free, -2 free without free neighbours.
 // ---------------------------------------------------------------------------
+// Rounds are launched in batches; round r > 0 returns at once when round r - 1
+// left no vertex pending (prev points at that round's flag).  Rounds after the
+// last productive one change nothing either way.
 __global__ void k_match_pick(int n, const int* rp, const int* col, const double* w,
-                             const int* mate, int* ptr) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || mate[v] != -1) return;
-  int best = -1;
-  double bw = 0.0;
-  for (int p = rp[v]; p < rp[v + 1]; ++p) {
-    int u = col[p];
-    if (mate[u] != -1) continue;
-    double wu = w[p];
-    if (best < 0 || edge_before(wu, v, u, bw, v, best)) {
-      best = u;
-      bw = wu;
+                             const int* mate, int* ptr, const int* prev) {
+  if (prev && *prev == 0) return;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    if (mate[v] != -1) continue;
+    int best = -1;
+    double bw = 0.0;
+    for (int p = rp[v]; p < rp[v + 1]; ++p) {
+      int u = col[p];
+      if (mate[u] != -1) continue;
+      double wu = w[p];
+      if (best < 0 || edge_before(wu, v, u, bw, v, best)) {
+        best = u;
+        bw = wu;
+      }
     }
+    ptr[v] = best;
   }
-  ptr[v] = best;
 }
 
-__global__ void k_match_commit(int n, int* mate, const int* ptr, int* active) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || mate[v] != -1) return;
-  int u = ptr[v];
-  if (u < 0) {
-    mate[v] = -2;
-  } else if (ptr[u] == v) {
-    mate[v] = u;
-  } else {
-    atomicOr(active, 1);
+__global__ void k_match_commit(int n, int* mate, const int* ptr, int* active, const int* prev) {
+  if (prev && *prev == 0) return;
+  bool pending = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    if (mate[v] != -1) continue;
+    int u = ptr[v];
+    if (u < 0) {
+      mate[v] = -2;
+    } else if (ptr[u] == v) {
+      mate[v] = u;
+    } else {
+      pending = true;
+    }
   }
+  if (__ballot(pending) != 0ULL && (threadIdx.x & 63) == 0) *active = 1;
 }
 
 // Aggregates (Algorithm 1): pairs; an unmatched vertex joins the aggregate of
@@ -338,7 +369,7 @@ __global__ void k_agg_root(int n, const int* rp, const int* col, const double* w
     }
   int mb = mate[best];
   if (mb < 0) {
-    atomicOr(err, 1);
+    wave_flag(err);
     root[v] = v;
     return;
   }
@@ -361,59 +392,92 @@ __global__ void k_agg_q(int n, const int* root, const int* minmem, const int* id
 // sequential first-fit in priority order.
 // ---------------------------------------------------------------------------
 __global__ void k_colour_round(int n, const int* rp, const int* col, uint32_t seed, int* colour,
-                               int* active, int* maxc) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || colour[v] >= 0) return;
-  uint32_t pv = colour_priority(v, seed);
-  int a = rp[v], b = rp[v + 1];
-  for (int p = a; p < b; ++p) {
-    int u = col[p];
-    if (colour[u] < 0) {
-      uint32_t pu = colour_priority(u, seed);
-      if (pu > pv || (pu == pv && u < v)) {
-        atomicOr(active, 1);
-        return;
+                               int* active, const int* prev) {
+  if (prev && *prev == 0) return;  // uniform over the grid
+  bool wait_any = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    if (colour[v] >= 0) continue;
+    const uint32_t pv = colour_priority(v, seed);
+    const int a = rp[v], b = rp[v + 1];
+    bool wait = false;
+    for (int p = a; p < b && !wait; ++p) {
+      const int u = col[p];
+      if (colour[u] < 0) {
+        const uint32_t pu = colour_priority(u, seed);
+        wait = pu > pv || (pu == pv && u < v);
+      }
+    }
+    if (wait) {
+      wait_any = true;
+      continue;
+    }
+    for (int base = 0;; base += 64) {
+      unsigned long long mask = 0;
+      for (int p = a; p < b; ++p) {
+        const int c = colour[col[p]];
+        if (c >= base && c < base + 64) mask |= 1ULL << (c - base);
+      }
+      if (mask != ~0ULL) {
+        colour[v] = base + __builtin_ctzll(~mask);
+        break;
       }
     }
   }
-  for (int base = 0;; base += 64) {
-    unsigned long long mask = 0;
-    for (int p = a; p < b; ++p) {
-      int c = colour[col[p]];
-      if (c >= base && c < base + 64) mask |= 1ULL << (c - base);
-    }
-    if (mask != ~0ULL) {
-      int c = base + __builtin_ctzll(~mask);
-      colour[v] = c;
-      atomicMax(maxc, c);
-      return;
-    }
-  }
+  if (__ballot(wait_any) != 0ULL && (threadIdx.x & 63) == 0) *active = 1;
 }
 
-// Colour histogram: per-block counts in LDS, one global add per colour.
-__global__ __launch_bounds__(kBlock) void k_count_colours(int n, const int* colour, int ncol,
-                                                        int* cnt) {
-  __shared__ int hist[kBlock];
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ncol > kBlock) {
-    if (v < n) atomicAdd(&cnt[colour[v]], 1);
-    return;
-  }
-  if (threadIdx.x < ncol) hist[threadIdx.x] = 0;
+// Largest colour: per-block maxima, then one block over those.
+__global__ __launch_bounds__(kBlock) void k_max_blocks(int n, const int* a, int* bmax) {
+  __shared__ int lds[kBlock / 64];
+  int m = -1;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    m = max(m, a[v]);
+  m = block_max_int(m, lds);
+  if (threadIdx.x == 0) bmax[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_final(int nb, const int* bmax, int* out) {
+  __shared__ int lds[kBlock / 64];
+  int m = -1;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) m = max(m, bmax[b]);
+  m = block_max_int(m, lds);
+  if (threadIdx.x == 0) *out = m;
+}
+
+// Solve order: rows sorted by colour, ascending original index inside a
+// colour (a stable counting sort).  Block b counts its kBlock vertices per
+// colour into cnt[c * nb + b]; an exclusive scan of cnt in that (colour-major)
+// order gives every (colour, block) run its start; each vertex then adds the
+// number of earlier vertices of its block with its colour.
+__global__ __launch_bounds__(kBlock) void k_colour_block_count(int n, const int* colour, int ncol,
+                                                             int nb, int* cnt) {
+  extern __shared__ int hist[];
+  for (int c = threadIdx.x; c < ncol; c += kBlock) hist[c] = 0;
   __syncthreads();
+  const int v = blockIdx.x * kBlock + threadIdx.x;
   if (v < n) atomicAdd(&hist[colour[v]], 1);
   __syncthreads();
-  if (threadIdx.x < ncol && hist[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], hist[threadIdx.x]);
+  for (int c = threadIdx.x; c < ncol; c += kBlock) cnt[(size_t)c * nb + blockIdx.x] = hist[c];
 }
 
-__global__ void k_perm_fill(int n, const int* colour, int c, int start, const int* pos, int* perm,
-                            int* iperm) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || colour[v] != c) return;
-  int p = start + pos[v];
+__global__ __launch_bounds__(kBlock) void k_colour_scatter(int n, const int* colour, int nb,
+                                                         const int* off, int* perm, int* iperm) {
+  __shared__ int sc[kBlock];
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  const int c = v < n ? colour[v] : -1;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  if (v >= n) return;
+  int r = 0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) r += sc[t] == c;
+  const int p = off[(size_t)c * nb + blockIdx.x] + r;
   perm[v] = p;
   iperm[p] = v;
+}
+
+// cptr[c] = first solve-order row of colour c; cptr[ncol] = n.
+__global__ void k_colour_ptr(int n, int ncol, int nb, const int* off, int* cptr) {
+  for (int c = threadIdx.x; c <= ncol; c += blockDim.x) cptr[c] = c < ncol ? off[(size_t)c * nb] : n;
 }
 
 // Colour-ordered copy: row i of the solve order is original row iperm[i];
@@ -504,11 +568,14 @@ __global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, const int* ts
     myb = tb[s + lane];
     myw = tw[s + lane];
   }
+  // T is the same in every lane of the wave, so the terms are broadcast with
+  // readlane (scalar) instead of a cross-lane shuffle.
   int rank = 0;
   const int Tl = active ? T : 0;
-  for (int l = 0; l < 64; ++l) {
-    int J2 = __shfl(myJ, l, 64), a2 = __shfl(mya, l, 64), b2 = __shfl(myb, l, 64);
-    if (l < Tl && term_less(J2, a2, b2, myJ, mya, myb)) ++rank;
+  for (int l = 0; l < Tl; ++l) {
+    const int J2 = __builtin_amdgcn_readlane(myJ, l), a2 = __builtin_amdgcn_readlane(mya, l),
+              b2 = __builtin_amdgcn_readlane(myb, l);
+    if (term_less(J2, a2, b2, myJ, mya, myb)) ++rank;
   }
   if (active && lane < T) {
     sJ[wave][rank] = myJ;
@@ -531,12 +598,9 @@ __global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, const int* ts
 
 // Rows with more than 64 terms: one workgroup per listed row, rank sort into
 // global scratch, then a sequential collapse.
-__global__ __launch_bounds__(kBlock) void k_gal_rows_big(const int* list, const int* tstart,
-                                                       const int* tJ, const int* ta,
-                                                       const int* tb, const double* tw,
-                                                       int* sJ, double* sw, int* cJ,
-                                                       double* cw, int* uniq) {
-  const int I = list[blockIdx.x];
+__device__ inline void gal_big_row(int I, const int* tstart, const int* tJ, const int* ta,
+                                   const int* tb, const double* tw, int* sJ, double* sw, int* cJ,
+                                   double* cw, int* uniq) {
   const int s = tstart[I], T = tstart[I + 1] - s;
   for (int k = threadIdx.x; k < T; k += blockDim.x) {
     int J = tJ[s + k], a = ta[s + k], b = tb[s + k];
@@ -559,6 +623,18 @@ __global__ __launch_bounds__(kBlock) void k_gal_rows_big(const int* list, const 
       ++u;
     }
     uniq[I] = u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gal_rows_big(const int* list, const int* nlist,
+                                                       const int* tstart, const int* tJ,
+                                                       const int* ta, const int* tb,
+                                                       const double* tw, int* sJ, double* sw,
+                                                       int* cJ, double* cw, int* uniq) {
+  const int nbig = *nlist;
+  for (int row = blockIdx.x; row < nbig; row += gridDim.x) {
+    gal_big_row(list[row], tstart, tJ, ta, tb, tw, sJ, sw, cJ, cw, uniq);
+    __syncthreads();
   }
 }
 
@@ -592,16 +668,14 @@ static int read_int(const int* d, hipStream_t s, int* pinned) {
   return *pinned;
 }
 
-static double level_sigma(const Level& L, unsigned long long* dmax, hipStream_t s,
-                          unsigned long long* pinned) {
-  FV_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned long long), s));
-  k_degree_max<<<nblk(L.n), kBlock, 0, s>>>(L.n, L.rp_c, L.w_c, dmax);
-  FV_HIP(hipGetLastError());
-  FV_HIP(hipMemcpyAsync(pinned, dmax, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  FV_HIP(hipStreamSynchronize(s));
-  double d;
-  std::memcpy(&d, pinned, sizeof(double));
-  return 2.0 * d;
+// Copies up to 8 device ints into out[0..7] (one launch, so that one
+// read-back returns them all).
+struct IntSrc {
+  const int* p[8];
+};
+__global__ void k_gather_ints(IntSrc src, int count, int* out) {
+  const int t = threadIdx.x;
+  if (t < count) out[t] = src.p[t] ? *src.p[t] : 0;
 }
 
 static void free_level(fv_hierarchy* h, Level& L) {
@@ -627,6 +701,9 @@ static void free_level(fv_hierarchy* h, Level& L) {
 
 void free_hierarchy(fv_hierarchy* h) {
   if (!h) return;
+  // Solves on any stream may still read the levels; wait for them before the
+  // blocks go back to the cache (hipFree would synchronise the same way).
+  (void)hipDeviceSynchronize();
   for (int l = 0; l < FV_MAX_LEVELS; ++l) free_level(h, h->lv[l]);
   if (h->d_desc) dev_free(h->ctx, h->d_desc, sizeof(LevelDesc) * FV_MAX_LEVELS, &h->bytes);
   delete h;
@@ -647,16 +724,14 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
   if (n_coarse < 1) throw Error(FV_E_INVALID, "n_coarse < 1");
   if (max_levels < 1 || max_levels > FV_MAX_LEVELS) max_levels = FV_MAX_LEVELS;
 
-  Tmp tmp;
+  Tmp tmp{ctx, s, {}};
   int* pin_i = nullptr;
-  unsigned long long* pin_u = nullptr;
   long long* pin_ll = nullptr;
   FV_HIP(hipHostMalloc((void**)&pin_i, 64, hipHostMallocDefault));
   struct PinGuard {
     int* p;
     ~PinGuard() { (void)hipHostFree(p); }
   } pg{pin_i};
-  pin_u = reinterpret_cast<unsigned long long*>(pin_i + 4);
   pin_ll = reinterpret_cast<long long*>(pin_i + 8);
 
   // Stage the input on the device.
@@ -678,21 +753,29 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
   }
 
   Scanner sc;
-  sc.cap = n / kScanTile + 4;
-  sc.bsum = tmp.get<long long>(sc.cap);
+  sc.tmp = &tmp;
   sc.s = s;
   sc.host = pin_ll;
 
-  int* flags = tmp.get<int>(4);
-  FV_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
+  // Validation (Definition 2.1): the structure first (the value check reads
+  // through it), then values, symmetry and degrees.
+  int* flags = tmp.get<int>(8);
+  int* gath = tmp.get<int>(8);
+  FV_HIP(hipMemsetAsync(flags, 0, 8 * sizeof(int), s));
   k_val_structure<<<nblk(n), kBlock, 0, s>>>(n, nnz, rp_in, col_in, flags);
   FV_HIP(hipGetLastError());
   if (read_int(flags, s, pin_i) & 1) throw Error(FV_E_INVALID, "CSR structure invalid");
   int* offdeg = tmp.get<int>(n);
+  int* rp0 = tmp.get<int>(n + 1);
   k_val_values<<<nblk(n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, Lin->is_adjacency ? 1 : 0,
                                           offdeg, flags);
   FV_HIP(hipGetLastError());
-  int f = read_int(flags, s, pin_i);
+  sc.enqueue(FromArray{offdeg}, n, rp0, true);
+  k_gather_ints<<<1, 64, 0, s>>>(IntSrc{{flags, rp0 + n}}, 2, gath);
+  FV_HIP(hipMemcpyAsync(pin_i, gath, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  FV_HIP(hipStreamSynchronize(s));
+  const int f = pin_i[0];
+  const long long m0 = pin_i[1];
   if (f & 2) throw Error(FV_E_NOT_LAPLACIAN, "not a graph Laplacian / adjacency");
   if (f & 4) throw Error(FV_E_NOT_SYMMETRIC, "not symmetric");
   if (f & 8) throw Error(FV_E_ISOLATED, "isolated vertex");
@@ -703,7 +786,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     Level& L0 = h->lv[0];
     L0.n = n;
     L0.rp_c = halloc<int>(h, n + 1);
-    long long m0 = sc.run(FromArray{offdeg}, n, L0.rp_c, true);
+    FV_HIP(hipMemcpyAsync(L0.rp_c, rp0, sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
     L0.m = m0;
     L0.col_c = halloc<int>(h, m0);
     L0.w_c = halloc<double>(h, m0);
@@ -717,13 +800,13 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     int* ptr = tmp.get<int>(n);
     int* root = tmp.get<int>(n);
     int* minmem = tmp.get<int>(n);
-    int* id = tmp.get<int>(n);
+    int* id = tmp.get<int>(n + 1);
     int* tcount = tmp.get<int>(n + 1);
     int* tstart = tmp.get<int>(n + 1);
     int* tfill = tmp.get<int>(n);
     int* uniq = tmp.get<int>(n + 1);
     int* list = tmp.get<int>(n);
-    int* lpos = tmp.get<int>(n);
+    int* lpos = tmp.get<int>(n + 1);
     int* tJ = tmp.get<int>(mcap);
     int* ta = tmp.get<int>(mcap);
     int* tb = tmp.get<int>(mcap);
@@ -732,51 +815,92 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     double* cw = tmp.get<double>(mcap);
     int* sJ = tmp.get<int>(mcap);
     double* sw = tmp.get<double>(mcap);
-    int* pos = tmp.get<int>(n);
-    int* cnt = tmp.get<int>(n + 1);
-    unsigned long long* dmax = tmp.get<unsigned long long>(1);
+    unsigned long long* dmax = tmp.get<unsigned long long>(FV_MAX_LEVELS);
+    FV_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned long long) * FV_MAX_LEVELS, s));
+    // Per-round progress flags of the matching and colouring rounds.
+    constexpr int kRoundCap = 4096;
+    int* mflag = tmp.get<int>(kRoundCap);
+    int* cflag = tmp.get<int>(kRoundCap);
+    int* lflag = flags + 4;  // [0] aggregation error, [1] largest colour
+    int* bmax = tmp.get<int>(kRoundGrid);
 
     int l = 0;
     for (;;) {
       Level& F = h->lv[l];
-      F.sigma = level_sigma(F, dmax, s, pin_u);
+      k_degree_max<<<nblk(F.n), kBlock, 0, s>>>(F.n, F.rp_c, F.w_c, dmax + l);
+      FV_HIP(hipGetLastError());
       if (F.n <= n_coarse || l + 1 >= max_levels) break;
       const int fn = F.n;
-      // matching rounds
+      // Matching and colouring rounds run in batches; the host reads the
+      // progress flag of the last round of each batch, together with the
+      // aggregate count, in one read-back when the first batches suffice.
+      int mr = 0, cr = 0;
+      k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(mflag, kRoundCap, 0);
+      k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(cflag, kRoundCap, 0);
       k_fill_int<<<nblk(fn), kBlock, 0, s>>>(mate, fn, -1);
-      for (int round = 0;; ++round) {
-        k_match_pick<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr);
-        FV_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
-        k_match_commit<<<nblk(fn), kBlock, 0, s>>>(fn, mate, ptr, flags);
+      auto match_rounds = [&](int b) {
+        if (mr + b > kRoundCap) throw Error(FV_E_DEVICE, "matching did not terminate");
+        for (int r = mr; r < mr + b; ++r) {
+          const int* prev = r ? mflag + r - 1 : nullptr;
+          k_match_pick<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr,
+                                                         prev);
+          k_match_commit<<<round_grid(fn), kBlock, 0, s>>>(fn, mate, ptr, mflag + r, prev);
+        }
+        mr += b;
         FV_HIP(hipGetLastError());
-        if (!read_int(flags, s, pin_i)) break;
-        if (round > fn) throw Error(FV_E_DEVICE, "matching did not terminate");
-      }
-      // aggregates
-      FV_HIP(hipMemsetAsync(flags + 1, 0, sizeof(int), s));
-      k_agg_root<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, root, flags + 1);
-      k_fill_int<<<nblk(fn), kBlock, 0, s>>>(minmem, fn, INT_MAX);
-      k_agg_minmem<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem);
-      FV_HIP(hipGetLastError());
-      if (read_int(flags + 1, s, pin_i)) throw Error(FV_E_DEVICE, "matching not maximal");
-      const int nc = (int)sc.run(LeaderFlag{root, minmem}, fn, id, false);
-      if (nc < 2 || nc >= fn) break;
-      F.q_c = halloc<int>(h, fn);
-      k_agg_q<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem, id, F.q_c);
-      // colouring of this level for the smoother
+      };
+      auto aggregate = [&]() {
+        FV_HIP(hipMemsetAsync(lflag, 0, sizeof(int), s));
+        k_agg_root<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, root, lflag);
+        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(minmem, fn, INT_MAX);
+        k_agg_minmem<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem);
+        FV_HIP(hipGetLastError());
+        sc.enqueue(LeaderFlag{root, minmem}, fn, id, true);
+      };
+      const uint32_t lseed = level_seed(cseed, l);
+      auto colour_rounds = [&](int b) {
+        if (cr + b > kRoundCap) throw Error(FV_E_DEVICE, "colouring did not terminate");
+        for (int r = cr; r < cr + b; ++r)
+          k_colour_round<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed,
+                                                           F.colour_c, cflag + r,
+                                                           r ? cflag + r - 1 : nullptr);
+        cr += b;
+        k_max_blocks<<<round_grid(fn), kBlock, 0, s>>>(fn, F.colour_c, bmax);
+        k_max_final<<<1, kBlock, 0, s>>>(round_grid(fn), bmax, lflag + 1);
+        FV_HIP(hipGetLastError());
+      };
+      auto read_back = [&]() {
+        k_gather_ints<<<1, 64, 0, s>>>(
+            IntSrc{{mflag + mr - 1, cflag + cr - 1, lflag, lflag + 1, id + fn}}, 5, gath);
+        FV_HIP(hipMemcpyAsync(pin_i, gath, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+        FV_HIP(hipStreamSynchronize(s));
+      };
+      match_rounds(8);
+      aggregate();
       F.colour_c = halloc<int>(h, fn);
       k_fill_int<<<nblk(fn), kBlock, 0, s>>>(F.colour_c, fn, -1);
-      FV_HIP(hipMemsetAsync(flags + 2, 0, sizeof(int), s));
-      const uint32_t lseed = level_seed(cseed, l);
-      for (int round = 0;; ++round) {
-        FV_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
-        k_colour_round<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed, F.colour_c, flags,
-                                                   flags + 2);
-        FV_HIP(hipGetLastError());
-        if (!read_int(flags, s, pin_i)) break;
-        if (round > fn) throw Error(FV_E_DEVICE, "colouring did not terminate");
+      colour_rounds(16);
+      read_back();
+      while (pin_i[0]) {
+        match_rounds(8);
+        aggregate();
+        read_back();
       }
-      F.ncol = read_int(flags + 2, s, pin_i) + 1;
+      while (pin_i[1]) {
+        colour_rounds(8);
+        read_back();
+      }
+      if (pin_i[2]) throw Error(FV_E_DEVICE, "matching not maximal");
+      F.ncol = pin_i[3] + 1;
+      const int nc = pin_i[4];
+      if (nc < 2 || nc >= fn) {
+        dev_free(ctx, F.colour_c, sizeof(int) * fn, &h->bytes);
+        F.colour_c = nullptr;
+        F.ncol = 0;
+        break;
+      }
+      F.q_c = halloc<int>(h, fn);
+      k_agg_q<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem, id, F.q_c);
       // Galerkin coarse graph
       Level& Cl = h->lv[l + 1];
       Cl.n = nc;
@@ -784,18 +908,17 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       FV_HIP(hipMemsetAsync(tfill, 0, sizeof(int) * nc, s));
       k_gal_count<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.q_c, tcount);
       FV_HIP(hipGetLastError());
-      sc.run(FromArray{tcount}, nc, tstart, true);
+      sc.enqueue(FromArray{tcount}, nc, tstart, true);
       k_gal_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, F.q_c, tstart, tfill, tJ,
                                              ta, tb, tw);
       k_gal_rows_small<<<nblk(nc, kBlock / 64), kBlock, 0, s>>>(nc, tstart, tJ, ta, tb, tw, cJ, cw,
                                                                  uniq);
       FV_HIP(hipGetLastError());
-      const int nbig = (int)sc.run(BigRow{tstart}, nc, lpos, false);
-      if (nbig > 0) {
-        k_list_fill<<<nblk(nc), kBlock, 0, s>>>(nc, tstart, lpos, list);
-        k_gal_rows_big<<<nbig, kBlock, 0, s>>>(list, tstart, tJ, ta, tb, tw, sJ, sw, cJ, cw, uniq);
-        FV_HIP(hipGetLastError());
-      }
+      sc.enqueue(BigRow{tstart}, nc, lpos, true);
+      k_list_fill<<<nblk(nc), kBlock, 0, s>>>(nc, tstart, lpos, list);
+      k_gal_rows_big<<<std::min(nc, 512), kBlock, 0, s>>>(list, lpos + nc, tstart, tJ, ta, tb, tw,
+                                                          sJ, sw, cJ, cw, uniq);
+      FV_HIP(hipGetLastError());
       Cl.rp_c = halloc<int>(h, nc + 1);
       const long long mc = sc.run(FromArray{uniq}, nc, Cl.rp_c, true);
       Cl.m = mc;
@@ -820,26 +943,25 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         F.cptr_h = {0, fn};
         k_iota<<<nblk(fn), kBlock, 0, s>>>(F.perm, fn);
         k_iota<<<nblk(fn), kBlock, 0, s>>>(F.iperm, fn);
+        F.cptr = halloc<int>(h, 2);
+        FV_HIP(hipMemcpyAsync(F.cptr, F.cptr_h.data(), sizeof(int) * 2, hipMemcpyHostToDevice, s));
       } else {
-        FV_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (F.ncol + 1), s));
-        k_count_colours<<<nblk(fn), kBlock, 0, s>>>(fn, F.colour_c, F.ncol, cnt);
-        std::vector<int> ch(F.ncol);
-        FV_HIP(hipMemcpyAsync(ch.data(), cnt, sizeof(int) * F.ncol, hipMemcpyDeviceToHost, s));
-        FV_HIP(hipStreamSynchronize(s));
-        F.cptr_h.assign(F.ncol + 1, 0);
-        for (int c = 0; c < F.ncol; ++c) F.cptr_h[c + 1] = F.cptr_h[c] + ch[c];
-        for (int c = 0; c < F.ncol; ++c) {
-          sc.run(FlagEq{F.colour_c, c}, fn, pos, false);
-          k_perm_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.colour_c, c, F.cptr_h[c], pos, F.perm,
-                                                  F.iperm);
-        }
+        const int nb = nblk(fn);
+        const long long cells = (long long)F.ncol * nb;
+        if (cells >= INT_MAX) throw Error(FV_E_INVALID, "too many colours");
+        int* cnt = tmp.get<int>(cells);
+        int* off = tmp.get<int>(cells + 1);
+        k_colour_block_count<<<nb, kBlock, sizeof(int) * F.ncol, s>>>(fn, F.colour_c, F.ncol, nb,
+                                                                      cnt);
+        FV_HIP(hipGetLastError());
+        sc.enqueue(FromArray{cnt}, (int)cells, off, false);
+        k_colour_scatter<<<nb, kBlock, 0, s>>>(fn, F.colour_c, nb, off, F.perm, F.iperm);
+        F.cptr = halloc<int>(h, F.ncol + 1);
+        k_colour_ptr<<<1, kBlock, 0, s>>>(fn, F.ncol, nb, off, F.cptr);
         FV_HIP(hipGetLastError());
       }
-      F.cptr = halloc<int>(h, F.ncol + 1);
-      FV_HIP(hipMemcpyAsync(F.cptr, F.cptr_h.data(), sizeof(int) * (F.ncol + 1),
-                            hipMemcpyHostToDevice, s));
       F.rp = halloc<int>(h, fn + 1);
-      sc.run(PermDeg{F.rp_c, F.iperm}, fn, F.rp, true);
+      sc.enqueue(PermDeg{F.rp_c, F.iperm}, fn, F.rp, true);
       F.col = halloc<int>(h, F.m);
       F.w64 = halloc<double>(h, F.m);
       F.w32 = halloc<float>(h, F.m);
@@ -851,6 +973,22 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         k_qs<<<nblk(fn), kBlock, 0, s>>>(fn, F.perm, F.q_c, h->lv[k + 1].perm, F.qs);
         FV_HIP(hipGetLastError());
       }
+    }
+    // Read back the shifts and colour ranges of every level at once.
+    std::vector<unsigned long long> dm(J + 1);
+    FV_HIP(hipMemcpyAsync(dm.data(), dmax, sizeof(unsigned long long) * (J + 1),
+                          hipMemcpyDeviceToHost, s));
+    for (int k = 0; k < J; ++k) {
+      Level& F = h->lv[k];
+      F.cptr_h.assign(F.ncol + 1, 0);
+      FV_HIP(hipMemcpyAsync(F.cptr_h.data(), F.cptr, sizeof(int) * (F.ncol + 1),
+                            hipMemcpyDeviceToHost, s));
+    }
+    FV_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k <= J; ++k) {
+      double d;
+      std::memcpy(&d, &dm[k], sizeof(double));
+      h->lv[k].sigma = 2.0 * d;
     }
     // Device descriptors.
     std::vector<LevelDesc> d(FV_MAX_LEVELS);

@@ -203,50 +203,80 @@ struct EngineCtx {
 // steps).  Writes the unit iterate to out; returns steps, sets *conv.
 __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int max_it,
                                int forced, double* out, double* lx, int* conv, EngineCtx& E) {
-  const int n = L.n;
+  const int n = __builtin_amdgcn_readfirstlane(L.n);  // uniform: keeps loop branches scalar
   const double sigma = L.sigma;
   const double* __restrict__ w = L.w64;
   const int* __restrict__ col = L.col;
   int it = 0;
-  if (n <= 64) {
-    // One wavefront: lane i owns row i; neighbours read by lane shuffles.
+  if (n <= 64 && n * n * (int)sizeof(double) <= E.bytes) {
+    // One wavefront: lane i owns row i.  W is staged densely in LDS, column
+    // j contiguous, so that (L x)_i = sum_j W_ij (x_i - x_j) runs over j in
+    // ascending order (the CSR order of this level, whose rows are in
+    // original order) with x_j broadcast by readlane; absent edges add
+    // 0 * (x_i - x_j) = 0 exactly.
+    __attribute__((address_space(3))) double* Wd =
+        (__attribute__((address_space(3))) double*)(static_cast<double*>(E.xl));
+    for (int k = threadIdx.x; k < n * n; k += blockDim.x) Wd[k] = 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      for (int p = L.rp[i]; p < L.rp[i + 1]; ++p) Wd[col[p] * n + i] = w[p];
+    __syncthreads();
     __shared__ int s_it, s_conv;
     if (threadIdx.x < 64) {
       const int lane = threadIdx.x;
       const bool has = lane < n;
-      const int p0 = has ? L.rp[lane] : 0, p1 = has ? L.rp[lane + 1] : 0;
-      int deg = p1 - p0, maxdeg = deg;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) maxdeg = max(maxdeg, __shfl_xor(maxdeg, off, 64));
+      const int base = has ? lane : 0;
       double x = has ? 2.0 * splitmix_uniform(seed, (unsigned long long)lane + 1ULL) - 1.0 : 0.0;
       double m = wave_sum(x) / n;
       x = has ? x - m : 0.0;
       x *= 1.0 / sqrt(wave_sum(x * x));
+      // Up to 32 vertices (the usual coarsest size) the row is also held in
+      // registers, so an iteration touches no memory at all.
+      constexpr int kRegRow = 32;
+      double wr[kRegRow];
+#pragma unroll
+      for (int j = 0; j < kRegRow; ++j) wr[j] = j < n ? Wd[j * n + base] : 0.0;
+      auto bcast = [](double v, int j) {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), j),
+                                __builtin_amdgcn_readlane(__double2loint(v), j));
+      };
       int cv = 0;
       for (;;) {
         double l = 0.0;
-        for (int k = 0; k < maxdeg; ++k) {
-          const int j = k < deg ? col[p0 + k] : lane;
-          const double xj = __shfl(x, j, 64);
-          if (k < deg) l += w[p0 + k] * (x - xj);
+        if (n <= kRegRow) {
+          // Columns j >= n have wr[j] = 0 and x_j = 0: exact zeros added after
+          // the real terms, so no per-column branch is needed.
+#pragma unroll
+          for (int j = 0; j < kRegRow; ++j) l += wr[j] * (x - bcast(x, j));
+        } else {
+#pragma unroll 8
+          for (int j = 0; j < n; ++j) l += Wd[j * n + base] * (x - bcast(x, j));
         }
+        l = has ? l : 0.0;
+        // The shifted step does not depend on the stop test, so its mean is
+        // reduced together with the Rayleigh quotient.
+        double y = has ? sigma * x - l : 0.0;
+        const double rho = wave_sum(x * l);
+        const double my = wave_sum(y) / n;
+        y = has ? y - my : 0.0;
         if (forced >= 0) {
           if (it >= forced) {
             cv = 1;
             break;
           }
         } else {
-          const double rho = wave_sum(x * l);
           const double r = l - rho * x;
-          if (sqrt(wave_sum(r * r)) <= 1e-13 * sigma) {
+          const double rr = wave_sum(r * r);
+          const double yy = wave_sum(y * y);
+          if (sqrt(rr) <= 1e-13 * sigma) {
             cv = 1;
             break;
           }
           if (it >= max_it) break;
+          x = y * (1.0 / sqrt(yy));
+          ++it;
+          continue;
         }
-        double y = sigma * x - l;
-        const double my = wave_sum(y) / n;
-        y = has ? y - my : 0.0;
         x = y * (1.0 / sqrt(wave_sum(y * y)));
         ++it;
       }
@@ -824,49 +854,56 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
                       double* lambda_out, fv_solve_stats* stats, fv_status* item_status,
                       hipStream_t s) {
   if (count <= 0) return FV_OK;
-  // Per-item device memory: xa, xb, lx (8 bytes each per vertex), output,
-  // state and schedule.
-  std::vector<size_t> off(count + 1, 0);
+  // Per-item device memory: xa, xb, lx (8 bytes each per vertex) and, for
+  // host outputs, the FP64 result.  States, schedules and schedule lengths of
+  // all items are contiguous so that one copy each reads them back.
+  std::vector<size_t> off(count + 1, 0), xoff(count + 1, 0);
   for (int k = 0; k < count; ++k) {
     const size_t n = hierarchy_nmax(hs[k]);
-    off[k + 1] = off[k] + align_up(8 * n) * (x_on_device ? 3 : 4) + align_up(sizeof(DevState)) +
-                 align_up(4 * FV_SCHEDULE_CAP) + align_up(64);
+    off[k + 1] = off[k] + align_up(8 * n) * 3;
+    xoff[k + 1] = xoff[k] + (x_on_device ? 0 : n);
   }
-  const size_t bytes = off[count] + align_up(sizeof(GraphTask) * count) + 256;
+  const size_t o_out = off[count];
+  const size_t o_st = o_out + align_up(8 * xoff[count]);
+  const size_t o_sched = o_st + align_up(sizeof(DevState) * count);
+  const size_t o_slen = o_sched + align_up(sizeof(int) * FV_SCHEDULE_CAP * count);
+  const size_t o_tasks = o_slen + align_up(sizeof(int) * count);
+  const size_t o_queue = o_tasks + align_up(sizeof(GraphTask) * count);
+  const size_t bytes = o_queue + 256;
   budget_reserve(ctx, bytes);
   char* base = nullptr;
-  if (hipMalloc(reinterpret_cast<void**>(&base), bytes) != hipSuccess) {
+  try {
+    base = static_cast<char*>(block_get(ctx, bytes));
+  } catch (...) {
     budget_release(ctx, bytes);
-    throw Error(FV_E_NOMEM, "batch workspace allocation failed");
+    throw;
   }
   struct Guard {
     fv_context* c;
+    hipStream_t s;
     void* p;
     size_t b;
     ~Guard() {
-      (void)hipFree(p);
+      (void)hipStreamSynchronize(s);
+      block_put(c, p);
       budget_release(c, b);
     }
-  } guard{ctx, base, bytes};
+  } guard{ctx, s, base, bytes};
+  DevState* d_st = reinterpret_cast<DevState*>(base + o_st);
+  int* d_sched = reinterpret_cast<int*>(base + o_sched);
+  int* d_slen = reinterpret_cast<int*>(base + o_slen);
+  double* d_out = reinterpret_cast<double*>(base + o_out);
   std::vector<GraphTask> tasks(count);
   std::vector<int> order(count);
-  std::vector<double*> outs(count);
   for (int k = 0; k < count; ++k) {
     char* p = base + off[k];
     const size_t n = hierarchy_nmax(hs[k]);
     void* xa = p;
     void* xb = p + align_up(8 * n);
     double* lx = reinterpret_cast<double*>(p + 2 * align_up(8 * n));
-    char* q = p + 3 * align_up(8 * n);
-    double* xo = x_on_device ? x_out[k] : reinterpret_cast<double*>(q);
-    if (!x_on_device) q += align_up(8 * n);
-    outs[k] = xo;
-    DevState* st = reinterpret_cast<DevState*>(q);
-    q += align_up(sizeof(DevState));
-    int* sched = reinterpret_cast<int*>(q);
-    q += align_up(4 * FV_SCHEDULE_CAP);
-    int* slen = reinterpret_cast<int*>(q);
-    fill_task(tasks[k], hs[k], o, 0, xa, xb, lx, xo, st, nullptr, 0, sched, slen);
+    double* xo = x_on_device ? x_out[k] : d_out + xoff[k];
+    fill_task(tasks[k], hs[k], o, 0, xa, xb, lx, xo, d_st + k, nullptr, 0,
+              d_sched + (size_t)k * FV_SCHEDULE_CAP, d_slen + k);
     long long work = 0;
     for (int l = 0; l < hs[k]->levels; ++l) work += hs[k]->lv[l].m + hs[k]->lv[l].n;
     tasks[k].work = work;
@@ -876,8 +913,8 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
                    [&](int a, int b) { return tasks[a].work > tasks[b].work; });
   std::vector<GraphTask> sorted(count);
   for (int k = 0; k < count; ++k) sorted[k] = tasks[order[k]];
-  GraphTask* d_tasks = reinterpret_cast<GraphTask*>(base + off[count]);
-  unsigned* queue = reinterpret_cast<unsigned*>(base + off[count] + align_up(sizeof(GraphTask) * count));
+  GraphTask* d_tasks = reinterpret_cast<GraphTask*>(base + o_tasks);
+  unsigned* queue = reinterpret_cast<unsigned*>(base + o_queue);
   FV_HIP(hipMemcpyAsync(d_tasks, sorted.data(), sizeof(GraphTask) * count, hipMemcpyHostToDevice, s));
   FV_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned), s));
   int dev = 0, ncu = 256;
@@ -902,19 +939,21 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
   FV_HIP(hipGetLastError());
   FV_HIP(hipEventRecord(e1, s));
   std::vector<DevState> hst(count);
-  std::vector<int> hsched(count * (size_t)FV_SCHEDULE_CAP);
+  std::vector<int> hsched(stats ? count * (size_t)FV_SCHEDULE_CAP : 0);
   std::vector<int> hslen(count);
-  for (int k = 0; k < count; ++k) {
-    FV_HIP(hipMemcpyAsync(&hst[k], tasks[k].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipMemcpyAsync(&hslen[k], tasks[k].sched_len, sizeof(int), hipMemcpyDeviceToHost, s));
-    if (stats)
-      FV_HIP(hipMemcpyAsync(&hsched[(size_t)k * FV_SCHEDULE_CAP], tasks[k].sched,
-                            sizeof(int) * FV_SCHEDULE_CAP, hipMemcpyDeviceToHost, s));
-    if (!x_on_device)
-      FV_HIP(hipMemcpyAsync(x_out[k], outs[k], sizeof(double) * hierarchy_nmax(hs[k]),
-                            hipMemcpyDeviceToHost, s));
-  }
+  std::vector<double> hout(xoff[count]);
+  FV_HIP(hipMemcpyAsync(hst.data(), d_st, sizeof(DevState) * count, hipMemcpyDeviceToHost, s));
+  FV_HIP(hipMemcpyAsync(hslen.data(), d_slen, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  if (stats)
+    FV_HIP(hipMemcpyAsync(hsched.data(), d_sched, sizeof(int) * FV_SCHEDULE_CAP * count,
+                          hipMemcpyDeviceToHost, s));
+  if (!hout.empty())
+    FV_HIP(hipMemcpyAsync(hout.data(), d_out, sizeof(double) * hout.size(), hipMemcpyDeviceToHost,
+                          s));
   FV_HIP(hipStreamSynchronize(s));
+  if (!x_on_device)
+    for (int k = 0; k < count; ++k)
+      std::memcpy(x_out[k], hout.data() + xoff[k], sizeof(double) * (xoff[k + 1] - xoff[k]));
   float ms = 0.0f;
   FV_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
