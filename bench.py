@@ -1,11 +1,24 @@
 """Benchmark: Fiedler solves per second on one MI355X, with the roofline of the
 level-0 smoothing kernel and the CPU oracle timed beside it.
 
-Workload: 1024 x 1000 5-point grid (n = 1,024,000, 4,091,952 stored
-off-diagonals), edge weights iid U[0.5, 1.5] from SplitMix64 seed 2, input
-CSR resident in HBM.  One step = the whole path: device setup (matching,
-aggregation, Galerkin, colouring) plus the cascadic solve to a finest-level
-residual ||L x - lambda x|| / ||x|| <= 1e-6, in FP32-mixed precision.
+Default workload (``--workload grid``): 1024 x 1000 5-point grid (n =
+1,024,000, 4,091,952 stored off-diagonals), edge weights iid U[0.5, 1.5] from
+SplitMix64 seed 2, input CSR resident in HBM.  One step = the whole path:
+device setup (matching, aggregation, Galerkin, colouring) plus the cascadic
+solve to a finest-level residual ||L x - lambda x|| / ||x|| <= 1e-6, in
+FP32-mixed precision.
+
+Other workloads (one JSON line each):
+* ``rgg``: random geometric graph, 4M points in the unit square, mean degree
+  ~8 (largest component), FP32-mixed, cascade plus at most 20 finest rounds;
+  the residual reached is reported (lambda_2 is nearly double on a square
+  domain, which stalls the residual near 1e-6).
+* ``batch``: 4096 graphs (n log-uniform in [200, 50k], half 4:3 grids, half
+  Erdos-Renyi G(n, 6/(n-1)) largest components), one batched FP32-mixed launch
+  against a loop of per-graph FP64 solves on the same hierarchies.
+* ``serve``: open-loop Poisson requests against the serving loop (pool of
+  request graphs, n log-uniform in [1e3, 2e6], 70% random geometric / 30%
+  grids), latency from the scheduled arrival, p50/p99.
 
 Prints one JSON line.
 """
@@ -23,11 +36,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# SOR factor 1.9, per-phase cosine tolerance 3e-12, at most 40 sweeps and one
+# SOR factor 1.9, per-phase cosine tolerance 3e-12, at most 30 sweeps and one
 # power step per phase, finest rounds repeated until the residual is <= 1e-6.
-SOLVE = dict(seed=1, tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=40, max_pi=1,
+SOLVE = dict(seed=1, tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1,
              max_outer=400, max_coarsest=100000)
 N_COARSE = 25
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def pass_bytes(n, m, prec):
@@ -36,30 +53,47 @@ def pass_bytes(n, m, prec):
     return (8 * m + 4 * (n + 1) + 8 * n) if prec == "fp32" else (12 * m + 4 * (n + 1) + 16 * n)
 
 
-def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name):
+    """Device time of one level-0 sweep from two replayed schedules that differ
+    only in the number of level-0 sweeps (HIP events inside the library)."""
+    J = h.levels - 1
+    S0, S1 = 2, 2 + sweeps
+
+    def sched(s):
+        return [0] + [0, 0] * (J - 1) + [s, 0]
+
+    def dev_ms(s):
+        return min(fv.fiedler_solve(ctx, h, x_out=x, prec=prec, seed=1, omega=SOLVE["omega"],
+                                    replay=sched(s)).t_solve_ms for _ in range(3))
+
+    t_a, t_b = dev_ms(S0), dev_ms(S1)
+    log(f"roofline replays: {S0} sweeps {t_a:.3f} ms, {S1} sweeps {t_b:.3f} ms")
+    t_sweep_ms = (t_b - t_a) / (S1 - S0)
+    n0, m0, c0 = h.n[0], h.nnz[0], h.colours[0]
+    bytes_sweep = pass_bytes(n0, m0, prec)
+    achieved = bytes_sweep / (t_sweep_ms * 1e-3) / 1e9
+    return {
+        "kernel": f"{kernel_name}<{'float' if prec == 'fp32' else 'double'}> (level 0)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_sweep": bytes_sweep,
+        "launches_per_sweep": c0,
+        "avg_launch_us": round(t_sweep_ms * 1e3 / c0, 3),
+        "sweep_us": round(t_sweep_ms * 1e3, 3),
+    }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--roofline-sweeps", type=int, default=200)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-
+def single_graph(args, g, solve, metric, workload, cpu_fn, require_converged=True):
+    """Timed steps of setup + solve on one device-resident graph."""
     import numpy as np
 
-    import gen
     import paper_1602_04386_amd as fv
     from paper_1602_04386_amd.devmem import DeviceArray, hip
 
-    g = gen.grid_1024x1000()
     ctx = fv.Context(0)
     # Input CSR and output resident in HBM before any timed work.
     rp, col, w = DeviceArray(g.rowptr), DeviceArray(g.col), DeviceArray(g.w)
@@ -68,13 +102,13 @@ def main():
 
     def step():
         h = fv.build_hierarchy(ctx, g.n, rp, col, w, is_adjacency=True, n_coarse=N_COARSE)
-        r = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, **SOLVE)
+        r = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, **solve)
         return h, r
 
     for _ in range(args.warmup):
         h, r = step()
         h.free()
-    log(f"warmup done: residual {r.residual:.3e}")
+        log(f"warmup done: residual {r.residual:.3e}")
     lat, res, lams, sched = [], [], [], None
     hip().hipDeviceSynchronize()
     t0 = time.perf_counter()
@@ -90,56 +124,35 @@ def main():
     hip().hipDeviceSynchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
-    ok = all(v <= SOLVE["tol_res"] for v in res)
+    ok = all(v <= solve["tol_res"] for v in res)
+    log(f"timed steps: {ms_per_step:.2f} ms/step, residual max {max(res):.3e}")
 
     # Setup and solve split (one more step, timed separately).
     ts = time.perf_counter()
     h = fv.build_hierarchy(ctx, g.n, rp, col, w, is_adjacency=True, n_coarse=N_COARSE)
     t_setup = (time.perf_counter() - ts) * 1e3
     ts = time.perf_counter()
-    r = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, **SOLVE)
+    r = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, **solve)
     t_solve = (time.perf_counter() - ts) * 1e3
-
-    # Roofline of the level-0 smoothing kernel: two replayed schedules that
-    # differ only in the number of level-0 sweeps; the device-time difference
-    # divided by the sweep count is one sweep (ncolours launches).
     J = h.levels - 1
-    S0, S1 = 2, 2 + args.roofline_sweeps
-
-    def sweep_sched(s):
-        return [0] + [0, 0] * (J - 1) + [s, 0]
-
-    def dev_ms(s):
-        best = float("inf")
-        for _ in range(3):
-            rr = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, seed=1,
-                                  replay=sweep_sched(s))
-            best = min(best, rr.t_solve_ms)
-        return best
-
-    t_a, t_b = dev_ms(S0), dev_ms(S1)
-    log(f"roofline replays: {S0} sweeps {t_a:.3f} ms, {S1} sweeps {t_b:.3f} ms")
-    t_sweep_ms = (t_b - t_a) / (S1 - S0)
-    n0, m0, c0 = h.n[0], h.nnz[0], h.colours[0]
-    bytes_sweep = pass_bytes(n0, m0, args.prec)
-    achieved = bytes_sweep / (t_sweep_ms * 1e-3) / 1e9
+    roof = level0_roofline(fv, ctx, h, x, args.prec, args.roofline_sweeps, "k_gs_tile")
     h.free()
 
-    # The same solve in the other precision, on the same hierarchy build, for
-    # the FP32-mixed versus FP64 comparison (eigenvalue difference, solves/s).
+    # The same solve in the other precision, for the FP32-mixed versus FP64
+    # comparison (eigenvalue difference, solves/s).
     other = "fp64" if args.prec == "fp32" else "fp32"
     t_o, r_o = [], None
     for _ in range(2):
         ts = time.perf_counter()
         h = fv.build_hierarchy(ctx, g.n, rp, col, w, is_adjacency=True, n_coarse=N_COARSE)
-        r_o = fv.fiedler_solve(ctx, h, x_out=x, prec=other, **SOLVE)
+        r_o = fv.fiedler_solve(ctx, h, x_out=x, prec=other, **solve)
         t_o.append(time.perf_counter() - ts)
         h.free()
     log(f"{other} leg: {min(t_o) * 1e3:.1f} ms, residual {r_o.residual:.3e}")
 
     out = {
-        "metric": "Fiedler solves/s at residual<=1e-6 (grid 1024x1000, setup+solve)",
-        "value": round(args.steps / elapsed, 4) if ok else 0.0,
+        "metric": metric,
+        "value": round(args.steps / elapsed, 4) if (ok or not require_converged) else 0.0,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -153,56 +166,314 @@ def main():
         "dtype": "fp32-mixed" if args.prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "grid 1024x1000, weights iid U[0.5,1.5] (SplitMix64 seed 2), "
-                        "n=1024000, nnz=4091952",
-            "n_coarse": N_COARSE, "solve": SOLVE, "levels": len(levels[0]),
+            "workload": workload,
+            "n_coarse": N_COARSE,
+            "solve": solve,
+            "levels": len(levels[0]),
             "level_n": levels[0], "level_colours": levels[2],
             "residual_max": max(res), "lambda": lams[-1], "converged": ok,
             "setup_ms": round(t_setup, 3), "solve_ms": round(t_solve, 3),
             "schedule_head": sched[:12] if sched else None,
             "finest_rounds": (len(sched) - 1 - 2 * J) // 2 if sched else None,
         },
-        "roofline": {
-            "kernel": "k_gs_tile<float> (level 0)" if args.prec == "fp32"
-                      else "k_gs_tile<double> (level 0)",
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "bytes_per_sweep": bytes_sweep,
-            "launches_per_sweep": c0,
-            "avg_launch_us": round(t_sweep_ms * 1e3 / c0, 3),
-            "sweep_us": round(t_sweep_ms * 1e3, 3),
+        "roofline": roof,
+        "other_precision": {
+            "dtype": "f64" if other == "fp64" else "fp32-mixed",
+            "value": round(1.0 / min(t_o), 4),
+            "unit": "solves/s", "residual": r_o.residual, "lambda": r_o.lam,
+            "lambda_rel_diff": abs(r_o.lam - lams[-1]) / abs(r_o.lam),
         },
-    }
-    out["other_precision"] = {
-        "dtype": "f64" if other == "fp64" else "fp32-mixed",
-        "value": round(1.0 / min(t_o), 4) if r_o.residual <= SOLVE["tol_res"] else 0.0,
-        "unit": "solves/s", "residual": r_o.residual, "lambda": r_o.lam,
-        "lambda_rel_diff": abs(r_o.lam - lams[-1]) / abs(r_o.lam),
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, args.prec)
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_fn(g)
+    ctx.close()
+    return out
 
 
-def cpu_baseline(g, prec):
-    """The FP64 oracle, one thread, on one full setup + solve of the same
-    grid with the same solve parameters (a bounded sample)."""
-    import oracle
+def run_grid(args):
+    import gen
 
-    oracle.build()
+    g = gen.grid_1024x1000()
+
+    def cpu(g):
+        """The FP64 oracle, one thread, on one full setup + solve of the same
+        grid with the same solve parameters (a bounded sample)."""
+        import oracle
+
+        oracle.build()
+        t = time.perf_counter()
+        h = oracle.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=N_COARSE)
+        t_setup = time.perf_counter() - t
+        r = h.solve(**SOLVE)
+        total = time.perf_counter() - t
+        return {"value": round(1.0 / total, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"one setup+solve of the same grid, FP64, same parameters "
+                          f"(setup {t_setup:.1f} s, total {total:.1f} s, residual {r.residual:.2e})"}
+
+    return single_graph(
+        args, g, SOLVE, "Fiedler solves/s at residual<=1e-6 (grid 1024x1000, setup+solve)",
+        "grid 1024x1000, weights iid U[0.5,1.5] (SplitMix64 seed 2), n=1024000, nnz=4091952", cpu)
+
+
+def run_rgg(args):
+    import gen
+
     t = time.perf_counter()
-    h = oracle.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=N_COARSE)
+    g = gen.rgg_4m()
+    log(f"generated rgg n={g.n} nnz={len(g.col)} in {time.perf_counter() - t:.1f} s")
+    solve = dict(SOLVE, max_outer=20)
+
+    def cpu(g):
+        """The oracle's setup and two level-0 sweeps of the same graph (a bounded
+        sample of the path; the full FP64 solve takes many minutes)."""
+        import oracle
+
+        oracle.build()
+        t = time.perf_counter()
+        h = oracle.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=N_COARSE)
+        t_setup = time.perf_counter() - t
+        J = h.nlevels - 1
+        t = time.perf_counter()
+        h.solve(seed=1, omega=SOLVE["omega"], replay=[0] + [0, 0] * (J - 1) + [2, 0])
+        t_sw = (time.perf_counter() - t) / 2
+        return {"value": round(1.0 / t_sw, 4), "unit": "level-0 sweeps/s", "cores": 1,
+                "kind": "oracle",
+                "sample": f"oracle setup ({t_setup:.1f} s) and 2 level-0 sweeps "
+                          f"({t_sw * 1e3:.0f} ms each) of the same graph, FP64"}
+
+    return single_graph(
+        args, g, solve,
+        "Fiedler solves/s (RGG 4M, setup + cascade + <=20 finest rounds; residual reported)",
+        f"random geometric graph, 4M points in the unit square, r=sqrt(8/(pi n)), weights "
+        f"exp(-d^2/r^2), largest component n={g.n}, nnz={len(g.col)} (SplitMix64 seed 3)", cpu,
+        require_converged=False)
+
+
+def run_batch(args):
+    import numpy as np
+
+    import gen
+    import paper_1602_04386_amd as fv
+    from paper_1602_04386_amd.devmem import DeviceArray, hip
+
+    t = time.perf_counter()
+    graphs = gen.batch_mix(args.batch_count)
+    log(f"generated {len(graphs)} graphs, sum n={sum(g.n for g in graphs)} in "
+        f"{time.perf_counter() - t:.1f} s")
+    solve = dict(SOLVE, max_outer=200)
+    ctx = fv.Context(0)
+    dev = [(DeviceArray(g.rowptr), DeviceArray(g.col), DeviceArray(g.w)) for g in graphs]
+    xs = [DeviceArray(dtype=np.float64, count=g.n) for g in graphs]
+    hip().hipDeviceSynchronize()
+    t = time.perf_counter()
+    hs = []
+    for g, d in zip(graphs, dev):
+        hs.append(fv.build_hierarchy(ctx, g.n, *d, is_adjacency=True, n_coarse=N_COARSE))
+        if len(hs) % 512 == 0:
+            log(f"  built {len(hs)} hierarchies in {time.perf_counter() - t:.1f} s")
+    hip().hipDeviceSynchronize()
     t_setup = time.perf_counter() - t
-    r = h.solve(**SOLVE)
-    total = time.perf_counter() - t
-    return {"value": round(1.0 / total, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one setup+solve of the same grid, FP64, same parameters "
-                      f"(setup {t_setup:.1f} s, total {total:.1f} s, residual {r.residual:.2e})"}
+    log(f"setup of {len(hs)} hierarchies: {t_setup:.2f} s")
+
+    # warm-up on a slice, then the whole batch once in each mode
+    fv.fiedler_solve_batch(ctx, hs[:64], x_out=xs[:64], prec="fp32", **solve)
+    t = time.perf_counter()
+    rb = fv.fiedler_solve_batch(ctx, hs, x_out=xs, prec="fp32", **solve)
+    t_b32 = time.perf_counter() - t
+    log(f"batched FP32: {t_b32:.2f} s")
+    # Per-graph loops (one fv_fiedler_solve call per graph) on every
+    # args.loop_stride-th graph: a uniform sample of the same mix, so that their
+    # solves/s estimate the whole batch's in bounded time.
+    sub = list(range(0, len(hs), args.loop_stride))
+
+    def loop(prec):
+        out, t = {}, time.perf_counter()
+        for k, i in enumerate(sub):
+            out[i] = fv.fiedler_solve(ctx, hs[i], x_out=xs[i], prec=prec, **solve)
+            if (k + 1) % 64 == 0:
+                log(f"  per-graph {prec}: {k + 1}/{len(sub)} in {time.perf_counter() - t:.1f} s")
+        return out, time.perf_counter() - t
+
+    r64, t_l64 = loop("fp64")
+    log(f"per-graph FP64 loop over {len(sub)} graphs: {t_l64:.2f} s")
+    r32, t_l32 = loop("fp32")
+    log(f"per-graph FP32 loop over {len(sub)} graphs: {t_l32:.2f} s")
+
+    kind = ["grid" if g.name.startswith("grid") else "er" for g in graphs]
+    tol = solve["tol_res"]
+
+    def conv(rs, idx):
+        out = {}
+        for k in ("grid", "er"):
+            ii = [i for i in idx if kind[i] == k]
+            out[k] = f"{sum(1 for i in ii if rs[i].residual <= tol)}/{len(ii)}"
+        return out
+
+    both = [i for i in sub if rb[i].residual <= tol and r64[i].residual <= tol]
+    dl = max((abs(rb[i].lam - r64[i].lam) / abs(r64[i].lam) for i in both), default=None)
+    count = len(hs)
+    rate64, rate32 = len(sub) / t_l64, len(sub) / t_l32
+    out = {
+        "metric": "batched Fiedler solves/s (4096 mixed graphs, FP32-mixed, one launch)",
+        "value": round(count / t_b32, 2),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(t_b32 * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32-mixed", "data": "synthetic",
+        "config": {
+            "workload": f"{count} graphs, n log-uniform [200, 50000] (SplitMix64 seed 4), half 4:3 "
+                        f"grids U[0.5,1.5], half Erdos-Renyi G(n, 6/(n-1)) largest components "
+                        f"U[0.5,1.5]; sum n={sum(g.n for g in graphs)}",
+            "solve": solve, "setup_s": round(t_setup, 3),
+        },
+        "per_graph_fp64": {"value": round(rate64, 2), "unit": "solves/s",
+                           "sample": f"every {args.loop_stride}th graph ({len(sub)} graphs)",
+                           "seconds": round(t_l64, 3), "converged": conv(r64, sub)},
+        "per_graph_fp32": {"value": round(rate32, 2), "unit": "solves/s",
+                           "sample": f"every {args.loop_stride}th graph ({len(sub)} graphs)",
+                           "seconds": round(t_l32, 3), "converged": conv(r32, sub)},
+        "batched_fp32": {"seconds": round(t_b32, 3), "converged": conv(rb, range(count)),
+                         "lambda_rel_diff_vs_fp64_max": dl,
+                         "speedup_vs_per_graph_fp64": round(count / t_b32 / rate64, 3)},
+    }
+    ctx.close()
+    return out
+
+
+def run_serve(args):
+    import numpy as np
+
+    import gen
+    import paper_1602_04386_amd as fv
+
+    t = time.perf_counter()
+    pool = gen.serve_pool(args.pool)
+    log(f"generated pool of {len(pool)} graphs, sum n={sum(g.n for g in pool)} in "
+        f"{time.perf_counter() - t:.1f} s")
+    solve = dict(SOLVE, max_outer=10)
+    ctx = fv.Context(0)
+    srv = fv.Server(ctx, max_inflight=64, queue_capacity=1 << 16, cache_hierarchies=True,
+                    n_coarse=N_COARSE, prec="fp32", **solve)
+
+    def wait_all(tickets, limit_s):
+        done = {}
+        t_start = time.perf_counter()
+        t_log = t_start
+        while len(done) < len(tickets) and time.perf_counter() < t_start + limit_s:
+            for tk in tickets:
+                if tk not in done:
+                    r = srv.poll(tk)
+                    if r is not None:
+                        done[tk] = (time.perf_counter(), r[0])
+            if time.perf_counter() - t_log > 10:
+                t_log = time.perf_counter()
+                log(f"  waiting: {len(done)}/{len(tickets)} done after {t_log - t_start:.0f} s")
+            time.sleep(0.0005)
+        return done
+
+    # Warm-up: every pool graph once (builds and caches its hierarchy).
+    t = time.perf_counter()
+    tks = [srv.submit(i, g) for i, g in enumerate(pool)]
+    wait_all(tks, 600)
+    log(f"warm-up (hierarchies cached): {time.perf_counter() - t:.1f} s")
+
+    # Closed-loop capacity: keep 64 requests in flight for a few seconds.
+    rng = gen.splitmix64(7, 1 << 16)
+    pick = [int(v % len(pool)) for v in rng]
+    t0 = time.perf_counter()
+    inflight, k, ncl = {}, 0, 0
+    while time.perf_counter() - t0 < args.capacity_s:
+        while len(inflight) < 64:
+            gi = pick[k % len(pick)]
+            inflight[srv.submit(gi, pool[gi])] = gi
+            k += 1
+        for tk in list(inflight):
+            if srv.poll(tk) is not None:
+                del inflight[tk]
+                ncl += 1
+        time.sleep(0.0005)
+    cap_rate = ncl / (time.perf_counter() - t0)
+    wait_all(list(inflight), 600)
+    log(f"closed-loop capacity: {cap_rate:.1f} solves/s")
+
+    # Open loop at the requested rate, or 80% of capacity if that is lower.
+    rate = min(args.rate, 0.8 * cap_rate)
+    arrivals = gen.poisson_arrivals(rate, args.duration, seed=5)
+    sub = {}
+    lat, stat, hits = [], [], 0
+    t0 = time.perf_counter()
+    i, t_log = 0, 0.0
+    while i < len(arrivals) or sub:
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i] <= now:
+            gi = pick[i % len(pick)]
+            sub[srv.submit(gi, pool[gi])] = arrivals[i]
+            i += 1
+        for tk in list(sub):
+            r = srv.poll(tk)
+            if r is not None:
+                lat.append((time.perf_counter() - t0 - sub.pop(tk)) * 1e3)
+                stat.append(r[0]["residual"])
+                hits += r[0]["cache_hit"]
+        if now > args.duration + 120:
+            break
+        if now - t_log > 5:
+            t_log = now
+            log(f"  open loop t={now:.0f} s: submitted {i}, outstanding {len(sub)}, done {len(lat)}")
+        time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    log(f"open loop: {len(lat)} of {len(arrivals)} requests in {wall:.1f} s")
+    srv.close()
+    ctx.close()
+    n_done = len(lat)
+    out = {
+        "metric": "served Fiedler solves/s and latency (Poisson arrivals, resident hierarchies)",
+        "value": round(n_done / wall, 2),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": n_done, "warmup": len(pool),
+        "ms_per_step": round(wall * 1e3 / max(n_done, 1), 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat else None,
+        "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32-mixed", "data": "synthetic",
+        "config": {
+            "workload": f"pool of {len(pool)} graphs, n log-uniform [1e3, 2e6] (SplitMix64 seed 5), "
+                        f"70% random geometric / 30% 4:3 grids; sum n={sum(g.n for g in pool)}",
+            "solve": solve,
+            "requested_rate": args.rate, "offered_rate": round(rate, 2),
+            "closed_loop_capacity": round(cap_rate, 2),
+            "saturated_at_requested_rate": args.rate > 0.8 * cap_rate,
+            "duration_s": args.duration, "requests": len(arrivals), "completed": n_done,
+            "cache_hit_rate": round(hits / max(n_done, 1), 4),
+            "residual_le_1e-6": round(sum(1 for v in stat if v <= 1e-6) / max(n_done, 1), 4),
+        },
+    }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--workload", default="grid", choices=["grid", "rgg", "batch", "serve"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--roofline-sweeps", type=int, default=200)
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--loop-stride", type=int, default=8)
+    ap.add_argument("--pool", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--capacity-s", type=float, default=5.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    run = {"grid": run_grid, "rgg": run_rgg, "batch": run_batch, "serve": run_serve}[args.workload]
+    print(json.dumps(run(args)))
 
 
 if __name__ == "__main__":

@@ -323,3 +323,30 @@ def batch_mix(count: int = 4096, seed: int = 4, nmin: int = 200, nmax: int = 500
         else:
             out.append(erdos_renyi(n, 6.0 / (n - 1), seed=s ^ 0x99))
     return out
+
+
+def serve_pool(count: int = 32, seed: int = 5, nmin: int = 1000, nmax: int = 2_000_000):
+    """Pool of request graphs: n log-uniform in [nmin, nmax]; a seeded coin
+    picks a random geometric graph (probability 0.7, largest component) or a
+    4:3 grid with U[0.5,1.5] weights."""
+    out = []
+    for g in range(count):
+        s = derive_seed(seed, g)
+        u = uniform01(s, 2)
+        n = int(round(math.exp(math.log(nmin) + u[0] * (math.log(nmax) - math.log(nmin)))))
+        if u[1] < 0.7:
+            out.append(rgg(n, s ^ 0x55))
+        else:
+            a = int(round(math.sqrt(4.0 * n / 3.0)))
+            b = max(2, int(round(n / a)))
+            out.append(grid(a, b, "uniform", seed=s ^ 0x33))
+    return out
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int = 5) -> np.ndarray:
+    """Arrival times in [0, duration) of a Poisson process of the given rate:
+    exponential gaps -ln(1 - u) / rate from SplitMix64 uniforms."""
+    count = int(rate * duration * 1.5) + 64
+    u = uniform01(seed, count)
+    t = np.cumsum(-np.log1p(-u) / rate)
+    return t[t < duration]

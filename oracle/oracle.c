@@ -435,22 +435,17 @@ void or_pi_apply(int32_t n, const int32_t* rp, const int32_t* col, const double*
 }
 
 /*
- * Whether row i takes part in a shifted sweep: its shifted diagonal d_i - rho
- * must be at least d_i / 2.  A row below that (rho not small against its
- * degree) keeps its value for the sweep, so the eigenvector stays a fixed
- * point of the sweep; such rows are corrected by the power-iteration phase.
- */
-static int or_row_active(double d, double rho) { return d > 0.0 && d - rho >= 0.5 * d; }
-
-/*
  * One Gauss-Seidel sweep (Algorithm 2) on (L - rho I) x = 0, the eigenproblem
  * written as a singular linear system with the current Rayleigh quotient as
- * the shift.  Rows are visited colour by colour (ascending colour, ascending
- * index inside a colour), in place:
- *   x_i <- (1 - omega) x_i + omega sum_j w_ij x_j / (d_i - rho),
- * d_i = sum_j w_ij, both sums in CSR order, for every active row (see
- * or_row_active); omega = 1 is Gauss-Seidel, rho = 0 the plain sweep on
- * L x = 0.
+ * the shift.  The splitting keeps Gauss-Seidel's own lower triangle D - W_l
+ * and moves the shift to the right-hand side with the other known values:
+ * (D - W_l) x' = (W_u + rho I) x.  Rows are visited colour by colour
+ * (ascending colour, ascending index inside a colour), in place:
+ *   x_i <- (1 - omega) x_i + omega (sum_j w_ij x_j + rho x_i) / d_i,
+ * d_i = sum_j w_ij, both sums in CSR order, x_j the newest values and x_i the
+ * row's value before its update.  An eigenvector with rho its eigenvalue is a
+ * fixed point; rho = 0 gives the plain sweep on L x = 0; omega = 1 is
+ * Gauss-Seidel.  Division is by d_i > 0 only, whatever rho is.
  */
 void or_gs_sweep(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
                  const int32_t* colour, int32_t ncolours, double rho, double omega, double* x) {
@@ -459,8 +454,8 @@ void or_gs_sweep(int32_t n, const int32_t* rp, const int32_t* col, const double*
       if (colour[i] != c) continue;
       double num = 0.0, den = 0.0;
       for (int64_t p = rp[i]; p < rp[i + 1]; ++p) { num += w[p] * x[col[p]]; den += w[p]; }
-      if (or_row_active(den, rho)) {
-        double g = num / (den - rho);
+      if (den > 0.0) {
+        double g = (num + rho * x[i]) / den;
         x[i] = omega == 1.0 ? g : (1.0 - omega) * x[i] + omega * g;
       }
     }
@@ -473,7 +468,7 @@ void or_gs_sweep_lex(int32_t n, const int32_t* rp, const int32_t* col, const dou
   for (int32_t i = 0; i < n; ++i) {
     double num = 0.0, den = 0.0;
     for (int64_t p = rp[i]; p < rp[i + 1]; ++p) { num += w[p] * x[col[p]]; den += w[p]; }
-    if (or_row_active(den, rho)) x[i] = num / (den - rho);
+    if (den > 0.0) x[i] = (num + rho * x[i]) / den;
   }
 }
 

@@ -349,17 +349,27 @@ def fiedler_solve(ctx: Context, h: Hierarchy, x_out=None, **kw) -> SolveResult:
     return _stats_to_result(st, x, lam.value, S)
 
 
-def fiedler_solve_batch(ctx: Context, hs: list, **kw) -> list:
-    """fv_fiedler_solve_batch over host outputs; returns one SolveResult per graph."""
+def fiedler_solve_batch(ctx: Context, hs: list, x_out=None, **kw) -> list:
+    """fv_fiedler_solve_batch; returns one SolveResult per graph.  x_out:
+    optional list of device arrays (n float64 each, data_ptr()); otherwise host
+    numpy arrays are returned."""
     o, keep = solve_opts(**kw)
     count = len(hs)
-    xs = [np.zeros(h.n[0]) for h in hs]
+    if x_out is None:
+        xs = [np.zeros(h.n[0]) for h in hs]
+        ptrs, on_dev = [x.ctypes.data for x in xs], 0
+    else:
+        if len(x_out) != count:
+            raise ValueError("x_out needs one device array per hierarchy")
+        xs = list(x_out)
+        ptrs, on_dev = [x.data_ptr() for x in xs], 1
     hp = (C.c_void_p * count)(*[h._h.value for h in hs])
-    xp = (C.c_void_p * count)(*[x.ctypes.data for x in xs])
+    xp = (C.c_void_p * count)(*ptrs)
     lam = (C.c_double * count)()
     stats = (fv_solve_stats * count)()
     ist = (C.c_int32 * count)()
-    st = lib().fv_fiedler_solve_batch(ctx.handle, count, hp, C.byref(o), xp, 0, lam, stats, ist)
+    st = lib().fv_fiedler_solve_batch(ctx.handle, count, hp, C.byref(o), xp, on_dev, lam, stats,
+                                      ist)
     del keep
     _check(st, "fv_fiedler_solve_batch")
     return [_stats_to_result(ist[k], xs[k], lam[k], stats[k]) for k in range(count)]

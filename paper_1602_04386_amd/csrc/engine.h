@@ -51,9 +51,8 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
     den += wj;
   }
   double u = xo;
-  const double a = den - rho;
-  if (den > 0.0 && a >= 0.5 * den) {
-    const double g = num / a;
+  if (den > 0.0) {
+    const double g = (num + rho * xo) / den;
     u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
   }
   const VT us = (VT)u;

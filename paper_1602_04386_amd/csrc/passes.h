@@ -91,9 +91,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_tile(LevelDesc L, int r0, int r1,
         den += wj;
       }
       double u = xo;
-      const double sh = den - rho;
-      if (den > 0.0 && sh >= 0.5 * den) {
-        const double g = num / sh;
+      if (den > 0.0) {
+        const double g = (num + rho * xo) / den;
         u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
       }
       const VT us = (VT)u;

@@ -42,12 +42,12 @@ struct WSel<double> {
 // Per-row arithmetic.
 // ---------------------------------------------------------------------------
 
-// Shifted Gauss-Seidel update of row i (Algorithm 2 on (L - rho I) x = 0):
-// x_i <- sum_j w_ij x_j / (d_i - rho), relaxed by omega, for rows whose shifted
-// diagonal d_i - rho is at least d_i / 2; other rows keep their value (the
-// eigenvector stays a fixed point).  Rows below lower_end were already updated
-// in this sweep and are read as stored; the others are read through the
-// pending normalisation.  Accumulates
+// Shifted Gauss-Seidel update of row i (Algorithm 2 on (L - rho I) x = 0 with
+// the splitting (D - W_l) x' = (W_u + rho I) x):
+// x_i <- (sum_j w_ij x_j + rho xhat_i) / d_i, relaxed by omega (an eigenvector
+// with rho its eigenvalue is a fixed point).  Rows below lower_end were
+// already updated in this sweep and are read as stored; the others are read
+// through the pending normalisation.  Accumulates
 // {sum u, sum u^2, sum u xhat_i, sum xhat_i, sum over already-updated
 // neighbours of w (u - x_j)^2} where u is the stored new value; the last term
 // adds up to u^T L u over the sweep (each edge counted by its later colour).
@@ -68,9 +68,8 @@ __device__ inline void row_gs(int i, const LevelDesc& L, VT* __restrict__ x, int
     den += wj;
   }
   double u = xo;
-  const double a = den - rho;
-  if (den > 0.0 && a >= 0.5 * den) {
-    const double g = num / a;
+  if (den > 0.0) {
+    const double g = (num + rho * xo) / den;
     u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
   }
   const VT us = (VT)u;
@@ -249,7 +248,6 @@ __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int 
 #pragma unroll
           for (int j = 0; j < kRegRow; ++j) l += wr[j] * (x - bcast(x, j));
         } else {
-#pragma unroll 8
           for (int j = 0; j < n; ++j) l += Wd[j * n + base] * (x - bcast(x, j));
         }
         l = has ? l : 0.0;

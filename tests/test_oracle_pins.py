@@ -300,19 +300,23 @@ def _colour_order(c):
 
 
 @pytest.mark.parametrize("omega", [1.0, 1.5])
-def test_gs_sweep_is_matrix_splitting(orc, omega):
+@pytest.mark.parametrize("rho", [0.05, 3.0])
+def test_gs_sweep_is_matrix_splitting(orc, omega, rho):
+    # rho = 3 exceeds the degree of some rows: no row is special-cased
     g = gen.random_connected(48, 17)
     c, k = orc.colour(g.n, g.rowptr, g.col, orc.level_seed(0, 0))
     x = np.sin(np.arange(g.n) * 0.7)
-    rho = 0.05
     W = dense_W(g.n, g.rowptr, g.col, g.w)
     d = W.sum(1)
+    assert d.min() < rho or rho < 1
     o = _colour_order(c)
     Wp = W[np.ix_(o, o)]
-    Dp = np.diag(np.maximum(d[o] - rho, 0.5 * d[o]))
+    Dp = np.diag(d[o])
     Wl, Wu = np.tril(Wp, -1), np.triu(Wp, 1)
-    # SOR splitting: (D - omega W_l) x' = ((1 - omega) D + omega W_u) x
-    xp = np.linalg.solve(Dp - omega * Wl, ((1 - omega) * Dp + omega * Wu) @ x[o])
+    # SOR on the splitting L - rho I = (D - W_l) - (W_u + rho I):
+    # (D - omega W_l) x' = ((1 - omega) D + omega (W_u + rho I)) x
+    xp = np.linalg.solve(Dp - omega * Wl,
+                         ((1 - omega) * Dp + omega * (Wu + rho * np.eye(g.n))) @ x[o])
     expect = np.empty(g.n)
     expect[o] = xp
     got = oracle_sweep(orc, g, c, k, x, rho, omega)
@@ -328,7 +332,6 @@ def oracle_sweep(orc, g, c, k, x, rho, omega):
 
 
 def test_fiedler_vector_is_fixed_point_of_shifted_sweep(orc):
-    # weighted grid: lambda_2 < min degree / 2, so the shift guard is inactive
     g = gen.grid(12, 10, "uniform", seed=1)
     L = dense_L(g.n, g.rowptr, g.col, g.w)
     ev, V = np.linalg.eigh(L)
@@ -424,6 +427,22 @@ def test_random_graph_vs_eigh(orc, seed):
     h, r = orc.solve_graph(g, n_coarse=8, **TIGHT)
     assert r.status == 0
     # residual bound (Kato-Temple): |rho - lambda_2| <= r^2 / (lambda_3 - rho)
+    assert abs(r.lam - ev[1]) <= r.residual ** 2 / (ev[2] - r.lam) + 1e-12
+    assert abs(r.lam - ev[1]) <= 1e-9 * ev[1]
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("omega", [1.0, 1.9])
+def test_erdos_renyi_with_pendants_vs_eigh(orc, seed, omega):
+    # expander-like graph whose lambda_2 is comparable to its smallest degrees:
+    # the shift then exceeds the degree of some rows, and the sweep must still
+    # converge to phi_2 (over-relaxed too)
+    g = gen.erdos_renyi(400, 6 / 399, 100 + seed)
+    L = dense_L(g.n, g.rowptr, g.col, g.w)
+    ev = np.linalg.eigvalsh(L)
+    assert np.diag(L).min() < 2 * ev[1]
+    h, r = orc.solve_graph(g, n_coarse=8, omega=omega, **TIGHT)
+    assert r.status == 0
     assert abs(r.lam - ev[1]) <= r.residual ** 2 / (ev[2] - r.lam) + 1e-12
     assert abs(r.lam - ev[1]) <= 1e-9 * ev[1]
 
