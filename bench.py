@@ -453,6 +453,43 @@ def run_serve(args):
     return out
 
 
+def run_counters_probe(args):
+    """Short run for hardware-counter passes: one 256 MiB device-to-device
+    copy (the calibration kernel, known bytes), then the level-0 sweeps of the
+    default workload replayed (args.probe_sweeps of them) on a fresh hierarchy."""
+    import numpy as np
+
+    import gen
+    import paper_1602_04386_amd as fv
+    from paper_1602_04386_amd.devmem import DeviceArray, hip
+
+    nbytes = 256 << 20
+    src = DeviceArray(dtype=np.uint8, count=nbytes)
+    dst = DeviceArray(dtype=np.uint8, count=nbytes)
+    hip().hipMemcpy(C_void(dst.data_ptr()), C_void(src.data_ptr()), nbytes, 3)  # D2D
+    hip().hipDeviceSynchronize()
+    g = gen.grid_1024x1000()
+    ctx = fv.Context(0)
+    rp, col, w = DeviceArray(g.rowptr), DeviceArray(g.col), DeviceArray(g.w)
+    x = DeviceArray(dtype=np.float64, count=g.n)
+    h = fv.build_hierarchy(ctx, g.n, rp, col, w, is_adjacency=True, n_coarse=N_COARSE)
+    J = h.levels - 1
+    r = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, seed=1, omega=SOLVE["omega"],
+                         replay=[0] + [0, 0] * (J - 1) + [args.probe_sweeps, 0])
+    out = {"probe": "counters", "copy_bytes": nbytes, "level0_sweeps": args.probe_sweeps,
+           "level0_colours": h.colours[0], "bytes_per_sweep": pass_bytes(h.n[0], h.nnz[0], args.prec),
+           "level0_rows": h.n[0], "level0_nnz": h.nnz[0], "t_solve_ms": r.t_solve_ms}
+    h.free()
+    ctx.close()
+    return out
+
+
+def C_void(p):
+    import ctypes
+
+    return ctypes.c_void_p(p)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,10 +505,16 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--capacity-s", type=float, default=5.0)
+    ap.add_argument("--counters-probe", action="store_true",
+                    help="short run for rocprofv3 --pmc passes (copy calibration + level-0 sweeps)")
+    ap.add_argument("--probe-sweeps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.counters_probe:
+        print(json.dumps(run_counters_probe(args)))
+        return
     run = {"grid": run_grid, "rgg": run_rgg, "batch": run_batch, "serve": run_serve}[args.workload]
     print(json.dumps(run(args)))
 

@@ -180,12 +180,6 @@ fv_status fv_context_create(int device, size_t hbm_budget_bytes, fv_context** ou
       delete c;
       return FV_E_DEVICE;
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 256, hipHostMallocDefault) !=
-        hipSuccess) {
-      (void)hipStreamDestroy(c->stream);
-      delete c;
-      return FV_E_DEVICE;
-    }
     *out = c;
     return FV_OK;
   })
@@ -194,10 +188,9 @@ fv_status fv_context_create(int device, size_t hbm_budget_bytes, fv_context** ou
 void fv_context_destroy(fv_context* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  (void)hipStreamSynchronize(c->stream);
-  if (c->ws) (void)hipFree(c->ws);
+  (void)hipDeviceSynchronize();
+  fv::release_scratch(c, c->scratch);
   fv::block_trim(c);
-  if (c->pinned) (void)hipHostFree(c->pinned);
   (void)hipStreamDestroy(c->stream);
   delete c;
 }

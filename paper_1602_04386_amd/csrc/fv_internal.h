@@ -140,16 +140,25 @@ struct Level {
 }  // namespace fv
 
 // Opaque handles of the public ABI.
+namespace fv {
+// Workspace of the single-graph solve: device scratch (grown on demand,
+// counted against the budget) and a small pinned host buffer for flags.  The
+// context owns one; each serving worker owns its own so that solves on
+// different streams never share it.
+struct SolveScratch {
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* pinned = nullptr;
+};
+}  // namespace fv
+
 struct fv_context {
   int device = 0;
   hipStream_t stream = nullptr;
   size_t budget = 0;   // 0 = unbounded
   size_t in_use = 0;   // bytes held by live hierarchies and workspaces
   std::mutex mu;       // guards in_use (the server's threads share the context)
-  // reusable single-solve workspace
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  int* pinned = nullptr;  // small pinned host buffer for flag readback
+  fv::SolveScratch scratch;  // workspace of fv_fiedler_solve
   // Device blocks released by finished work, kept for reuse so that building
   // and freeing hierarchies does not pay hipMalloc / hipFree every time.
   std::multimap<size_t, void*> cache;      // block size -> block
@@ -191,6 +200,11 @@ size_t hierarchy_nmax(const fv_hierarchy* h);
 // Solve (solve.hip).
 fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
                     double* x_out, int x_on_device, double* lambda_out, fv_solve_stats* stats);
+// The same on a given stream and workspace (the server's workers).
+fv_status solve_one_with(fv_context* ctx, SolveScratch& sc, const fv_hierarchy* h,
+                         const fv_solve_opts* o, double* x_out, int x_on_device,
+                         double* lambda_out, fv_solve_stats* stats, hipStream_t s);
+void release_scratch(fv_context* ctx, SolveScratch& sc);
 fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* h,
                       const fv_solve_opts* o, double* const* x_out, int x_on_device,
                       double* lambda_out, fv_solve_stats* stats, fv_status* item_status,

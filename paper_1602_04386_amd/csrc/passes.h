@@ -2,12 +2,14 @@
 // per-row arithmetic).
 //
 // Each pass kernel handles tiles of kBlock consecutive rows (solve order).  A
-// tile first stages its row pointers, the column indices and weights of its
-// CSR slice, and the neighbour values those columns gather, in LDS: the CSR
-// slice is read with unit-stride loads and all gathers of the tile are in
-// flight together.  Each thread then reduces its own row from LDS in CSR
-// order, the same arithmetic as the direct row functions.  A tile whose slice
-// exceeds kTileNnz entries falls back to direct loads.
+// tile first stages its row pointers in LDS, then walks its rows in chunks
+// whose CSR slice fits kTileNnz entries: the chunk's column indices, weights
+// and the neighbour values those columns gather are staged in LDS with
+// unit-stride loads and all gathers of the chunk in flight together, and each
+// thread then reduces its own row from LDS in CSR order, the same arithmetic
+// as the direct row functions.  Usually the whole tile is one chunk; dense
+// tiles (irregular graphs put their high-degree vertices in the last colours)
+// take two or three, and a single row longer than kTileNnz uses direct loads.
 //
 // A pass writes one partial-sum slot per block; a one-block finishing kernel
 // reduces the slots in a fixed order and updates the device state.  The
@@ -16,6 +18,7 @@
 #pragma once
 
 constexpr int kTileNnz = 2048;
+constexpr int kStageU = kTileNnz / kBlock;  // staged entries per thread and round
 
 template <class WT, class XT>
 struct TileLds {
@@ -25,25 +28,73 @@ struct TileLds {
   XT x[kTileNnz];
 };
 
-// Stages rows [rs, re) (re - rs <= kBlock).  Returns the CSR offset of the
-// tile, or -1 when the slice is too long to stage.
-template <class WT, class XT, class G>
-__device__ inline int stage_tile(const LevelDesc& L, const WT* __restrict__ w, int rs, int re,
-                                 TileLds<WT, XT>& T, G gather) {
+// Walks the rows [rs, re) (re - rs <= kBlock) of a tile chunk by chunk.  For
+// each chunk it stages the CSR slice and gather(col) in LDS, then calls
+// body(t, a, e) in the thread of every row rs + t of the chunk, [a, e) being
+// that row's entries in T.  A row longer than kTileNnz is passed to
+// direct(t) instead.  Every thread of the block must call; the rows of one
+// tile never read values that the body writes.
+// skip (the phase's stop flag, loaded by the caller before this call) is
+// tested only after the row pointers are requested, so that both loads are in
+// flight together; when set, nothing else happens and false is returned.
+template <class WT, class XT, class G, class B, class D>
+__device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict__ w, int rs,
+                                       int re, TileLds<WT, XT>& T, int skip, G gather, B body,
+                                       D direct) {
   const int nr = re - rs;
   for (int k = threadIdx.x; k <= nr; k += blockDim.x) T.rp[k] = L.rp[rs + k];
   __syncthreads();
-  const int p0 = T.rp[0], cnt = T.rp[nr] - p0;
-  if (cnt > kTileNnz) return -1;
+  if (skip) return false;
   const int* __restrict__ col = L.col;
-  for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-    const int c = col[p0 + k];
-    T.col[k] = c;
-    T.w[k] = w[p0 + k];
-    T.x[k] = gather(c);
+  const int t = threadIdx.x;
+  int lo = 0;
+  while (lo < nr) {  // uniform: every bound comes from T.rp
+    const int p_lo = T.rp[lo];
+    if (T.rp[lo + 1] - p_lo > kTileNnz) {
+      if (t == lo) direct(t);
+      ++lo;
+      continue;
+    }
+    int a = lo + 1, b = nr;  // last row boundary whose slice still fits
+    while (a < b) {
+      const int mid = (a + b + 1) >> 1;
+      if (T.rp[mid] - p_lo <= kTileNnz) a = mid; else b = mid - 1;
+    }
+    const int hi = a, cnt = T.rp[hi] - p_lo;
+    // kStageU entries per thread per round: all index and weight loads of the
+    // round are issued first, then all gathers, so a round costs two memory
+    // round trips instead of two per entry.
+    for (int base = 0; base < cnt; base += kStageU * kBlock) {
+      int cc[kStageU];
+      WT ww[kStageU];
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u) {
+        const int k = base + u * kBlock + t;
+        cc[u] = k < cnt ? col[p_lo + k] : 0;
+        ww[u] = k < cnt ? w[p_lo + k] : WT(0);
+      }
+      XT xx[kStageU];
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u) {
+        const int k = base + u * kBlock + t;
+        xx[u] = k < cnt ? gather(cc[u]) : XT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u) {
+        const int k = base + u * kBlock + t;
+        if (k < cnt) {
+          T.col[k] = cc[u];
+          T.w[k] = ww[u];
+          T.x[k] = xx[u];
+        }
+      }
+    }
+    __syncthreads();
+    if (t >= lo && t < hi) body(t, T.rp[t] - p_lo, T.rp[t + 1] - p_lo);
+    __syncthreads();
+    lo = hi;
   }
-  __syncthreads();
-  return p0;
+  return true;
 }
 
 __global__ void k_phase_begin(DevState* st, int cap, int forced, double tol) {
@@ -68,49 +119,47 @@ __global__ __launch_bounds__(kBlock) void k_gs_tile(LevelDesc L, int r0, int r1,
                                                   int slot_base, double omega) {
   __shared__ TileLds<VT, VT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
-  if (st->done) return;
+  const int done = st->done;
   VT* x = st->cur ? xb : xa;
   const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int rs = r0 + b * kBlock, re = min(rs + kBlock, r1);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int p0 = stage_tile<VT, VT>(L, w, rs, re, T, [&](int c) { return x[c]; });
-  const int t = threadIdx.x, i = rs + t;
-  if (i < re) {
-    if (p0 < 0) {
-      row_gs<VT>(i, L, x, r0, mu, inv_s, rho, omega, acc);
-    } else {
-      const int a = T.rp[t] - p0, e = T.rp[t + 1] - p0;
-      const double xo = ((double)x[i] - mu) * inv_s;
-      double num = 0.0, den = 0.0;
-      for (int k = a; k < e; ++k) {
-        const double wj = (double)T.w[k];
-        const double xj = (double)T.x[k];
-        num += wj * (T.col[k] < r0 ? xj : (xj - mu) * inv_s);
-        den += wj;
-      }
-      double u = xo;
-      if (den > 0.0) {
-        const double g = (num + rho * xo) / den;
-        u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
-      }
-      const VT us = (VT)u;
-      x[i] = us;
-      const double ud = (double)us;
-      double en = 0.0;
-      for (int k = a; k < e; ++k)
-        if (T.col[k] < r0) {
-          const double d = ud - (double)T.x[k];
-          en += (double)T.w[k] * d * d;
+  const bool ran = for_tile_chunks<VT, VT>(
+      L, w, rs, re, T, done, [&](int c) { return x[c]; },
+      [&](int t, int a, int e) {
+        const int i = rs + t;
+        const double xo = ((double)x[i] - mu) * inv_s;
+        double num = 0.0, den = 0.0;
+        for (int k = a; k < e; ++k) {
+          const double wj = (double)T.w[k];
+          const double xj = (double)T.x[k];
+          num += wj * (T.col[k] < r0 ? xj : (xj - mu) * inv_s);
+          den += wj;
         }
-      acc[0] += ud;
-      acc[1] += ud * ud;
-      acc[2] += ud * xo;
-      acc[3] += xo;
-      acc[4] += en;
-    }
-  }
+        double u = xo;
+        if (den > 0.0) {
+          const double g = (num + rho * xo) / den;
+          u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
+        }
+        const VT us = (VT)u;
+        x[i] = us;
+        const double ud = (double)us;
+        double en = 0.0;
+        for (int k = a; k < e; ++k)
+          if (T.col[k] < r0) {
+            const double d = ud - (double)T.x[k];
+            en += (double)T.w[k] * d * d;
+          }
+        acc[0] += ud;
+        acc[1] += ud * ud;
+        acc[2] += ud * xo;
+        acc[3] += xo;
+        acc[4] += en;
+      },
+      [&](int t) { row_gs<VT>(rs + t, L, x, r0, mu, inv_s, rho, omega, acc); });
+  if (!ran) return;
   block_sum<kNP>(acc, lds);
   write_slot(part, stride, slot_base + blockIdx.x, acc);
 }
@@ -122,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride) {
   __shared__ TileLds<VT, VT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
-  if (st->done) return;
+  const int done = st->done;
   const int cur = st->cur;
   const VT* x = cur ? xb : xa;
   VT* y = cur ? xa : xb;
@@ -131,26 +180,24 @@ __global__ __launch_bounds__(kBlock) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int p0 = stage_tile<VT, VT>(L, w, rs, re, T, [&](int c) { return x[c]; });
-  const int t = threadIdx.x, i = rs + t;
-  if (i < re) {
-    if (p0 < 0) {
-      row_pi<VT>(i, L, x, y, mu, inv_s, sigma, acc);
-    } else {
-      const int a = T.rp[t] - p0, e = T.rp[t + 1] - p0;
-      const double xi = (double)x[i];
-      double lx = 0.0;
-      for (int k = a; k < e; ++k) lx += (double)T.w[k] * (xi - (double)T.x[k]);
-      const double xo = (xi - mu) * inv_s;
-      const VT ys = (VT)(sigma * xo - lx * inv_s);
-      y[i] = ys;
-      const double yd = (double)ys;
-      acc[0] += yd;
-      acc[1] += yd * yd;
-      acc[2] += yd * xo;
-      acc[3] += xo;
-    }
-  }
+  const bool ran = for_tile_chunks<VT, VT>(
+      L, w, rs, re, T, done, [&](int c) { return x[c]; },
+      [&](int t, int a, int e) {
+        const int i = rs + t;
+        const double xi = (double)x[i];
+        double lx = 0.0;
+        for (int k = a; k < e; ++k) lx += (double)T.w[k] * (xi - (double)T.x[k]);
+        const double xo = (xi - mu) * inv_s;
+        const VT ys = (VT)(sigma * xo - lx * inv_s);
+        y[i] = ys;
+        const double yd = (double)ys;
+        acc[0] += yd;
+        acc[1] += yd * yd;
+        acc[2] += yd * xo;
+        acc[3] += xo;
+      },
+      [&](int t) { row_pi<VT>(rs + t, L, x, y, mu, inv_s, sigma, acc); });
+  if (!ran) return;
   block_sum<kNP>(acc, lds);
   write_slot(part, stride, blockIdx.x, acc);
 }
@@ -173,28 +220,23 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(LevelDesc L, const SRC*
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int p0 = stage_tile<VT, VT>(L, w, rs, re, T, [&](int c) {
-    return (VT)(((double)xc[qs[c]] - mu) * inv_s);
-  });
-  const int t = threadIdx.x, i = rs + t;
-  if (i < re) {
-    if (p0 < 0) {
-      row_prolong<SRC, VT>(i, L, xc, xf, mu, inv_s, acc);
-    } else {
-      const VT vs = (VT)(((double)xc[qs[i]] - mu) * inv_s);
-      xf[i] = vs;
-      const double v = (double)vs;
-      const int a = T.rp[t] - p0, e = T.rp[t + 1] - p0;
-      double en = 0.0;
-      for (int k = a; k < e; ++k) {
-        const double d = v - (double)T.x[k];
-        en += (double)T.w[k] * d * d;
-      }
-      acc[0] += v;
-      acc[1] += v * v;
-      acc[4] += 0.5 * en;
-    }
-  }
+  for_tile_chunks<VT, VT>(
+      L, w, rs, re, T, 0, [&](int c) { return (VT)(((double)xc[qs[c]] - mu) * inv_s); },
+      [&](int t, int a, int e) {
+        const int i = rs + t;
+        const VT vs = (VT)(((double)xc[qs[i]] - mu) * inv_s);
+        xf[i] = vs;
+        const double v = (double)vs;
+        double en = 0.0;
+        for (int k = a; k < e; ++k) {
+          const double d = v - (double)T.x[k];
+          en += (double)T.w[k] * d * d;
+        }
+        acc[0] += v;
+        acc[1] += v * v;
+        acc[4] += 0.5 * en;
+      },
+      [&](int t) { row_prolong<SRC, VT>(rs + t, L, xc, xf, mu, inv_s, acc); });
   block_sum<kNP>(acc, lds);
   write_slot(part, stride, blockIdx.x, acc);
 }
@@ -212,25 +254,23 @@ __global__ __launch_bounds__(kBlock) void k_rq_tile(LevelDesc L, const VT* xa, c
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   double a3[3] = {0.0, 0.0, 0.0};
-  const int p0 = stage_tile<double, VT>(L, L.w64, rs, re, T, [&](int c) { return x[c]; });
-  const int t = threadIdx.x, i = rs + t;
-  if (i < re) {
-    if (p0 < 0) {
-      row_rq<VT>(i, L, x, mu, inv_s, lxo, a3);
-    } else {
-      const double xi = ((double)x[i] - mu) * inv_s;
-      double lx = 0.0, e = 0.0;
-      for (int k = T.rp[t] - p0; k < T.rp[t + 1] - p0; ++k) {
-        const double d = xi - ((double)T.x[k] - mu) * inv_s;
-        lx += T.w[k] * d;
-        e += T.w[k] * d * d;
-      }
-      lxo[i] = lx;
-      a3[0] += xi * xi;
-      a3[1] += 0.5 * e;
-      a3[2] = fmax(a3[2], fabs(xi));
-    }
-  }
+  for_tile_chunks<double, VT>(
+      L, L.w64, rs, re, T, 0, [&](int c) { return x[c]; },
+      [&](int t, int a, int e) {
+        const int i = rs + t;
+        const double xi = ((double)x[i] - mu) * inv_s;
+        double lx = 0.0, en = 0.0;
+        for (int k = a; k < e; ++k) {
+          const double d = xi - ((double)T.x[k] - mu) * inv_s;
+          lx += T.w[k] * d;
+          en += T.w[k] * d * d;
+        }
+        lxo[i] = lx;
+        a3[0] += xi * xi;
+        a3[1] += 0.5 * en;
+        a3[2] = fmax(a3[2], fabs(xi));
+      },
+      [&](int t) { row_rq<VT>(rs + t, L, x, mu, inv_s, lxo, a3); });
   const double mx = block_max(a3[2], lds);
   double t2[2] = {a3[0], a3[1]};
   block_sum<2>(t2, lds);

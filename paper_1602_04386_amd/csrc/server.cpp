@@ -2,7 +2,10 @@
 //
 // Worker threads, each with its own HIP stream, take up to their share of the
 // in-flight slots from the request queue, build (or reuse from the cache) the
-// requests' hierarchies, and run them as one persistent batched launch.  A
+// requests' hierarchies, and run the small ones (finest level up to
+// kServeBatchMaxN vertices) as one persistent batched launch, one workgroup
+// per graph, and the large ones one after another through the
+// multi-workgroup single-graph path with the worker's own workspace.  A
 // request that arrives while others run on the device is admitted by the next
 // worker whose launch finishes, so launches from different workers overlap on
 // the device.  Device memory for hierarchies and launch workspaces comes out
@@ -89,10 +92,15 @@ auto with_budget(fv_server* s, F f) -> decltype(f()) {
   }
 }
 
+// Finest-level size above which a request leaves the batched launch: one
+// workgroup per graph stops paying off once a level no longer fits its LDS.
+constexpr int kServeBatchMaxN = 16384;
+
 void worker_main(fv_server* s, int share) {
   (void)hipSetDevice(s->ctx->device);
   hipStream_t stream = nullptr;
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
+  fv::SolveScratch scratch;
   std::vector<uint64_t> batch;
   for (;;) {
     batch.clear();
@@ -175,12 +183,17 @@ void worker_main(fv_server* s, int share) {
         owned[k] = hs[k] ? 1 : 0;
       }
     }
-    // One batched launch for the admitted requests that have a hierarchy.
+    // One batched launch for the small admitted requests that have a
+    // hierarchy; the large ones run one by one below.
     std::vector<const fv_hierarchy*> run_h;
     std::vector<double*> run_x;
-    std::vector<size_t> run_k;
+    std::vector<size_t> run_k, solo_k;
     for (size_t k = 0; k < batch.size(); ++k)
       if (hs[k] && st[k] == FV_OK) {
+        if (fv::hierarchy_nmax(hs[k]) > (size_t)kServeBatchMaxN) {
+          solo_k.push_back(k);
+          continue;
+        }
         run_h.push_back(hs[k]);
         std::lock_guard<std::mutex> g(s->mu);
         run_x.push_back(s->reqs[batch[k]].req.x_out);
@@ -202,12 +215,38 @@ void worker_main(fv_server* s, int share) {
       }
     }
     for (size_t j = 0; j < run_k.size(); ++j) st[run_k[j]] = ist[j];
+    std::vector<double> solo_lam(solo_k.size(), 0.0), solo_res(solo_k.size(), 0.0);
+    for (size_t j = 0; j < solo_k.size(); ++j) {
+      const size_t k = solo_k[j];
+      double* xo;
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        xo = s->reqs[batch[k]].req.x_out;
+      }
+      fv_solve_stats S;
+      try {
+        st[k] = with_budget(s, [&] {
+          return fv::solve_one_with(s->ctx, scratch, hs[k], &s->opts.solve, xo, 0, &solo_lam[j],
+                                    &S, stream);
+        });
+        solo_res[j] = S.residual;  // FV_E_NOT_CONVERGED still fills x and lambda
+      } catch (const fv::Error& e) {
+        st[k] = e.st;
+      } catch (...) {
+        st[k] = FV_E_DEVICE;
+      }
+    }
     const auto t_done = Clock::now();
     std::lock_guard<std::mutex> g(s->mu);
     for (size_t j = 0; j < run_k.size(); ++j) {
       Request& r = s->reqs[batch[run_k[j]]];
       r.res.lambda = lam[j];
       r.res.residual = stats[j].residual;
+    }
+    for (size_t j = 0; j < solo_k.size(); ++j) {
+      Request& r = s->reqs[batch[solo_k[j]]];
+      r.res.lambda = solo_lam[j];
+      r.res.residual = solo_res[j];
     }
     for (size_t k = 0; k < batch.size(); ++k) {
       Request& r = s->reqs[batch[k]];
@@ -225,6 +264,8 @@ void worker_main(fv_server* s, int share) {
     s->inflight -= (int)batch.size();
     s->cv.notify_all();
   }
+  (void)hipStreamSynchronize(stream);
+  fv::release_scratch(s->ctx, scratch);
   (void)hipStreamDestroy(stream);
 }
 

@@ -638,32 +638,37 @@ static long long schedule_bytes(const fv_hierarchy* h, const int* sched, int len
   return b;
 }
 
+static void release_scratch_device(fv_context* ctx, SolveScratch& sc) {
+  if (sc.ws) dev_free(ctx, sc.ws, sc.ws_bytes, nullptr);
+  sc.ws = nullptr;
+  sc.ws_bytes = 0;
+}
+
+// Frees a workspace; the streams that used it must have been synchronised.
+void release_scratch(fv_context* ctx, SolveScratch& sc) {
+  release_scratch_device(ctx, sc);
+  if (sc.pinned) (void)hipHostFree(sc.pinned);
+  sc.pinned = nullptr;
+}
+
 template <class VT>
-static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
-                             double* x_out, int x_on_device, double* lambda_out,
-                             fv_solve_stats* stats, hipStream_t s) {
+static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarchy* h,
+                             const fv_solve_opts* o, double* x_out, int x_on_device,
+                             double* lambda_out, fv_solve_stats* stats, hipStream_t s) {
   const int J = h->levels - 1;
   const size_t nmax = hierarchy_nmax(h);
   int maxcol = 1;
   for (int l = 0; l < h->levels; ++l) maxcol = std::max(maxcol, h->lv[l].ncol);
   const size_t need = solve_workspace_bytes(nmax, maxcol);
-  if (ctx->ws_bytes < need) {
-    if (ctx->ws) {
-      budget_release(ctx, ctx->ws_bytes);
-      (void)hipFree(ctx->ws);
-      ctx->ws = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    budget_reserve(ctx, need);
-    if (hipMalloc(&ctx->ws, need) != hipSuccess) {
-      budget_release(ctx, need);
-      ctx->ws = nullptr;
-      throw Error(FV_E_NOMEM, "workspace allocation failed");
-    }
-    ctx->ws_bytes = need;
+  if (sc.ws_bytes < need) {
+    (void)hipDeviceSynchronize();  // the old workspace may be in use on any stream
+    release_scratch_device(ctx, sc);
+    sc.ws = dev_alloc(ctx, need, nullptr);
+    sc.ws_bytes = need;
   }
-  Workspace W = carve(ctx->ws, nmax, maxcol);
-  int* pinned = ctx->pinned;
+  if (!sc.pinned) FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&sc.pinned), 256, hipHostMallocDefault));
+  Workspace W = carve(sc.ws, nmax, maxcol);
+  int* pinned = sc.pinned;
 
   // Split: levels whose vector fits the engine's LDS go to the one-workgroup
   // engine; the rest to multi-workgroup passes.
@@ -836,12 +841,18 @@ static fv_status solve_one_t(fv_context* ctx, const fv_hierarchy* h, const fv_so
   return status;
 }
 
+fv_status solve_one_with(fv_context* ctx, SolveScratch& sc, const fv_hierarchy* h,
+                         const fv_solve_opts* o, double* x_out, int x_on_device,
+                         double* lambda_out, fv_solve_stats* stats, hipStream_t s) {
+  if (o->prec == FV_PREC_FP32_MIXED)
+    return solve_one_t<float>(ctx, sc, h, o, x_out, x_on_device, lambda_out, stats, s);
+  return solve_one_t<double>(ctx, sc, h, o, x_out, x_on_device, lambda_out, stats, s);
+}
+
 fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
                     double* x_out, int x_on_device, double* lambda_out, fv_solve_stats* stats) {
   hipStream_t s = o->stream ? static_cast<hipStream_t>(o->stream) : ctx->stream;
-  if (o->prec == FV_PREC_FP32_MIXED)
-    return solve_one_t<float>(ctx, h, o, x_out, x_on_device, lambda_out, stats, s);
-  return solve_one_t<double>(ctx, h, o, x_out, x_on_device, lambda_out, stats, s);
+  return solve_one_with(ctx, ctx->scratch, h, o, x_out, x_on_device, lambda_out, stats, s);
 }
 
 // ---------------------------------------------------------------------------

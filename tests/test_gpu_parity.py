@@ -245,3 +245,35 @@ def test_server_results_equal_batch(fv, ctx):
         assert info["status"] == 0
         assert np.array_equal(x, ref[gi].x)
     assert out[tickets[-1]][0]["cache_hit"]
+
+
+def test_server_large_requests_take_the_single_graph_path(fv, ctx):
+    # a finest level above the batched launch's limit runs through the
+    # multi-workgroup path on the worker's own workspace: same bits as the
+    # single-graph call, also while small requests run beside it
+    import time
+
+    big = gen.grid(160, 120, "uniform", seed=9)  # 19,200 vertices
+    small = [gen.grid(20 + k, 15, "uniform", seed=k) for k in range(3)]
+    kw = dict(prec="fp32", tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1,
+              max_outer=50)
+    srv = fv.Server(ctx, max_inflight=8, n_coarse=25, **kw)
+    tickets = [srv.submit(100, big)] + [srv.submit(k, g) for k, g in enumerate(small)]
+    tickets.append(srv.submit(100, big))  # cached hierarchy, second run
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 120:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.001)
+    srv.close()
+    assert len(out) == len(tickets)
+    h = fv.build_hierarchy_graph(ctx, big, n_coarse=25)
+    ref = fv.fiedler_solve(ctx, h, **kw)
+    for t in (tickets[0], tickets[-1]):
+        info, x = out[t]
+        assert info["status"] == ref.status
+        assert np.array_equal(x, ref.x) and info["lambda"] == ref.lam
