@@ -53,6 +53,24 @@ def pass_bytes(n, m, prec):
     return (8 * m + 4 * (n + 1) + 8 * n) if prec == "fp32" else (12 * m + 4 * (n + 1) + 16 * n)
 
 
+def measured_traffic(prec):
+    """HBM bytes per level-0 colour launch of the default workload, from the
+    calibrated FETCH_SIZE / WRITE_SIZE passes summarised in profiles/; None when
+    the kernel sources changed since those counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_gs_tile_grid1024x1000_fp32_traffic.json")
+    if prec != "fp32" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    sha = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            sha.update(f.read())
+    return rec["traffic_bytes"] if sha.hexdigest() == rec["source_sha256"] else None
+
+
 def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name):
     """Device time of one level-0 sweep from two replayed schedules that differ
     only in the number of level-0 sweeps (HIP events inside the library)."""
@@ -68,6 +86,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name):
 
     t_a, t_b = dev_ms(S0), dev_ms(S1)
     log(f"roofline replays: {S0} sweeps {t_a:.3f} ms, {S1} sweeps {t_b:.3f} ms")
+    traffic = measured_traffic(prec) if h.n[0] == 1024000 else None
     t_sweep_ms = (t_b - t_a) / (S1 - S0)
     n0, m0, c0 = h.n[0], h.nnz[0], h.colours[0]
     bytes_sweep = pass_bytes(n0, m0, prec)
@@ -79,7 +98,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name):
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
         "bytes_per_sweep": bytes_sweep,
         "launches_per_sweep": c0,
         "avg_launch_us": round(t_sweep_ms * 1e3 / c0, 3),
