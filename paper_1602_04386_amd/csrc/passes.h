@@ -3,13 +3,13 @@
 //
 // Each pass kernel handles tiles of kBlock consecutive rows (solve order).  A
 // tile first stages its row pointers in LDS, then walks its rows in chunks
-// whose CSR slice fits kTileNnz entries: the chunk's column indices, weights
+// whose CSR slice fits the tile's LDS capacity: the chunk's column indices, weights
 // and the neighbour values those columns gather are staged in LDS with
 // unit-stride loads and all gathers of the chunk in flight together, and each
 // thread then reduces its own row from LDS in CSR order, the same arithmetic
 // as the direct row functions.  Usually the whole tile is one chunk; dense
 // tiles (irregular graphs put their high-degree vertices in the last colours)
-// take two or three, and a single row longer than kTileNnz uses direct loads.
+// take two, and a single row longer than the capacity uses direct loads.
 //
 // A pass writes one partial-sum slot per block; a one-block finishing kernel
 // reduces the slots in a fixed order and updates the device state.  The
@@ -17,21 +17,26 @@
 // device-scope fence.
 #pragma once
 
-constexpr int kTileNnz = 2048;
-constexpr int kStageU = kTileNnz / kBlock;  // staged entries per thread and round
+// Entries a tile stages at once.  2048 keeps an FP32 tile at 25 KB of LDS
+// (six blocks per CU); 4096 entries made the level-0 sweeps 15 % slower
+// through the lost occupancy.
+template <class WT, class XT>
+constexpr int tile_cap() { return 2048; }
+constexpr int kStageU = 8;  // staged entries per thread and load round
 
 template <class WT, class XT>
 struct TileLds {
+  static constexpr int kCap = tile_cap<WT, XT>();
   int rp[kBlock + 1];
-  int col[kTileNnz];
-  WT w[kTileNnz];
-  XT x[kTileNnz];
+  int col[kCap];
+  WT w[kCap];
+  XT x[kCap];
 };
 
 // Walks the rows [rs, re) (re - rs <= kBlock) of a tile chunk by chunk.  For
 // each chunk it stages the CSR slice and gather(col) in LDS, then calls
 // body(t, a, e) in the thread of every row rs + t of the chunk, [a, e) being
-// that row's entries in T.  A row longer than kTileNnz is passed to
+// that row's entries in T.  A row longer than T.kCap is passed to
 // direct(t) instead.  Every thread of the block must call; the rows of one
 // tile never read values that the body writes.
 // skip (the phase's stop flag, loaded by the caller before this call) is
@@ -50,7 +55,7 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
   int lo = 0;
   while (lo < nr) {  // uniform: every bound comes from T.rp
     const int p_lo = T.rp[lo];
-    if (T.rp[lo + 1] - p_lo > kTileNnz) {
+    if (T.rp[lo + 1] - p_lo > T.kCap) {
       if (t == lo) direct(t);
       ++lo;
       continue;
@@ -58,7 +63,7 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
     int a = lo + 1, b = nr;  // last row boundary whose slice still fits
     while (a < b) {
       const int mid = (a + b + 1) >> 1;
-      if (T.rp[mid] - p_lo <= kTileNnz) a = mid; else b = mid - 1;
+      if (T.rp[mid] - p_lo <= T.kCap) a = mid; else b = mid - 1;
     }
     const int hi = a, cnt = T.rp[hi] - p_lo;
     // kStageU entries per thread per round: all index and weight loads of the
@@ -345,6 +350,46 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
   st->cos = r.cos;
   if (mode == kFinGS) st->rho = r.rho;
   if (mode == kFinPI) st->cur = 1 - st->cur;
+  const int it = st->iters + 1;
+  st->iters = it;
+  st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+}
+
+// Finishing kernel of a sweep whose last colours are small: the block first
+// sweeps the rows of colours c0 .. ncol-1 itself (colour by colour, the
+// barrier ordering them), adding their sums to the partial slots of the
+// colours the tile kernels did, then finishes as k_finish does.  One launch
+// instead of one per small trailing colour (first-fit colourings leave a few
+// colours with a handful of rows each).
+constexpr int kTailBlock = 512;
+constexpr int kTailRows = 512;  // one row per thread: the tail adds one dependent row pass
+
+template <class VT>
+__global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* xa, VT* xb,
+                                                             DevState* st, const double* part,
+                                                             int stride, int nslots, int c0,
+                                                             double omega) {
+  __shared__ double lds[block_sum_lds(kTailBlock)];
+  if (st->done) return;
+  VT* x = st->cur ? xb : xa;
+  const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
+  double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int sl = threadIdx.x; sl < nslots; sl += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + sl];
+  for (int c = c0; c < L.ncol; ++c) {
+    const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+      row_gs<VT>(i, L, x, r0, mu, inv_s, rho, omega, S);
+    __syncthreads();  // the next colour reads this colour's new values
+  }
+  block_sum<kNP>(S, lds);
+  if (threadIdx.x != 0) return;
+  const Scal r = after_gs(S, L.n);
+  st->mu = r.mu;
+  st->inv_s = r.inv_s;
+  st->cos = r.cos;
+  st->rho = r.rho;
   const int it = st->iters + 1;
   st->iters = it;
   st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;

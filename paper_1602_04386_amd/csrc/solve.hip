@@ -534,9 +534,13 @@ static int run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const W
   k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol);
   VT* xa = static_cast<VT*>(W.xa);
   VT* xb = static_cast<VT*>(W.xb);
+  // Trailing colours with at most kTailRows rows in all are swept by the
+  // finishing block (k_finish_gs_tail) instead of one launch each.
+  int ct = L.ncol;
+  while (ct > 1 && Lh.cptr_h[L.ncol] - Lh.cptr_h[ct - 1] <= kTailRows) --ct;
   std::vector<int> nbs(L.ncol);
   int nslots = 0;
-  for (int c = 0; c < L.ncol; ++c) {
+  for (int c = 0; c < ct; ++c) {
     nbs[c] = nblk(Lh.cptr_h[c + 1] - Lh.cptr_h[c]);
     nslots += nbs[c];
   }
@@ -545,12 +549,16 @@ static int run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const W
     for (int it = 0; it < k; ++it) {
       if (gs) {
         int base = 0;
-        for (int c = 0; c < L.ncol; ++c) {
+        for (int c = 0; c < ct; ++c) {
           k_gs_tile<VT><<<nbs[c], kBlock, 0, s>>>(L, Lh.cptr_h[c], Lh.cptr_h[c + 1], xa, xb,
                                                   W.st, W.part, W.stride, base, omega);
           base += nbs[c];
         }
-        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS);
+        if (ct < L.ncol)
+          k_finish_gs_tail<VT><<<1, kTailBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride, nslots,
+                                                        ct, omega);
+        else
+          k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS);
       } else {
         const int nb = nblk(L.n);
         k_pi_tile<VT><<<nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
