@@ -124,6 +124,37 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(F f, int n, const long lo
 
 __global__ void k_write_total(const long long* src, int* dst) { *dst = (int)*src; }
 
+// The whole scan in one block when n fits one tile: exclusive scan into out
+// (if non-null), the total into *total and, when write_total, into out[n].
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_scan_small(F f, int n, int* out, bool write_total,
+                                                     long long* total) {
+  __shared__ long long lds[kBlock / 64];
+  const int base = threadIdx.x * kScanPer;
+  long long vals[kScanPer];
+  long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int i = base + k;
+    vals[k] = i < n ? (long long)f(i) : 0;
+    s += vals[k];
+  }
+  const long long inc = block_inclusive_scan_ll(s, lds);
+  long long run = inc - s;
+  if (out) {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int i = base + k;
+      if (i < n) out[i] = (int)run;
+      run += vals[k];
+    }
+  }
+  if (threadIdx.x == blockDim.x - 1) {
+    *total = inc;
+    if (out && write_total) out[n] = (int)inc;
+  }
+}
+
 struct Scanner {
   Tmp* tmp = nullptr;
   long long* bsum = nullptr;
@@ -139,6 +170,12 @@ struct Scanner {
     if (nb + 1 > cap) {
       cap = nb + 4;
       bsum = tmp->get<long long>(cap);
+    }
+    if (nb == 1) {
+      k_scan_small<<<1, kBlock, 0, s>>>(f, n, out, write_total, bsum + 1);
+      FV_HIP(hipGetLastError());
+      last = bsum + 1;
+      return;
     }
     k_scan_reduce<<<nb, kBlock, 0, s>>>(f, n, bsum);
     k_scan_blocks<<<1, kBlock, 0, s>>>(bsum, nb);
@@ -342,6 +379,106 @@ __global__ void k_match_commit(int n, int* mate, const int* ptr, int* active, co
     }
   }
   if (__ballot(pending) != 0ULL && (threadIdx.x & 63) == 0) *active = 1;
+}
+
+// The whole matching of a small level in one workgroup: the same pick and
+// commit rounds, separated by barriers instead of kernel boundaries.
+constexpr int kLocalBlock = 1024;
+constexpr int kLocalMaxN = 4096;
+
+__global__ __launch_bounds__(kLocalBlock) void k_match_local(int n, const int* rp, const int* col,
+                                                           const double* w, int* mate, int* ptr,
+                                                           int* err) {
+  __shared__ int pending;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) mate[v] = -1;
+  __syncthreads();
+  for (int round = 0;; ++round) {
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (mate[v] != -1) continue;
+      int best = -1;
+      double bw = 0.0;
+      for (int p = rp[v]; p < rp[v + 1]; ++p) {
+        const int u = col[p];
+        if (mate[u] != -1) continue;
+        const double wu = w[p];
+        if (best < 0 || edge_before(wu, v, u, bw, v, best)) {
+          best = u;
+          bw = wu;
+        }
+      }
+      ptr[v] = best;
+    }
+    if (threadIdx.x == 0) pending = 0;
+    __syncthreads();
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (mate[v] != -1) continue;
+      const int u = ptr[v];
+      if (u < 0) mate[v] = -2;
+      else if (ptr[u] == v) mate[v] = u;
+      else pending = 1;
+    }
+    __syncthreads();
+    if (!pending) break;
+    if (round > n) {  // cannot happen under a strict order; never spin
+      if (threadIdx.x == 0) *err = 1;
+      break;
+    }
+    __syncthreads();
+  }
+}
+
+// The whole Jones-Plassmann colouring of a small level in one workgroup;
+// *maxc receives the largest colour.
+__global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* rp, const int* col,
+                                                            uint32_t seed, int* colour, int* maxc,
+                                                            int* err) {
+  __shared__ int waiting;
+  __shared__ int lmax[kLocalBlock / 64];
+  for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = -1;
+  __syncthreads();
+  for (int round = 0;; ++round) {
+    if (threadIdx.x == 0) waiting = 0;
+    __syncthreads();
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (colour[v] >= 0) continue;
+      const uint32_t pv = colour_priority(v, seed);
+      const int a = rp[v], b = rp[v + 1];
+      bool wait = false;
+      for (int p = a; p < b && !wait; ++p) {
+        const int u = col[p];
+        if (colour[u] < 0) {
+          const uint32_t pu = colour_priority(u, seed);
+          wait = pu > pv || (pu == pv && u < v);
+        }
+      }
+      if (wait) {
+        waiting = 1;
+        continue;
+      }
+      for (int base = 0;; base += 64) {
+        unsigned long long mask = 0;
+        for (int p = a; p < b; ++p) {
+          const int c = colour[col[p]];
+          if (c >= base && c < base + 64) mask |= 1ULL << (c - base);
+        }
+        if (mask != ~0ULL) {
+          colour[v] = base + __builtin_ctzll(~mask);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (!waiting) break;
+    if (round > n) {
+      if (threadIdx.x == 0) *err = 1;
+      break;
+    }
+    __syncthreads();  // every thread has read `waiting` before it is reset
+  }
+  int m = -1;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) m = max(m, colour[v]);
+  m = block_max_int(m, lmax);
+  if (threadIdx.x == 0) *maxc = m;
 }
 
 // Aggregates (Algorithm 1): pairs; an unmatched vertex joins the aggregate of
@@ -821,7 +958,9 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     constexpr int kRoundCap = 4096;
     int* mflag = tmp.get<int>(kRoundCap);
     int* cflag = tmp.get<int>(kRoundCap);
-    int* lflag = flags + 4;  // [0] aggregation error, [1] largest colour
+    // [0] aggregation error, [1] largest colour, [2] a one-workgroup loop
+    // overran, [3] always 0
+    int* lflag = flags + 4;
     int* bmax = tmp.get<int>(kRoundGrid);
 
     int l = 0;
@@ -834,10 +973,13 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // Matching and colouring rounds run in batches; the host reads the
       // progress flag of the last round of each batch, together with the
       // aggregate count, in one read-back when the first batches suffice.
+      const bool local = fn <= kLocalMaxN;
       int mr = 0, cr = 0;
-      k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(mflag, kRoundCap, 0);
-      k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(cflag, kRoundCap, 0);
-      k_fill_int<<<nblk(fn), kBlock, 0, s>>>(mate, fn, -1);
+      if (!local) {
+        k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(mflag, kRoundCap, 0);
+        k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(cflag, kRoundCap, 0);
+        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(mate, fn, -1);
+      }
       auto match_rounds = [&](int b) {
         if (mr + b > kRoundCap) throw Error(FV_E_DEVICE, "matching did not terminate");
         for (int r = mr; r < mr + b; ++r) {
@@ -870,17 +1012,31 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         FV_HIP(hipGetLastError());
       };
       auto read_back = [&]() {
+        // lflag[3] is never written: it stands for "no round pending" on the
+        // one-workgroup path, whose loops run to the end
+        const int* mdone = local ? lflag + 3 : mflag + mr - 1;
+        const int* cdone = local ? lflag + 3 : cflag + cr - 1;
         k_gather_ints<<<1, 64, 0, s>>>(
-            IntSrc{{mflag + mr - 1, cflag + cr - 1, lflag, lflag + 1, id + fn}}, 5, gath);
-        FV_HIP(hipMemcpyAsync(pin_i, gath, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+            IntSrc{{mdone, cdone, lflag, lflag + 1, id + fn, lflag + 2}}, 6, gath);
+        FV_HIP(hipMemcpyAsync(pin_i, gath, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
         FV_HIP(hipStreamSynchronize(s));
       };
-      match_rounds(8);
-      aggregate();
       F.colour_c = halloc<int>(h, fn);
-      k_fill_int<<<nblk(fn), kBlock, 0, s>>>(F.colour_c, fn, -1);
-      colour_rounds(16);
+      if (local) {
+        // one workgroup runs every round of both loops
+        k_match_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr, lflag + 2);
+        aggregate();
+        k_colour_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed, F.colour_c,
+                                                 lflag + 1, lflag + 2);
+        FV_HIP(hipGetLastError());
+      } else {
+        match_rounds(8);
+        aggregate();
+        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(F.colour_c, fn, -1);
+        colour_rounds(16);
+      }
       read_back();
+      if (pin_i[5]) throw Error(FV_E_DEVICE, "matching or colouring did not terminate");
       while (pin_i[0]) {
         match_rounds(8);
         aggregate();
