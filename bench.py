@@ -334,7 +334,7 @@ def run_batch(args):
     count = len(hs)
     rate64, rate32 = len(sub) / t_l64, len(sub) / t_l32
     out = {
-        "metric": "batched Fiedler solves/s (4096 mixed graphs, FP32-mixed, one launch)",
+        "metric": f"batched Fiedler solves/s ({count} mixed graphs, FP32-mixed, one launch)",
         "value": round(count / t_b32, 2),
         "unit": "solves/s",
         "n_gpus": 1, "steps": 1, "warmup": 1,

@@ -37,18 +37,45 @@ struct LView {
 
 // ---- per-row arithmetic on a view (same operation order as row_gs & co.) --
 
+// Neighbours of a row fetched per batch: the batch's column indices and
+// weights are loaded first (indices past the row end repeat its last entry and
+// get weight 0, so no load is conditional), then the neighbour values; the
+// first batch's values stay in registers for the edge-energy pass.  The sums
+// take the same terms in the same order as a plain loop (the padding adds
+// exact zeros at the end).
+constexpr int kRowU = 4;
+
 template <class VT, class V, class XP>
 __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, double mu, double inv_s,
                                double rho, double omega, double (&acc)[kNP]) {
   const int p0 = L.rp[i], p1 = L.rp[i + 1];
   const double xo = ((double)x[i] - mu) * inv_s;
   double num = 0.0, den = 0.0;
-  for (int p = p0; p < p1; ++p) {
-    const int j = L.col[p];
-    const double wj = (double)L.w[p];
-    const double xj = (double)x[j];
-    num += wj * (j < lower_end ? xj : (xj - mu) * inv_s);
-    den += wj;
+  int j0[kRowU];
+  double w0[kRowU], x0[kRowU];
+  for (int pb = p0; pb < p1; pb += kRowU) {
+    int jj[kRowU];
+    double ww[kRowU], xx[kRowU];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) {
+      const int q = min(pb + u, p1 - 1);
+      jj[u] = L.col[q];
+      ww[u] = pb + u < p1 ? (double)L.w[q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) xx[u] = (double)x[jj[u]];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) {
+      num += ww[u] * (jj[u] < lower_end ? xx[u] : (xx[u] - mu) * inv_s);
+      den += ww[u];
+    }
+    if (pb == p0)
+#pragma unroll
+      for (int u = 0; u < kRowU; ++u) {
+        j0[u] = jj[u];
+        w0[u] = ww[u];
+        x0[u] = xx[u];
+      }
   }
   double u = xo;
   if (den > 0.0) {
@@ -59,7 +86,13 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
   x[i] = us;
   const double ud = (double)us;
   double e = 0.0;
-  for (int p = p0; p < p1; ++p) {
+  if (p1 > p0)
+#pragma unroll
+    for (int k = 0; k < kRowU; ++k) {
+      const double d = ud - x0[k];
+      e += (j0[k] < lower_end ? w0[k] : 0.0) * d * d;
+    }
+  for (int p = p0 + kRowU; p < p1; ++p) {
     const int j = L.col[p];
     if (j < lower_end) {
       const double d = ud - (double)x[j];
@@ -209,15 +242,26 @@ using XView = LView<lds_ptr<VT>, const int*, const VT*>;
 template <class VT>
 using SView = LView<lds_ptr<VT>, lds_ptr<const int>, lds_ptr<const VT>>;
 
+// The colour ranges of the level in LDS (when there are at most kEngineMaxCol
+// colours): every colour step reads its bounds, and a global load there would
+// put a memory round trip on the critical path of each colour.
+__device__ __forceinline__ const int* stage_cptr(const LevelDesc& D, EngineCtx& E) {
+  if (D.ncol > kEngineMaxCol) return D.cptr;
+  __syncthreads();  // the previous level's steps are done with E.cptr
+  for (int k = threadIdx.x; k <= D.ncol; k += blockDim.x) E.cptr[k] = D.cptr[k];
+  __syncthreads();
+  return E.cptr;
+}
+
 template <class V, class IP, class WP>
-__device__ __forceinline__ V make_view(const LevelDesc& D, IP rp, IP col, WP w) {
+__device__ __forceinline__ V make_view(const LevelDesc& D, const int* cptr, IP rp, IP col, WP w) {
   V v;
   v.n = D.n;
   v.ncol = D.ncol;
   v.rp = rp;
   v.col = col;
   v.w = w;
-  v.cptr = D.cptr;
+  v.cptr = cptr;
   v.qs = D.qs;
   v.perm = D.perm;
   v.iperm = D.iperm;
@@ -328,15 +372,14 @@ __device__ void engine_run(const GraphTask& T, EngineCtx& E) {
       size_t wo, co, ro;
       const bool staged = stage_csr<VT>(D, E, wo, co, ro);
       if (staged) {
-        SView<VT> L = make_view<SView<VT>>(
-            D, (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + ro)),
+        SView<VT> L = make_view<SView<VT>>(D, stage_cptr(D, E), (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + ro)),
             (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + co)),
             (lds_ptr<const VT>)(reinterpret_cast<const VT*>(lbase + wo)));
         if (src64) run_level<VT>(L, xl, xa64, G(gfree), s, T, fg, fp, g, p, E);
         else run_level<VT>(L, xl, G(gsrc), G(gfree), s, T, fg, fp, g, p, E);
         if (keep) final_mode = 2;
       } else {
-        XView<VT> L = make_view<XView<VT>>(D, (const int*)D.rp, (const int*)D.col,
+        XView<VT> L = make_view<XView<VT>>(D, stage_cptr(D, E), (const int*)D.rp, (const int*)D.col,
                                            WSel<VT>::w(D));
         if (src64) run_level<VT>(L, xl, xa64, G(gfree), s, T, fg, fp, g, p, E);
         else run_level<VT>(L, xl, G(gsrc), G(gfree), s, T, fg, fp, g, p, E);
@@ -347,7 +390,7 @@ __device__ void engine_run(const GraphTask& T, EngineCtx& E) {
         gsrc = gfree;
       }
     } else {
-      GView<VT> L = make_view<GView<VT>>(D, (const int*)D.rp, (const int*)D.col, WSel<VT>::w(D));
+      GView<VT> L = make_view<GView<VT>>(D, stage_cptr(D, E), (const int*)D.rp, (const int*)D.col, WSel<VT>::w(D));
       if (src64) run_level<VT>(L, G(gfree), xa64, G(gsrc), s, T, fg, fp, g, p, E);
       else run_level<VT>(L, G(gfree), G(gsrc), G(gsrc), s, T, fg, fp, g, p, E);
       gsrc = gfree;
@@ -393,17 +436,16 @@ __device__ void engine_run(const GraphTask& T, EngineCtx& E) {
     size_t wo = ((size_t)D0.n * sizeof(VT) + 15) & ~(size_t)15;
     size_t co = wo + (((size_t)D0.m * sizeof(VT) + 15) & ~(size_t)15);
     size_t ro = co + (((size_t)D0.m * 4 + 15) & ~(size_t)15);
-    SView<VT> L = make_view<SView<VT>>(
-        D0, (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + ro)),
+    SView<VT> L = make_view<SView<VT>>(D0, stage_cptr(D0, E), (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + ro)),
         (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + co)),
         (lds_ptr<const VT>)(reinterpret_cast<const VT*>(lbase + wo)));
     finish_level0<VT>(L, xl, G(0), s, T, J, si, slen, lam, res, E);
   } else if (final_mode == 1) {
-    XView<VT> L = make_view<XView<VT>>(D0, (const int*)D0.rp, (const int*)D0.col,
+    XView<VT> L = make_view<XView<VT>>(D0, stage_cptr(D0, E), (const int*)D0.rp, (const int*)D0.col,
                                        WSel<VT>::w(D0));
     finish_level0<VT>(L, xl, G(0), s, T, J, si, slen, lam, res, E);
   } else {
-    GView<VT> L = make_view<GView<VT>>(D0, (const int*)D0.rp, (const int*)D0.col,
+    GView<VT> L = make_view<GView<VT>>(D0, stage_cptr(D0, E), (const int*)D0.rp, (const int*)D0.col,
                                        WSel<VT>::w(D0));
     finish_level0<VT>(L, G(gsrc), G(1 - gsrc), s, T, J, si, slen, lam, res, E);
   }
@@ -428,8 +470,9 @@ __global__ __launch_bounds__(NT) void k_engine(const GraphTask* tasks, int ntask
   extern __shared__ __align__(16) unsigned char fv_dyn_lds[];
   __shared__ double lds[block_sum_lds(NT)];
   __shared__ int ilds[NT / 64];
+  __shared__ int s_cptr[kEngineMaxCol + 1];
   __shared__ int s_task;
-  EngineCtx E{lds, ilds, fv_dyn_lds, lds_cap, lds_cap * (int)sizeof(VT)};
+  EngineCtx E{lds, ilds, fv_dyn_lds, lds_cap, lds_cap * (int)sizeof(VT), s_cptr};
   for (;;) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(queue, 1u);
     __syncthreads();

@@ -38,7 +38,7 @@ struct Error : std::runtime_error {
 // Launch geometry.
 // ---------------------------------------------------------------------------
 constexpr int kBlock = 256;    // threads per block of the multi-workgroup row passes
-constexpr int kWGSolo = 1024;  // engine threads for the small levels of one graph
+constexpr int kWGSolo = 512;  // engine threads for the small levels of one graph
 constexpr int kWGBatch = 512;  // engine threads per graph of a batch
 constexpr size_t kSoloLds = 144 * 1024;  // engine LDS for one graph's level vector
 constexpr size_t kBatchLds = 64 * 1024;  // per graph of a batch

@@ -188,12 +188,15 @@ __device__ inline Scal after_prolong(const double (&S)[kNP], int n) {
 // ---------------------------------------------------------------------------
 // One-workgroup engine.
 // ---------------------------------------------------------------------------
+constexpr int kEngineMaxCol = 255;
+
 struct EngineCtx {
   double* lds;  // (threads / 64) * kNP doubles
   int* ilds;
   void* xl;     // dynamic LDS: one level vector, then optionally its CSR
   int cap;      // capacity in vector entries
   int bytes;    // size in bytes
+  int* cptr;    // LDS, kEngineMaxCol + 1 entries: the current level's colour ranges
 };
 
 // Coarsest solve in FP64 (Algorithm 3, Step 2): power iteration on
@@ -349,103 +352,12 @@ __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int 
   return it;
 }
 
-template <class VT>
-__device__ Scal engine_gs_sweep(const LevelDesc& L, VT* x, Scal s, double omega, EngineCtx& E) {
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int c = 0; c < L.ncol; ++c) {
-    const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-      row_gs<VT>(i, L, x, r0, s.mu, s.inv_s, s.rho, omega, acc);
-    __syncthreads();
-  }
-  block_sum<kNP>(acc, E.lds);
-  return after_gs(acc, L.n);
-}
-
-template <class VT>
-__device__ Scal engine_pi_step(const LevelDesc& L, const VT* x, VT* y, Scal s, EngineCtx& E) {
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < L.n; i += blockDim.x)
-    row_pi<VT>(i, L, x, y, s.mu, s.inv_s, L.sigma, acc);
-  __syncthreads();
-  block_sum<kNP>(acc, E.lds);
-  Scal r = after_gs(acc, L.n);
-  r.rho = s.rho;
-  return r;
-}
-
-template <class SRC, class VT>
-__device__ Scal engine_prolong(const LevelDesc& L, const SRC* xc, VT* xf, Scal s, EngineCtx& E) {
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < L.n; i += blockDim.x)
-    row_prolong<SRC, VT>(i, L, xc, xf, s.mu, s.inv_s, acc);
-  __syncthreads();
-  block_sum<kNP>(acc, E.lds);
-  return after_prolong(acc, L.n);
-}
-
 // Phase counts: forced (replay) or free with the cosine test.
 struct PhaseCfg {
   int forced;  // -1 = free
   int cap;
   double tol;
 };
-
-template <class VT>
-__device__ int engine_gs_phase(const LevelDesc& L, VT* x, Scal& s, double omega, PhaseCfg P,
-                               EngineCtx& E) {
-  const int lim = P.forced >= 0 ? P.forced : P.cap;
-  int k = 0;
-  while (k < lim) {
-    s = engine_gs_sweep<VT>(L, x, s, omega, E);
-    ++k;
-    if (P.forced < 0 && s.cos > 1.0 - P.tol) break;
-  }
-  return k;
-}
-
-template <class VT>
-__device__ int engine_pi_phase(const LevelDesc& L, VT* xa, VT* xb, int& cur, Scal& s,
-                               PhaseCfg P, EngineCtx& E) {
-  const int lim = P.forced >= 0 ? P.forced : P.cap;
-  int k = 0;
-  while (k < lim) {
-    VT* x = cur ? xb : xa;
-    VT* y = cur ? xa : xb;
-    s = engine_pi_step<VT>(L, x, y, s, E);
-    cur = 1 - cur;
-    ++k;
-    if (P.forced < 0 && s.cos > 1.0 - P.tol) break;
-  }
-  return k;
-}
-
-// Rayleigh quotient, residual and sign index on the finest level.
-template <class VT>
-__device__ void engine_rq_residual(const LevelDesc& L, const VT* x, const Scal& s, double* lx,
-                                   double& lam, double& res, double& sign, EngineCtx& E) {
-  double a3[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < L.n; i += blockDim.x) row_rq<VT>(i, L, x, s.mu, s.inv_s, lx, a3);
-  __syncthreads();
-  const double mx = block_max(a3[2], E.lds);
-  double t[2] = {a3[0], a3[1]};
-  block_sum<2>(t, E.lds);
-  lam = t[1] / t[0];
-  const double thr = 1e-3 * mx;
-  double r[1] = {0.0};
-  int cand = INT_MAX;
-  for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
-    const double xh = ((double)x[i] - s.mu) * s.inv_s;
-    const double d = lx[i] - lam * xh;
-    r[0] += d * d;
-    if (fabs(xh) >= thr) cand = min(cand, L.iperm[i]);
-  }
-  block_sum<1>(r, E.lds);
-  cand = block_min_int(cand, E.ilds);
-  res = sqrt(r[0] / t[0]);
-  const double xv = cand < INT_MAX ? ((double)x[L.perm[cand]] - s.mu) * s.inv_s : 1.0;
-  sign = xv < 0.0 ? -1.0 : 1.0;
-}
 
 #include "engine.h"
 
