@@ -159,6 +159,10 @@ fv_status fv_build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opt
 fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz,
                             int32_t* colours, double* sigma);
 
+/* Device bytes the hierarchy holds (counted against its context's HBM
+ * budget while the hierarchy lives).  FV_E_INVALID for a NULL argument. */
+fv_status fv_hierarchy_bytes(const fv_hierarchy* h, int64_t* bytes);
+
 /* Copies level `level` to host buffers in the canonical numbering (vertices of
  * a coarse level numbered by their aggregate's smallest member): row_ptr[n+1],
  * col[nnz], w[nnz] (off-diagonal weights), q[n] (aggregate of each vertex in

@@ -77,7 +77,7 @@ class fv_result(C.Structure):
 
 
 EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
-           "fv_context_destroy", "fv_build_hierarchy", "fv_hierarchy_info",
+           "fv_context_destroy", "fv_build_hierarchy", "fv_hierarchy_info", "fv_hierarchy_bytes",
            "fv_hierarchy_export_level", "fv_free_hierarchy", "fv_fiedler_solve",
            "fv_fiedler_solve_batch", "fv_server_create", "fv_submit", "fv_poll",
            "fv_server_destroy", "fv_status_str"]
@@ -107,6 +107,8 @@ def lib() -> C.CDLL:
         L.fv_build_hierarchy.restype = C.c_int
         L.fv_hierarchy_info.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fv_hierarchy_info.restype = C.c_int
+        L.fv_hierarchy_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.fv_hierarchy_bytes.restype = C.c_int
         L.fv_hierarchy_export_level.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
         L.fv_hierarchy_export_level.restype = C.c_int
         L.fv_free_hierarchy.argtypes = [vp]
@@ -228,6 +230,12 @@ class Hierarchy:
                "fv_hierarchy_info")
         L = lev.value
         return L, list(n[:L]), list(nnz[:L]), list(col[:L]), list(sig[:L])
+
+    def device_bytes(self) -> int:
+        """fv_hierarchy_bytes: device memory the hierarchy holds."""
+        b = C.c_int64()
+        _check(lib().fv_hierarchy_bytes(self._h, C.byref(b)), "fv_hierarchy_bytes")
+        return b.value
 
     def export_level(self, level: int) -> LevelExport:
         n, m = self.n[level], self.nnz[level]

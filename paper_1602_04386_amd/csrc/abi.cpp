@@ -222,6 +222,12 @@ fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, 
   return FV_OK;
 }
 
+fv_status fv_hierarchy_bytes(const fv_hierarchy* h, int64_t* bytes) {
+  if (!h || !bytes) return FV_E_INVALID;
+  *bytes = (int64_t)h->bytes;
+  return FV_OK;
+}
+
 fv_status fv_hierarchy_export_level(const fv_hierarchy* h, int32_t level, int32_t* row_ptr,
                                     int32_t* col, double* w, int32_t* q, int32_t* colour) {
   if (!h || level < 0 || level >= h->levels) return FV_E_INVALID;
