@@ -135,6 +135,35 @@ __device__ inline void block_sum(double (&v)[NP], double* lds) {
   __syncthreads();
 }
 
+// Sum of NP values over the block for a single consumer: thread k < NP
+// returns the block total of value k (other threads return 0).  Rows of 16
+// lanes are summed with DPP as in block_sum; thread k then adds the block's
+// row sums of value k in row order.  One barrier instead of three.
+template <int NP>
+__device__ inline double block_sum_spread(double (&v)[NP], double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) v[k] = row_sum16(v[k]);
+  if ((lane & 15) == 0)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) lds[(wid * 4 + (lane >> 4)) * NP + k] = v[k];
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < NP)
+    for (int r = 0; r < nw * 4; ++r) t += lds[r * NP + threadIdx.x];
+  return t;
+}
+
+// Lanes 0 .. NP-1 of wave 0 hold one value each (block_sum_spread's result);
+// every lane of wave 0 receives all NP.  Call from all of wave 0.
+template <int NP>
+__device__ inline void wave0_collect(double t, double (&out)[NP]) {
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+    out[k] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(t), k),
+                              __builtin_amdgcn_readlane(__double2loint(t), k));
+}
+
 __device__ inline long long block_sum_ll(long long v, long long* lds) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   v = wave_sum_ll(v);

@@ -68,6 +68,7 @@ struct DevState {
   unsigned counter;  // last-block-done counter
   int sign_idx;   // first (canonical) index with |x_i| >= 1e-3 max|x|
   int err;
+  int halt;       // finest residual reached the tolerance: later phases do nothing
 };
 
 // Per-level descriptor as the kernels see it (solve order: rows of one colour

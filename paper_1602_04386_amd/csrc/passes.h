@@ -42,16 +42,25 @@ struct TileLds {
 // skip (the phase's stop flag, loaded by the caller before this call) is
 // tested only after the row pointers are requested, so that both loads are in
 // flight together; when set, nothing else happens and false is returned.
-template <class WT, class XT, class G, class B, class D>
+// pre() runs in every thread once the row pointer loads are issued and before
+// their values are used: the loads a thread issues there (its own row's
+// value) travel alongside the CSR staging instead of after it.  The block has
+// kBlock threads and re - rs <= kBlock.
+template <class WT, class XT, class P, class G, class B, class D>
 __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict__ w, int rs,
-                                       int re, TileLds<WT, XT>& T, int skip, G gather, B body,
-                                       D direct) {
+                                       int re, TileLds<WT, XT>& T, int skip, P pre, G gather,
+                                       B body, D direct) {
   const int nr = re - rs;
-  for (int k = threadIdx.x; k <= nr; k += blockDim.x) T.rp[k] = L.rp[rs + k];
+  const int t = threadIdx.x;
+  const bool extra = t == 0 && nr == kBlock;  // the pointer past a full tile
+  const int rp_a = t <= nr ? L.rp[rs + t] : 0;
+  const int rp_b = extra ? L.rp[rs + kBlock] : 0;
+  pre();
+  if (t <= nr) T.rp[t] = rp_a;
+  if (extra) T.rp[kBlock] = rp_b;
   __syncthreads();
   if (skip) return false;
   const int* __restrict__ col = L.col;
-  const int t = threadIdx.x;
   int lo = 0;
   while (lo < nr) {  // uniform: every bound comes from T.rp
     const int p_lo = T.rp[lo];
@@ -102,18 +111,26 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
   return true;
 }
 
-__global__ void k_phase_begin(DevState* st, int cap, int forced, double tol) {
-  st->done = cap <= 0 ? 1 : 0;
+// Opens a phase.  With use_halt set, a phase enqueued after the finest
+// residual met its tolerance starts finished, so the host may enqueue the next
+// finest round before it has read that residual.  *rec receives the phase's
+// step count (the finishing kernels keep it current).
+__global__ void k_phase_begin(DevState* st, int cap, int forced, double tol, int use_halt,
+                              int* rec) {
+  st->done = (cap <= 0 || (use_halt && st->halt)) ? 1 : 0;
+  *rec = 0;
   st->iters = 0;
   st->cap = cap;
   st->forced = forced;
   st->tol = tol;
 }
 
-__device__ inline void write_slot(double* part, int stride, int slot, const double (&S)[kNP]) {
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) part[k * stride + slot] = S[k];
+// Reduces a block's kNP sums and writes them to partial slot `slot`; threads
+// 0 .. kNP-1 store one value each.
+__device__ inline void store_block_sum(double (&S)[kNP], double* lds, double* part, int stride,
+                                       int slot) {
+  const double t = block_sum_spread<kNP>(S, lds);
+  if (threadIdx.x < kNP) part[threadIdx.x * stride + slot] = t;
 }
 
 // ---- smoothing sweep, one colour -------------------------------------------
@@ -131,11 +148,16 @@ __global__ __launch_bounds__(kBlock) void k_gs_tile(LevelDesc L, int r0, int r1,
   const int rs = r0 + b * kBlock, re = min(rs + kBlock, r1);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  VT xown = VT(0);
   const bool ran = for_tile_chunks<VT, VT>(
-      L, w, rs, re, T, done, [&](int c) { return x[c]; },
+      L, w, rs, re, T, done,
+      [&] {
+        if (rs + (int)threadIdx.x < re) xown = x[rs + threadIdx.x];
+      },
+      [&](int c) { return x[c]; },
       [&](int t, int a, int e) {
         const int i = rs + t;
-        const double xo = ((double)x[i] - mu) * inv_s;
+        const double xo = ((double)xown - mu) * inv_s;
         double num = 0.0, den = 0.0;
         for (int k = a; k < e; ++k) {
           const double wj = (double)T.w[k];
@@ -165,8 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_tile(LevelDesc L, int r0, int r1,
       },
       [&](int t) { row_gs<VT>(rs + t, L, x, r0, mu, inv_s, rho, omega, acc); });
   if (!ran) return;
-  block_sum<kNP>(acc, lds);
-  write_slot(part, stride, slot_base + blockIdx.x, acc);
+  store_block_sum(acc, lds, part, stride, slot_base + blockIdx.x);
 }
 
 // ---- power step ------------------------------------------------------------
@@ -185,11 +206,16 @@ __global__ __launch_bounds__(kBlock) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  VT xown = VT(0);
   const bool ran = for_tile_chunks<VT, VT>(
-      L, w, rs, re, T, done, [&](int c) { return x[c]; },
+      L, w, rs, re, T, done,
+      [&] {
+        if (rs + (int)threadIdx.x < re) xown = x[rs + threadIdx.x];
+      },
+      [&](int c) { return x[c]; },
       [&](int t, int a, int e) {
         const int i = rs + t;
-        const double xi = (double)x[i];
+        const double xi = (double)xown;
         double lx = 0.0;
         for (int k = a; k < e; ++k) lx += (double)T.w[k] * (xi - (double)T.x[k]);
         const double xo = (xi - mu) * inv_s;
@@ -203,8 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
       },
       [&](int t) { row_pi<VT>(rs + t, L, x, y, mu, inv_s, sigma, acc); });
   if (!ran) return;
-  block_sum<kNP>(acc, lds);
-  write_slot(part, stride, blockIdx.x, acc);
+  store_block_sum(acc, lds, part, stride, blockIdx.x);
 }
 
 // ---- prolongation ----------------------------------------------------------
@@ -225,11 +250,16 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(LevelDesc L, const SRC*
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  SRC cown = SRC(0);
   for_tile_chunks<VT, VT>(
-      L, w, rs, re, T, 0, [&](int c) { return (VT)(((double)xc[qs[c]] - mu) * inv_s); },
+      L, w, rs, re, T, 0,
+      [&] {
+        if (rs + (int)threadIdx.x < re) cown = xc[qs[rs + threadIdx.x]];
+      },
+      [&](int c) { return (VT)(((double)xc[qs[c]] - mu) * inv_s); },
       [&](int t, int a, int e) {
         const int i = rs + t;
-        const VT vs = (VT)(((double)xc[qs[i]] - mu) * inv_s);
+        const VT vs = (VT)(((double)cown - mu) * inv_s);
         xf[i] = vs;
         const double v = (double)vs;
         double en = 0.0;
@@ -242,8 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(LevelDesc L, const SRC*
         acc[4] += 0.5 * en;
       },
       [&](int t) { row_prolong<SRC, VT>(rs + t, L, xc, xf, mu, inv_s, acc); });
-  block_sum<kNP>(acc, lds);
-  write_slot(part, stride, blockIdx.x, acc);
+  store_block_sum(acc, lds, part, stride, blockIdx.x);
 }
 
 // ---- Rayleigh quotient and residual (FP64 weights) -------------------------
@@ -259,11 +288,16 @@ __global__ __launch_bounds__(kBlock) void k_rq_tile(LevelDesc L, const VT* xa, c
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   double a3[3] = {0.0, 0.0, 0.0};
+  VT xown = VT(0);
   for_tile_chunks<double, VT>(
-      L, L.w64, rs, re, T, 0, [&](int c) { return x[c]; },
+      L, L.w64, rs, re, T, 0,
+      [&] {
+        if (rs + (int)threadIdx.x < re) xown = x[rs + threadIdx.x];
+      },
+      [&](int c) { return x[c]; },
       [&](int t, int a, int e) {
         const int i = rs + t;
-        const double xi = ((double)x[i] - mu) * inv_s;
+        const double xi = ((double)xown - mu) * inv_s;
         double lx = 0.0, en = 0.0;
         for (int k = a; k < e; ++k) {
           const double d = xi - ((double)T.x[k] - mu) * inv_s;
@@ -278,9 +312,9 @@ __global__ __launch_bounds__(kBlock) void k_rq_tile(LevelDesc L, const VT* xa, c
       [&](int t) { row_rq<VT>(rs + t, L, x, mu, inv_s, lxo, a3); });
   const double mx = block_max(a3[2], lds);
   double t2[2] = {a3[0], a3[1]};
-  block_sum<2>(t2, lds);
-  double S[kNP] = {t2[0], t2[1], mx, 0.0, 0.0};
-  write_slot(part, stride, blockIdx.x, S);
+  const double t = block_sum_spread<2>(t2, lds);
+  if (threadIdx.x < 2) part[threadIdx.x * stride + blockIdx.x] = t;
+  if (threadIdx.x == 2) part[2 * stride + blockIdx.x] = mx;
 }
 
 template <class VT>
@@ -314,11 +348,12 @@ __global__ __launch_bounds__(kBlock) void k_res_tile(LevelDesc L, const VT* xa, 
 enum FinishMode { kFinGS = 0, kFinPI = 1, kFinProlong = 2, kFinRQ = 3 };
 
 __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* part, int stride,
-                                                 int nslots, int n, int mode) {
+                                                 int nslots, int n, int mode, int* rec) {
   __shared__ double lds[block_sum_lds(kBlock)];
   if ((mode == kFinGS || mode == kFinPI) && st->done) return;
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double mx = 0.0;
+#pragma unroll 4
   for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
     if (mode == kFinRQ) {
       S[0] += part[s];
@@ -329,8 +364,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
       for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + s];
     }
   }
-  block_sum<kNP>(S, lds);
-  if (mode == kFinRQ) mx = block_max(mx, lds);
+  const double t = block_sum_spread<kNP>(S, lds);
+  if (mode == kFinRQ) {
+    __syncthreads();  // the row sums in lds are read before block_max reuses it
+    mx = block_max(mx, lds);
+  }
+  if (threadIdx.x >= 64) return;
+  wave0_collect<kNP>(t, S);
   if (threadIdx.x != 0) return;
   if (mode == kFinRQ) {
     st->sumsq = S[0];
@@ -352,6 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
   if (mode == kFinPI) st->cur = 1 - st->cur;
   const int it = st->iters + 1;
   st->iters = it;
+  *rec = it;
   st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
 }
 
@@ -368,12 +409,13 @@ template <class VT>
 __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* xa, VT* xb,
                                                              DevState* st, const double* part,
                                                              int stride, int nslots, int c0,
-                                                             double omega) {
+                                                             double omega, int* rec) {
   __shared__ double lds[block_sum_lds(kTailBlock)];
   if (st->done) return;
   VT* x = st->cur ? xb : xa;
   const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
   for (int sl = threadIdx.x; sl < nslots; sl += blockDim.x)
 #pragma unroll
     for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + sl];
@@ -383,7 +425,9 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
       row_gs<VT>(i, L, x, r0, mu, inv_s, rho, omega, S);
     __syncthreads();  // the next colour reads this colour's new values
   }
-  block_sum<kNP>(S, lds);
+  const double t = block_sum_spread<kNP>(S, lds);
+  if (threadIdx.x >= 64) return;
+  wave0_collect<kNP>(t, S);
   if (threadIdx.x != 0) return;
   const Scal r = after_gs(S, L.n);
   st->mu = r.mu;
@@ -392,13 +436,15 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
   st->rho = r.rho;
   const int it = st->iters + 1;
   st->iters = it;
+  *rec = it;
   st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
 }
 
 template <class VT>
 __global__ __launch_bounds__(kBlock) void k_finish_res(LevelDesc L, const VT* xa, const VT* xb,
                                                      DevState* st, const double* part,
-                                                     const int* ipart, int nslots) {
+                                                     const int* ipart, int nslots,
+                                                     double tol_halt) {
   __shared__ double lds[block_sum_lds(kBlock)];
   __shared__ int ilds[kBlock / 64];
   double s[1] = {0.0};
@@ -411,7 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_finish_res(LevelDesc L, const VT* xa
   c = block_min_int(c, ilds);
   if (threadIdx.x != 0) return;
   const VT* x = st->cur ? xb : xa;
-  st->res = sqrt(s[0] / st->sumsq);
+  const double res = sqrt(s[0] / st->sumsq);
+  st->res = res;
+  st->halt = (tol_halt > 0.0 && res <= tol_halt) ? 1 : 0;
   st->sign_idx = c;
   const double xv = c < INT_MAX ? ((double)x[L.perm[c]] - st->mu) * st->inv_s : 1.0;
   st->sign = xv < 0.0 ? -1.0 : 1.0;

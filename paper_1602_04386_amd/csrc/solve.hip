@@ -390,6 +390,7 @@ struct Workspace {
   int* sched;
   int* sched_len;
   int* replay;
+  int* rec;  // step count of each multi-workgroup phase, one slot spare
   unsigned* queue;
   int stride;
 };
@@ -406,7 +407,7 @@ size_t solve_workspace_bytes(size_t nmax, int maxcol) {
   const size_t slots = slot_count(nmax, maxcol);
   return 3 * align_up(8 * std::max<size_t>(nmax, 1)) + align_up(8 * kNP * slots) +
          align_up(4 * slots) + align_up(sizeof(DevState)) + align_up(sizeof(GraphTask)) +
-         2 * align_up(4 * FV_SCHEDULE_CAP) + align_up(64);
+         2 * align_up(4 * FV_SCHEDULE_CAP) + align_up(4 * (FV_SCHEDULE_CAP + 1)) + align_up(64);
 }
 
 static Workspace carve(void* base, size_t nmax, int maxcol) {
@@ -427,23 +428,39 @@ static Workspace carve(void* base, size_t nmax, int maxcol) {
   w.task = reinterpret_cast<GraphTask*>(take(sizeof(GraphTask)));
   w.sched = reinterpret_cast<int*>(take(4 * FV_SCHEDULE_CAP));
   w.replay = reinterpret_cast<int*>(take(4 * FV_SCHEDULE_CAP));
+  w.rec = reinterpret_cast<int*>(take(4 * (FV_SCHEDULE_CAP + 1)));
   w.queue = reinterpret_cast<unsigned*>(take(64));
   w.sched_len = reinterpret_cast<int*>(w.queue + 4);
   w.stride = (int)slots;
   return w;
 }
 
-struct HostState {
-  int done;
-  int iters;
+// Host side of the early stop.  The host enqueues a phase in chunks of
+// kChunk steps and reads the phase's done flag after each, but it enqueues
+// chunk k+1 before it waits for the flag of chunk k: the device always has
+// queued work while the host waits, and a phase that has ended leaves at most
+// one chunk of launches that return at once.
+struct HostSync {
+  int* flags;        // pinned host memory: two done flags, then the residual
+  hipEvent_t ev[2];  // flag slot k is valid once ev[k] has completed
+  hipEvent_t ev_res;
+  double* res() const { return reinterpret_cast<double*>(flags + 8); }
 };
 
-template <class VT>
-static int run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const Workspace& W,
-                           int forced, int cap, double tol, double omega, hipStream_t s,
-                           int* pinned) {
+constexpr int kChunk = 2;
+
+// Enqueues one smoothing (gs) or power phase: `forced` steps exactly when it
+// is not negative, else up to `cap` steps with the cosine test.  The step
+// count lands in *rec on the device.  before_wait, when given, runs once
+// after the first chunk is enqueued and before any flag is awaited; it
+// returns true when the phase is moot (the finest residual already met its
+// tolerance), and the phase then ends without further launches.
+template <class VT, class BeforeWait>
+static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const Workspace& W,
+                            int forced, int cap, double tol, double omega, hipStream_t s,
+                            HostSync& hs, int* rec, bool use_halt, BeforeWait before_wait) {
   const int lim = forced >= 0 ? forced : cap;
-  k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol);
+  k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol, use_halt ? 1 : 0, rec);
   VT* xa = static_cast<VT*>(W.xa);
   VT* xb = static_cast<VT*>(W.xb);
   // Trailing colours with at most kTailRows rows in all are swept by the
@@ -468,34 +485,45 @@ static int run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const W
         }
         if (ct < L.ncol)
           k_finish_gs_tail<VT><<<1, kTailBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride, nslots,
-                                                        ct, omega);
+                                                        ct, omega, rec);
         else
-          k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS);
+          k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec);
       } else {
         const int nb = nblk(L.n);
         k_pi_tile<VT><<<nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
-        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, L.n, kFinPI);
+        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, L.n, kFinPI, rec);
       }
     }
     FV_HIP(hipGetLastError());
   };
   if (forced >= 0) {
     enqueue(forced);
-    return forced;
+    return before_wait();
   }
-  int enq = 0, chunk = 2;
-  while (enq < lim) {
-    const int k = std::min(chunk, lim - enq);
+  int enq = 0, prev = -1, slot = 0;
+  bool first = true;
+  for (;;) {
+    const int k = std::min(kChunk, lim - enq);
     enqueue(k);
     enq += k;
-    FV_HIP(hipMemcpyAsync(pinned, &W.st->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipStreamSynchronize(s));
-    if (pinned[0]) break;
-    chunk = std::min(chunk * 2, 64);
+    const bool more = enq < lim;
+    if (more) {
+      FV_HIP(hipMemcpyAsync(hs.flags + slot, &W.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+      FV_HIP(hipEventRecord(hs.ev[slot], s));
+    }
+    if (first) {
+      first = false;
+      if (before_wait()) return true;
+    }
+    if (!more) break;
+    if (prev >= 0) {
+      FV_HIP(hipEventSynchronize(hs.ev[prev]));
+      if (hs.flags[prev]) break;
+    }
+    prev = slot;
+    slot ^= 1;
   }
-  FV_HIP(hipMemcpyAsync(pinned, &W.st->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  FV_HIP(hipStreamSynchronize(s));
-  return pinned[1];
+  return false;
 }
 
 static LevelDesc host_desc(const Level& F) {
@@ -653,18 +681,28 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
     fcos = hs.cos;
     if (hs.err) status = FV_E_NOT_CONVERGED;
   } else {
-    // Engine part of the schedule.
-    FV_HIP(hipMemcpyAsync(pinned, W.sched_len, sizeof(int), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipStreamSynchronize(s));
-    const int elen = std::min(pinned[0], FV_SCHEDULE_CAP);
-    sched.resize(elen);
-    FV_HIP(hipMemcpyAsync(sched.data(), W.sched, sizeof(int) * elen, hipMemcpyDeviceToHost, s));
-    DevState hs0;
-    FV_HIP(hipMemcpyAsync(&hs0, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    FV_HIP(hipStreamSynchronize(s));
-    if (hs0.err) status = FV_E_NOT_CONVERGED;
-    int ri = elen;  // replay cursor continues after the engine's entries
+    // The engine records the coarsest count and one (smoothing, power) pair
+    // per level it ran; the replay cursor continues after those.  Nothing is
+    // read back until the end of the solve.
+    const int elen = std::min(1 + 2 * (J - t), FV_SCHEDULE_CAP);
+    int ri = elen;
     auto next_forced = [&]() -> int { return (o->replay && ri < replay_len) ? o->replay[ri++] : -1; };
+    HostSync hsync;
+    hsync.flags = pinned;
+    FV_HIP(hipEventCreateWithFlags(&hsync.ev[0], hipEventDisableTiming));
+    FV_HIP(hipEventCreateWithFlags(&hsync.ev[1], hipEventDisableTiming));
+    FV_HIP(hipEventCreateWithFlags(&hsync.ev_res, hipEventDisableTiming));
+    struct SyncGuard {
+      HostSync& h;
+      ~SyncGuard() {
+        (void)hipEventDestroy(h.ev[0]);
+        (void)hipEventDestroy(h.ev[1]);
+        (void)hipEventDestroy(h.ev_res);
+      }
+    } sg{hsync};
+    int nrec = 0;  // phases recorded in W.rec; the spare slot takes any overflow
+    auto rec_slot = [&]() { return W.rec + std::min(nrec++, FV_SCHEDULE_CAP); };
+    auto no_wait = [] { return false; };
     // Multi-workgroup levels t-1 .. 0.
     for (int l = t - 1; l >= 0; --l) {
       const Level& F = h->lv[l];
@@ -679,49 +717,57 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
             L, static_cast<const VT*>(W.xa), static_cast<const VT*>(W.xb), static_cast<VT*>(W.xa),
             static_cast<VT*>(W.xb), W.st, W.part, W.stride);
       }
-      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F.n, kFinProlong);
+      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F.n, kFinProlong, nullptr);
       FV_HIP(hipGetLastError());
-      const int g = run_phase_multi<VT>(true, F, L, W, next_forced(), o->max_gs, o->tol_cos,
-                                        o->omega, s, pinned);
-      const int p = run_phase_multi<VT>(false, F, L, W, next_forced(), o->max_pi, o->tol_cos,
-                                        o->omega, s, pinned);
-      sched.push_back(g);
-      sched.push_back(p);
+      run_phase_multi<VT>(true, F, L, W, next_forced(), o->max_gs, o->tol_cos, o->omega, s, hsync,
+                          rec_slot(), false, no_wait);
+      run_phase_multi<VT>(false, F, L, W, next_forced(), o->max_pi, o->tol_cos, o->omega, s,
+                          hsync, rec_slot(), false, no_wait);
     }
     const Level& F0 = h->lv[0];
     const LevelDesc L0 = host_desc(F0);
+    // Under the residual test the last residual pass raises the device's halt
+    // flag itself, so a round enqueued before the host has read it is void.
+    const double tol_halt = o->replay ? 0.0 : o->tol_res;
     auto rq_res = [&]() {
       const int nb = nblk(F0.n);
       const VT* xa = static_cast<const VT*>(W.xa);
       const VT* xb = static_cast<const VT*>(W.xb);
       k_rq_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.stride);
-      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F0.n, kFinRQ);
+      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F0.n, kFinRQ, nullptr);
       k_res_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.ipart);
-      k_finish_res<VT><<<1, kBlock, 0, s>>>(L0, xa, xb, W.st, W.part, W.ipart, nb);
+      k_finish_res<VT><<<1, kBlock, 0, s>>>(L0, xa, xb, W.st, W.part, W.ipart, nb, tol_halt);
       FV_HIP(hipGetLastError());
     };
     rq_res();
     int outer = 0;
     for (;;) {
       int fg, fp;
+      bool spec = false;
       if (o->replay) {
         if (ri >= replay_len) break;
         fg = next_forced();
         fp = next_forced();
       } else {
         if (!(o->tol_res > 0.0) || outer >= o->max_outer) break;
-        DevState hs;
-        FV_HIP(hipMemcpyAsync(&hs, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-        FV_HIP(hipStreamSynchronize(s));
-        if (hs.res <= o->tol_res) break;
+        FV_HIP(hipMemcpyAsync(hsync.res(), &W.st->res, sizeof(double), hipMemcpyDeviceToHost, s));
+        FV_HIP(hipEventRecord(hsync.ev_res, s));
         fg = fp = -1;
+        spec = true;
       }
-      const int g = run_phase_multi<VT>(true, F0, L0, W, fg, o->max_gs, o->tol_cos, o->omega, s,
-                                        pinned);
-      const int p = run_phase_multi<VT>(false, F0, L0, W, fp, o->max_pi, o->tol_cos, o->omega, s,
-                                        pinned);
-      sched.push_back(g);
-      sched.push_back(p);
+      // The round's first chunk is enqueued before the last residual is read.
+      auto residual_met = [&]() -> bool {
+        if (!spec) return false;
+        FV_HIP(hipEventSynchronize(hsync.ev_res));
+        return *hsync.res() <= o->tol_res;
+      };
+      if (run_phase_multi<VT>(true, F0, L0, W, fg, o->max_gs, o->tol_cos, o->omega, s, hsync,
+                              rec_slot(), spec, residual_met)) {
+        --nrec;  // the void round is not part of the schedule
+        break;
+      }
+      run_phase_multi<VT>(false, F0, L0, W, fp, o->max_pi, o->tol_cos, o->omega, s, hsync,
+                          rec_slot(), spec, no_wait);
       ++outer;
       rq_res();
     }
@@ -733,10 +779,18 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
       FV_HIP(hipMemcpyAsync(x_out, W.lx, sizeof(double) * F0.n, hipMemcpyDeviceToHost, s));
     DevState hs;
     FV_HIP(hipMemcpyAsync(&hs, W.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    sched.resize(elen);
+    FV_HIP(hipMemcpyAsync(sched.data(), W.sched, sizeof(int) * elen, hipMemcpyDeviceToHost, s));
+    const int nr = std::min(nrec, FV_SCHEDULE_CAP);
+    std::vector<int> recs(nr);
+    if (nr > 0)
+      FV_HIP(hipMemcpyAsync(recs.data(), W.rec, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
+    sched.insert(sched.end(), recs.begin(), recs.end());
     lam = hs.lambda;
     res = hs.res;
     fcos = hs.cos;
+    if (hs.err) status = FV_E_NOT_CONVERGED;
     if (!o->replay && o->tol_res > 0.0 && res > o->tol_res) status = FV_E_NOT_CONVERGED;
   }
   float ms = 0.0f;
