@@ -111,6 +111,10 @@ typedef struct {
                             schedule step for step */
   int32_t replay_len;
   void* stream;          /* hipStream_t to run on, or NULL for the context's stream */
+  double tol_coarse;     /* the coarsest power iteration (Algorithm 3, Step 2) stops
+                            once ||L x - (x^T L x) x|| <= tol_coarse * sigma for the
+                            unit iterate x; the paper leaves this tolerance open.
+                            Default 1e-13 */
 } fv_solve_opts;
 
 /* Per-solve statistics.  schedule = [coarsest steps, then (gs sweeps, pi steps)

@@ -82,7 +82,7 @@ def lib():
         L.or_random_start.argtypes = [C.c_int32, C.c_uint64, f64p]
         L.or_coarsest.restype = C.c_int32
         L.or_coarsest.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_double, C.c_uint64, C.c_int32,
-                                  C.c_int32, f64p, C.POINTER(C.c_int32)]
+                                  C.c_int32, C.c_double, f64p, C.POINTER(C.c_int32)]
         L.or_fix_sign.restype = None
         L.or_fix_sign.argtypes = [C.c_int32, f64p]
         L.or_hier_build.restype = C.c_void_p
@@ -109,7 +109,8 @@ class SolveParams(C.Structure):
                 ("max_gs", C.c_int32), ("max_pi", C.c_int32), ("max_outer", C.c_int32),
                 ("max_coarsest", C.c_int32), ("gs_lexicographic", C.c_int32),
                 ("gs_unshifted", C.c_int32), ("omega", C.c_double),
-                ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32)]
+                ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32),
+                ("tol_coarse", C.c_double)]
 
 
 def _i32(a):
@@ -230,11 +231,11 @@ def random_start(n, seed):
     return x
 
 
-def coarsest(n, rowptr, col, w, sig, seed, max_it=100000, replay_it=-1):
+def coarsest(n, rowptr, col, w, sig, seed, max_it=100000, replay_it=-1, tol=1e-13):
     x = np.zeros(n)
     conv = C.c_int32(0)
-    it = lib().or_coarsest(n, _i32(rowptr), _i32(col), _f64(w), sig, seed, max_it, replay_it, x,
-                           C.byref(conv))
+    it = lib().or_coarsest(n, _i32(rowptr), _i32(col), _f64(w), sig, seed, max_it, replay_it, tol,
+                           x, C.byref(conv))
     return x, it, bool(conv.value)
 
 
@@ -298,7 +299,7 @@ class Hierarchy:
 
     def solve(self, seed=1, tol_cos=1e-6, tol_res=0.0, max_gs=100, max_pi=100, max_outer=50,
               max_coarsest=100000, lexicographic=False, unshifted=False, omega=1.0,
-              replay=None) -> SolveResult:
+              replay=None, tol_coarse=1e-13) -> SolveResult:
         n0 = self.level(0).n if self.nlevels else 0
         x = np.zeros(n0)
         scal = np.zeros(3)
@@ -306,7 +307,8 @@ class Hierarchy:
         counts = np.zeros(cap, np.int32)
         clen = C.c_int32(0)
         P = SolveParams(seed, tol_cos, tol_res, max_gs, max_pi, max_outer, max_coarsest,
-                        1 if lexicographic else 0, 1 if unshifted else 0, omega, None, 0)
+                        1 if lexicographic else 0, 1 if unshifted else 0, omega, None, 0,
+                        tol_coarse)
         keep = None
         if replay is not None:
             keep = (C.c_int32 * len(replay))(*[int(v) for v in replay])

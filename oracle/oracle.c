@@ -533,13 +533,14 @@ void or_random_start(int32_t n, uint64_t seed, double* x) {
  * Coarsest-level solve (Algorithm 3, Step 2; the text calls it a direct power
  * iteration): power iteration on B = sigma I - L with the all-ones vector
  * projected out, from the seeded random start.  Before each step the residual
- * ||L x - (x^T L x) x|| of the unit iterate is compared with 1e-13 sigma; the
- * loop ends below it or after max_it steps.  replay_it >= 0 forces exactly that
- * many steps instead.  Returns the number of steps taken.
+ * ||L x - (x^T L x) x|| of the unit iterate is compared with tol * sigma (the
+ * paper leaves the tolerance open; 1e-13 by default); the loop ends at or
+ * below it or after max_it steps.  replay_it >= 0 forces exactly that many
+ * steps instead.  Returns the number of steps taken.
  */
 int32_t or_coarsest(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
                     double sigma, uint64_t seed, int32_t max_it, int32_t replay_it,
-                    double* x, int32_t* converged) {
+                    double tol, double* x, int32_t* converged) {
   double* y = (double*)malloc(sizeof(double) * (size_t)n);
   double* lx = (double*)malloc(sizeof(double) * (size_t)n);
   or_random_start(n, seed, x);
@@ -554,7 +555,7 @@ int32_t or_coarsest(int32_t n, const int32_t* rp, const int32_t* col, const doub
       double rho = or_dot(n, x, lx);
       double r2 = 0.0;
       for (int32_t i = 0; i < n; ++i) { double r = lx[i] - rho * x[i]; r2 += r * r; }
-      if (sqrt(r2) <= 1e-13 * sigma) { *converged = 1; break; }
+      if (sqrt(r2) <= tol * sigma) { *converged = 1; break; }
       if (it >= max_it) break;
     }
     or_pi_apply(n, rp, col, w, sigma, x, y);
@@ -692,6 +693,7 @@ typedef struct {
   double omega;             /* relaxation factor of the sweep; 1 = Gauss-Seidel */
   const int32_t* replay;    /* NULL, or the phase counts to execute exactly */
   int32_t replay_len;
+  double tol_coarse;        /* coarsest stop: residual <= tol_coarse * sigma */
 } or_solve_params;
 
 /* Rayleigh quotient x^T L x / x^T x in the edge form of or_rq_residual. */
@@ -793,7 +795,7 @@ int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double
   const or_level* C = &h->lv[J];
   int32_t conv = 0;
   int32_t cit = or_coarsest(C->n, C->rp, C->col, C->w, C->sigma, P->seed, P->max_coarsest,
-                            OR_NEXT_FORCED(), x, &conv);
+                            OR_NEXT_FORCED(), P->tol_coarse, x, &conv);
   if (!conv) status = OR_E_NOT_CONVERGED;
   OR_PUSH(cit);
   double cosv = 1.0;

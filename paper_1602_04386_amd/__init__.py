@@ -50,7 +50,7 @@ class fv_solve_opts(C.Structure):
                 ("tol_res", C.c_double), ("omega", C.c_double), ("max_gs", C.c_int32),
                 ("max_pi", C.c_int32), ("max_outer", C.c_int32), ("max_coarsest", C.c_int32),
                 ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("tol_coarse", C.c_double)]
 
 
 class fv_solve_stats(C.Structure):
@@ -313,12 +313,14 @@ class SolveResult:
 
 
 def solve_opts(prec="fp64", seed=1, tol_cos=1e-6, tol_res=0.0, omega=1.0, max_gs=100,
-               max_pi=100, max_outer=50, max_coarsest=100000, replay=None, stream=None):
+               max_pi=100, max_outer=50, max_coarsest=100000, replay=None, stream=None,
+               tol_coarse=1e-13):
     o = fv_solve_opts()
     lib().fv_solve_opts_default(C.byref(o))
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.seed, o.tol_cos, o.tol_res, o.omega = seed, tol_cos, tol_res, omega
     o.max_gs, o.max_pi, o.max_outer, o.max_coarsest = max_gs, max_pi, max_outer, max_coarsest
+    o.tol_coarse = tol_coarse
     keep = None
     if replay is not None:
         keep = (C.c_int32 * len(replay))(*[int(v) for v in replay])

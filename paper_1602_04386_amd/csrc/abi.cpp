@@ -145,6 +145,7 @@ void fv_solve_opts_default(fv_solve_opts* o) {
   o->replay = nullptr;
   o->replay_len = 0;
   o->stream = nullptr;
+  o->tol_coarse = 1e-13;
 }
 
 const char* fv_status_str(fv_status st) {
@@ -259,7 +260,8 @@ void fv_free_hierarchy(fv_hierarchy* h) {
 
 static fv_status check_solve_opts(const fv_solve_opts* o) {
   if (o->prec != FV_PREC_FP64 && o->prec != FV_PREC_FP32_MIXED) return FV_E_INVALID;
-  if (!(o->tol_cos >= 0.0) || !(o->tol_res >= 0.0)) return FV_E_INVALID;
+  if (!(o->tol_cos >= 0.0) || !(o->tol_res >= 0.0) || !(o->tol_coarse >= 0.0))
+    return FV_E_INVALID;
   if (!(o->omega > 0.0 && o->omega < 2.0)) return FV_E_INVALID;
   if (o->max_gs < 0 || o->max_pi < 0 || o->max_outer < 0 || o->max_coarsest < 0)
     return FV_E_INVALID;

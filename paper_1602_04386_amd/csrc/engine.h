@@ -355,7 +355,8 @@ __device__ void engine_run(const GraphTask& T, EngineCtx& E) {
   lds_ptr<VT> xl = (lds_ptr<VT>)(reinterpret_cast<VT*>(lbase));
   int conv = 0;
   const int cit =
-      engine_coarsest(lv[J], T.seed, T.max_coarsest, next_forced(), xa64, T.lx, &conv, E);
+      engine_coarsest(lv[J], T.seed, T.max_coarsest, next_forced(), T.tol_coarse, xa64, T.lx,
+                      &conv, E);
   push(cit);
   __syncthreads();
   Scal s{0.0, 1.0, 1.0, 0.0};

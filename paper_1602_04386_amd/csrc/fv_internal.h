@@ -107,7 +107,7 @@ struct GraphTask {
   int* sched_len;
   int out_buf;          // 0: iterate ends in xa, 1: in xb (written by the engine)
   unsigned long long seed;
-  double tol_cos, tol_res, omega;
+  double tol_cos, tol_res, omega, tol_coarse;
   int max_gs, max_pi, max_outer, max_coarsest;
   long long work;       // ordering key (bigger first)
 };

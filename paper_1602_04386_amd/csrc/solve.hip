@@ -201,10 +201,11 @@ struct EngineCtx {
 
 // Coarsest solve in FP64 (Algorithm 3, Step 2): power iteration on
 // sigma I - L with projection, from the seeded start, stopping when
-// ||L x - rho x|| <= 1e-13 sigma or at the cap (forced >= 0: exactly forced
+// ||L x - rho x|| <= tol sigma or at the cap (forced >= 0: exactly forced
 // steps).  Writes the unit iterate to out; returns steps, sets *conv.
 __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int max_it,
-                               int forced, double* out, double* lx, int* conv, EngineCtx& E) {
+                               int forced, double tol, double* out, double* lx, int* conv,
+                               EngineCtx& E) {
   const int n = __builtin_amdgcn_readfirstlane(L.n);  // uniform: keeps loop branches scalar
   const double sigma = L.sigma;
   const double* __restrict__ w = L.w64;
@@ -269,7 +270,7 @@ __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int 
           const double r = l - rho * x;
           const double rr = wave_sum(r * r);
           const double yy = wave_sum(y * y);
-          if (sqrt(rr) <= 1e-13 * sigma) {
+          if (sqrt(rr) <= tol * sigma) {
             cv = 1;
             break;
           }
@@ -337,7 +338,7 @@ __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int 
         r[0] += d * d;
       }
       block_sum<1>(r, E.lds);
-      if (sqrt(r[0]) <= 1e-13 * sigma) {
+      if (sqrt(r[0]) <= tol * sigma) {
         cv = 1;
         break;
       }
@@ -570,6 +571,7 @@ static void fill_task(GraphTask& T, const fv_hierarchy* h, const fv_solve_opts* 
   T.max_pi = o->max_pi;
   T.max_outer = o->max_outer;
   T.max_coarsest = o->max_coarsest;
+  T.tol_coarse = o->tol_coarse;
 }
 
 static long long schedule_bytes(const fv_hierarchy* h, const int* sched, int len, int prec) {

@@ -91,6 +91,19 @@ def test_free_run_schedule(fv, ctx, orc, name):
     assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
 
 
+@pytest.mark.parametrize("name", ["c1_grid32x24", "grid64x48u", "rgg20k"])
+def test_free_run_schedule_loose_coarsest(fv, ctx, orc, name):
+    """A loose coarsest tolerance: the same first-crossing stop on both sides."""
+    g, nc = graph(name)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    ro = oh.solve(seed=1, tol_coarse=1e-6)
+    r = fv.fiedler_solve(ctx, h, prec="fp64", seed=1, tol_coarse=1e-6)
+    assert r.schedule == ro.counts
+    assert ro.counts[0] < oh.solve(seed=1).counts[0]
+    assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+
+
 def test_c1_closed_form_tight(fv, ctx):
     """32x24 unit grid: lambda_2 = 2 - 2 cos(pi/32) (the small FP64 workload)."""
     g = gen.grid_32x24()

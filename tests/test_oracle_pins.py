@@ -391,6 +391,28 @@ def test_coarsest_power_iteration_vs_eigh(orc, seed):
     assert abs(x.sum()) < 1e-12 and abs(np.linalg.norm(x) - 1) < 1e-14
 
 
+@pytest.mark.parametrize("tol", [1e-4, 1e-6, 1e-9])
+def test_coarsest_stops_at_first_step_below_tolerance(orc, tol):
+    """The stop rule: the returned iterate is the first whose residual
+    ||L x - (x^T L x) x|| is at or below tol * sigma; the iterate one step
+    earlier (rerun with a forced count) is above it, and the residuals are
+    recomputed here from the dense Laplacian."""
+    g = gen.random_connected(20, 71)
+    L = dense_L(g.n, g.rowptr, g.col, g.w)
+    sig = orc.sigma(g.n, g.rowptr, g.w)
+
+    def res(v):
+        return np.linalg.norm(L @ v - (v @ L @ v) * v)
+
+    x, it, conv = orc.coarsest(g.n, g.rowptr, g.col, g.w, sig, 3, tol=tol)
+    assert conv and it > 0
+    assert res(x) <= tol * sig * (1 + 1e-9)
+    xp, itp, _ = orc.coarsest(g.n, g.rowptr, g.col, g.w, sig, 3, replay_it=it - 1)
+    assert itp == it - 1 and res(xp) > tol * sig * (1 - 1e-9)
+    _, it_tight, _ = orc.coarsest(g.n, g.rowptr, g.col, g.w, sig, 3)
+    assert it_tight > it
+
+
 # ------------------------------------------------------------ whole solve --
 
 TIGHT = dict(tol_cos=1e-10, tol_res=1e-9, max_gs=2000, max_pi=50, max_outer=20000)
