@@ -307,8 +307,9 @@ __global__ void k_val_values(int n, const int* rp, const int* col, const double*
   if (f) atomicOr(flags, f);
 }
 
-__global__ void k_extract(int n, const int* rp, const int* col, const double* val, int adj,
-                          const int* rpw, int* colw, double* ww) {
+__global__ void k_extract(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                          const double* __restrict__ val, int adj, const int* __restrict__ rpw,
+                          int* __restrict__ colw, double* __restrict__ ww) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int k = rpw[i];
@@ -620,13 +621,16 @@ __global__ void k_colour_ptr(int n, int ncol, int nb, const int* off, int* cptr)
 // Colour-ordered copy: row i of the solve order is original row iperm[i];
 // columns are relabelled but keep their original order (so row sums add in
 // the same order as in the original numbering).
-__global__ void k_solve_fill(int n, const int* rp_c, const int* col_c, const double* w_c,
-                             const int* iperm, const int* perm, const int* rp, int* col,
-                             double* w64, float* w32) {
+__global__ void k_solve_fill(int n, const int* __restrict__ rp_c, const int* __restrict__ col_c,
+                             const double* __restrict__ w_c, const int* __restrict__ iperm,
+                             const int* __restrict__ perm, const int* __restrict__ rp,
+                             int* __restrict__ col, double* __restrict__ w64,
+                             float* __restrict__ w32) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int v = iperm[i];
   int k = rp[i];
+#pragma unroll 4
   for (int p = rp_c[v]; p < rp_c[v + 1]; ++p, ++k) {
     col[k] = perm[col_c[p]];
     double wv = w_c[p];
@@ -648,7 +652,8 @@ __global__ void k_qs(int n, const int* perm, const int* q, const int* perm_next,
 // max(v,j)) and each run of equal J is summed sequentially in that order, so
 // W_c(I,J) and W_c(J,I) add the same fine weights in the same order.
 // ---------------------------------------------------------------------------
-__global__ void k_gal_count(int n, const int* rp, const int* col, const int* q, int* tcount) {
+__global__ void k_gal_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const int* __restrict__ q, int* __restrict__ tcount) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int I = q[v], c = 0;
@@ -656,8 +661,11 @@ __global__ void k_gal_count(int n, const int* rp, const int* col, const int* q, 
   if (c) atomicAdd(&tcount[I], c);
 }
 
-__global__ void k_gal_fill(int n, const int* rp, const int* col, const double* w, const int* q,
-                           const int* tstart, int* tfill, int* tJ, int* ta, int* tb, double* tw) {
+__global__ void k_gal_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                           const double* __restrict__ w, const int* __restrict__ q,
+                           const int* __restrict__ tstart, int* __restrict__ tfill,
+                           int* __restrict__ tJ, int* __restrict__ ta, int* __restrict__ tb,
+                           double* __restrict__ tw) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int I = q[v], c = 0;

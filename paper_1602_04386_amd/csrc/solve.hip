@@ -905,9 +905,20 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
   int dev = 0, ncu = 256;
   FV_HIP(hipGetDevice(&dev));
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  // Two 512-thread workgroups per CU (register-limited), each with its own
-  // slice of LDS for the level vector.
-  const int grid = std::min(count, std::max(1, ncu * 2));
+  // As many persistent workgroups as can be resident at once (registers and
+  // the LDS slice for the level vector decide); each takes graphs from the
+  // shared queue until it is empty.
+  int per_cu = 1;
+  if (o->prec == FV_PREC_FP32_MIXED) {
+    enable_engine_lds<float, kWGBatch>(kBatchLds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_engine<float, kWGBatch>), kWGBatch, kBatchLds);
+  } else {
+    enable_engine_lds<double, kWGBatch>(kBatchLds);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_engine<double, kWGBatch>), kWGBatch, kBatchLds);
+  }
+  const int grid = std::min(count, std::max(1, ncu * std::max(per_cu, 1)));
   hipEvent_t e0, e1;
   FV_HIP(hipEventCreate(&e0));
   FV_HIP(hipEventCreate(&e1));
