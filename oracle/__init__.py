@@ -62,6 +62,8 @@ def lib():
                                   f64p, C.POINTER(C.c_int64)]
         L.or_colour.restype = C.c_int32
         L.or_colour.argtypes = [C.c_int32, i32p, i32p, C.c_uint32, i32p]
+        L.or_recolour.restype = C.c_int32
+        L.or_recolour.argtypes = [C.c_int32, i32p, i32p, C.c_int32, i32p]
         L.or_sigma.restype = C.c_double
         L.or_sigma.argtypes = [C.c_int32, i32p, f64p]
         L.or_pi_apply.restype = None
@@ -169,6 +171,14 @@ def galerkin(n, rowptr, col, w, q, nc):
 def colour(n, rowptr, col, level_seed):
     c = np.zeros(n, np.int32)
     k = lib().or_colour(n, _i32(rowptr), _i32(col), level_seed, c)
+    assert k >= 0
+    return c, k
+
+
+def recolour(n, rowptr, col, colour_in, ncol):
+    """One iterated-greedy pass over a colouring; returns (colour, count)."""
+    c = np.array(colour_in, dtype=np.int32, copy=True)
+    k = lib().or_recolour(n, _i32(rowptr), _i32(col), ncol, c)
     assert k >= 0
     return c, k
 

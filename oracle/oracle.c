@@ -405,6 +405,48 @@ int32_t or_colour(int32_t n, const int32_t* rp, const int32_t* col, uint32_t lev
   return ncol;
 }
 
+/*
+ * One iterated-greedy pass over a colouring (Culberson's iterated greedy,
+ * one step): the colour classes are taken from the highest colour down, and
+ * each vertex takes the smallest colour that no vertex recoloured before it
+ * has among its neighbours.  A class is an independent set, so the order
+ * inside a class does not matter, and first-fit in an order that keeps every
+ * old class together never needs more colours than the old colouring.  Used
+ * after or_colour: the small last classes that first-fit leaves are mostly
+ * absorbed.  Returns the number of colours.
+ */
+int32_t or_recolour(int32_t n, const int32_t* rp, const int32_t* col, int32_t ncol,
+                    int32_t* colour) {
+  int32_t maxdeg = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (rp[i + 1] - rp[i] > maxdeg) maxdeg = rp[i + 1] - rp[i];
+  char* used = (char*)calloc((size_t)maxdeg + 2, 1);
+  int32_t* nw = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!used || !nw) { free(used); free(nw); return OR_E_NOMEM; }
+  for (int32_t v = 0; v < n; ++v) nw[v] = -1;
+  int32_t k = 0;
+  for (int32_t c = ncol - 1; c >= 0; --c)
+    for (int32_t v = 0; v < n; ++v) {
+      if (colour[v] != c) continue;
+      for (int64_t p = rp[v]; p < rp[v + 1]; ++p) {
+        int32_t cc = nw[col[p]];
+        if (cc >= 0 && cc <= maxdeg) used[cc] = 1;
+      }
+      int32_t t = 0;
+      while (used[t]) ++t;
+      nw[v] = t;
+      if (t + 1 > k) k = t + 1;
+      for (int64_t p = rp[v]; p < rp[v + 1]; ++p) {
+        int32_t cc = nw[col[p]];
+        if (cc >= 0 && cc <= maxdeg) used[cc] = 0;
+      }
+    }
+  memcpy(colour, nw, sizeof(int32_t) * (size_t)n);
+  free(nw);
+  free(used);
+  return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Level operators.                                                          */
 /* ------------------------------------------------------------------------ */
@@ -605,7 +647,8 @@ void or_hier_free(void* hp) {
 /*
  * Builds the hierarchy from the adjacency W of the finest graph: while the
  * level has more than n_coarse vertices, aggregate (matching + attach), form
- * the Galerkin coarse graph, and colour the level for the smoother.  The loop
+ * the Galerkin coarse graph, and colour the level for the smoother (first-fit
+ * in priority order, then one iterated-greedy pass).  The loop
  * also stops when the next level would have fewer than 2 vertices or would not
  * be smaller, and at max_levels levels.
  */
@@ -642,6 +685,8 @@ void* or_hier_build(int32_t n, const int32_t* rp, const int32_t* col, const doub
     F->q = q;
     F->colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
     F->ncolours = or_colour(F->n, F->rp, F->col, or_level_seed(colour_seed, l), F->colour);
+    if (F->ncolours > 0)
+      F->ncolours = or_recolour(F->n, F->rp, F->col, F->ncolours, F->colour);
     or_level* C = &h->lv[l + 1];
     C->n = nc;
     C->rp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc + 1));

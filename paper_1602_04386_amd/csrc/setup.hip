@@ -428,11 +428,24 @@ __global__ __launch_bounds__(kLocalBlock) void k_match_local(int n, const int* r
   }
 }
 
-// The whole Jones-Plassmann colouring of a small level in one workgroup;
-// *maxc receives the largest colour.
+// Smallest colour >= 0 that no neighbour in col[a, b) has in c (-1: none).
+__device__ inline int first_fit(int a, int b, const int* col, const int* c) {
+  for (int base = 0;; base += 64) {
+    unsigned long long mask = 0;
+    for (int p = a; p < b; ++p) {
+      const int k = c[col[p]];
+      if (k >= base && k < base + 64) mask |= 1ULL << (k - base);
+    }
+    if (mask != ~0ULL) return base + __builtin_ctzll(~mask);
+  }
+}
+
+// The whole Jones-Plassmann colouring of a small level in one workgroup,
+// then the iterated-greedy pass (cnew: scratch of n); *maxc receives the
+// largest colour.
 __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* rp, const int* col,
-                                                            uint32_t seed, int* colour, int* maxc,
-                                                            int* err) {
+                                                            uint32_t seed, int* colour, int* cnew,
+                                                            int* maxc, int* err) {
   __shared__ int waiting;
   __shared__ int lmax[kLocalBlock / 64];
   for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = -1;
@@ -479,7 +492,21 @@ __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* 
   int m = -1;
   for (int v = threadIdx.x; v < n; v += blockDim.x) m = max(m, colour[v]);
   m = block_max_int(m, lmax);
-  if (threadIdx.x == 0) *maxc = m;
+  // One iterated-greedy pass (k_recolour_class, class by class in this block).
+  for (int v = threadIdx.x; v < n; v += blockDim.x) cnew[v] = -1;
+  __syncthreads();
+  for (int c = m; c >= 0; --c) {
+    for (int v = threadIdx.x; v < n; v += blockDim.x)
+      if (colour[v] == c) cnew[v] = first_fit(rp[v], rp[v + 1], col, cnew);
+    __syncthreads();
+  }
+  int m2 = -1;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) {
+    colour[v] = cnew[v];
+    m2 = max(m2, cnew[v]);
+  }
+  m2 = block_max_int(m2, lmax);
+  if (threadIdx.x == 0) *maxc = m2;
 }
 
 // Aggregates (Algorithm 1): pairs; an unmatched vertex joins the aggregate of
@@ -522,6 +549,20 @@ __global__ void k_agg_minmem(int n, const int* root, int* minmem) {
 __global__ void k_agg_q(int n, const int* root, const int* minmem, const int* id, int* q) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) q[v] = id[minmem[root[v]]];
+}
+
+// ---------------------------------------------------------------------------
+// Iterated greedy (one pass): the classes of a first-fit colouring, from the
+// highest colour down, are recoloured first-fit against the vertices already
+// recoloured.  A class is an independent set, so one launch per class gives
+// the sequential pass exactly, and the result never has more colours; the
+// small last classes that first-fit leaves are mostly absorbed, each of which
+// would cost a launch per sweep.
+// ---------------------------------------------------------------------------
+__global__ void k_recolour_class(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                 const int* __restrict__ old, int* cnew, int c) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    if (old[v] == c) cnew[v] = first_fit(rp[v], rp[v + 1], col, cnew);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +987,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     int* root = tmp.get<int>(n);
     int* minmem = tmp.get<int>(n);
     int* id = tmp.get<int>(n + 1);
+    int* cnew = tmp.get<int>(n);  // the recolouring pass's output
     int* tcount = tmp.get<int>(n + 1);
     int* tstart = tmp.get<int>(n + 1);
     int* tfill = tmp.get<int>(n);
@@ -1034,7 +1076,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         // one workgroup runs every round of both loops
         k_match_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr, lflag + 2);
         aggregate();
-        k_colour_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed, F.colour_c,
+        k_colour_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed, F.colour_c, cnew,
                                                  lflag + 1, lflag + 2);
         FV_HIP(hipGetLastError());
       } else {
@@ -1055,7 +1097,18 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         read_back();
       }
       if (pin_i[2]) throw Error(FV_E_DEVICE, "matching not maximal");
+      // ncol: exact on the one-workgroup path (its kernel recolours too); an
+      // upper bound after the recolouring pass below, trimmed once the colour
+      // ranges are read back at the end of the build.
       F.ncol = pin_i[3] + 1;
+      if (!local) {
+        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(cnew, fn, -1);
+        for (int c = F.ncol - 1; c >= 0; --c)
+          k_recolour_class<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.colour_c, cnew,
+                                                             c);
+        FV_HIP(hipGetLastError());
+        FV_HIP(hipMemcpyAsync(F.colour_c, cnew, sizeof(int) * fn, hipMemcpyDeviceToDevice, s));
+      }
       const int nc = pin_i[4];
       if (nc < 2 || nc >= fn) {
         dev_free(ctx, F.colour_c, sizeof(int) * fn, &h->bytes);
@@ -1149,6 +1202,11 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
                             hipMemcpyDeviceToHost, s));
     }
     FV_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < J; ++k) {  // drop the empty last classes the recolouring left
+      Level& F = h->lv[k];
+      while (F.ncol > 1 && F.cptr_h[F.ncol - 1] == F.n) --F.ncol;
+      F.cptr_h.resize(F.ncol + 1);
+    }
     for (int k = 0; k <= J; ++k) {
       double d;
       std::memcpy(&d, &dm[k], sizeof(double));

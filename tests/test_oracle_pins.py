@@ -293,6 +293,54 @@ def test_colouring_equals_jones_plassmann(orc, seed):
     assert k <= np.diff(g.rowptr).max() + 1
 
 
+def iterated_greedy(n, rp, col, colour):
+    """Classes from the highest colour down; inside a class every vertex
+    chooses at once from a snapshot of the colours already assigned (a class
+    is an independent set, so this is the sequential pass done in rounds)."""
+    colour = np.asarray(colour)
+    new = np.full(n, -1)
+    for c in range(int(colour.max()), -1, -1):
+        snap = new.copy()
+        for v in np.nonzero(colour == c)[0]:
+            used = {int(snap[u]) for u in col[rp[v]:rp[v + 1]] if snap[u] >= 0}
+            k = 0
+            while k in used:
+                k += 1
+            new[v] = k
+    return new
+
+
+def test_recolouring_path_closed_form(orc):
+    # path a-b-c-d coloured 0,1,2,0 (first-fit in the order a, d, b, c): the
+    # pass takes c first (colour 0), then b (1), then a and d -> 2 colours
+    g = gen.path(4)
+    c, k = orc.recolour(4, g.rowptr, g.col, [0, 1, 2, 0], 3)
+    assert list(c) == [0, 1, 0, 1] and k == 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_recolouring_equals_class_rounds(orc, seed):
+    g = gen.random_connected(60 + seed, 300 + seed) if seed % 2 else gen.grid(8, 6 + seed)
+    c0, k0 = orc.colour(g.n, g.rowptr, g.col, orc.level_seed(seed, seed))
+    c, k = orc.recolour(g.n, g.rowptr, g.col, c0, k0)
+    assert list(c) == list(iterated_greedy(g.n, g.rowptr, g.col, c0))
+    assert k == max(c) + 1 and k <= k0
+    assert set(c) == set(range(k))  # first-fit leaves no gaps
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    assert np.all(c[rows] != c[g.col])
+
+
+def test_hierarchy_colourings_are_recoloured_first_fit(orc):
+    g = gen.grid(40, 30, "uniform", seed=6)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=8, colour_seed=5)
+    for l in range(h.nlevels - 1):
+        L = h.level(l)
+        c0 = jones_plassmann(L.n, L.rowptr, L.col, orc.level_seed(5, l))
+        c = iterated_greedy(L.n, L.rowptr, L.col, c0)
+        assert np.array_equal(L.colour, c), l
+        assert L.ncolours == c.max() + 1
+
+
 # ------------------------------------------------------ smoother and power --
 
 def _colour_order(c):
