@@ -347,22 +347,43 @@ __global__ __launch_bounds__(kBlock) void k_res_tile(LevelDesc L, const VT* xa, 
 
 enum FinishMode { kFinGS = 0, kFinPI = 1, kFinProlong = 2, kFinRQ = 3 };
 
+// Adds the partial-slot rows 0 .. NR-1 of slots threadIdx.x, + blockDim.x, ...
+// into S in that order.  The loads of kSlotU consecutive slots are issued
+// before any of their additions, so a large level's thousands of slots cost a
+// few memory round trips per thread instead of one per slot.
+constexpr int kSlotU = 8;
+
+template <int NR>
+__device__ inline void sum_slots(const double* part, int stride, int nslots, double (&S)[kNP]) {
+  for (int s0 = threadIdx.x; s0 < nslots; s0 += blockDim.x * kSlotU) {
+    double v[kSlotU][NR];
+#pragma unroll
+    for (int u = 0; u < kSlotU; ++u) {
+      const int s = s0 + u * blockDim.x;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[u][k] = s < nslots ? part[k * stride + s] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSlotU; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) S[k] += v[u][k];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* part, int stride,
                                                  int nslots, int n, int mode, int* rec) {
   __shared__ double lds[block_sum_lds(kBlock)];
   if ((mode == kFinGS || mode == kFinPI) && st->done) return;
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double mx = 0.0;
-#pragma unroll 4
-  for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
-    if (mode == kFinRQ) {
+  if (mode == kFinRQ) {
+    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
       S[0] += part[s];
       S[1] += part[stride + s];
       mx = fmax(mx, part[2 * stride + s]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + s];
     }
+  } else {
+    sum_slots<kNP>(part, stride, nslots, S);
   }
   const double t = block_sum_spread<kNP>(S, lds);
   if (mode == kFinRQ) {
@@ -415,10 +436,7 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
   VT* x = st->cur ? xb : xa;
   const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int sl = threadIdx.x; sl < nslots; sl += blockDim.x)
-#pragma unroll
-    for (int k = 0; k < kNP; ++k) S[k] += part[k * stride + sl];
+  sum_slots<kNP>(part, stride, nslots, S);
   for (int c = c0; c < L.ncol; ++c) {
     const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
