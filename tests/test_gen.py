@@ -1,6 +1,7 @@
 """Input generators: published SplitMix64 values and the structure of every
 graph family (symmetric CSR, sorted columns, connected where promised)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -97,3 +98,23 @@ def test_batch_mix_members(n):
     gs = gen.batch_mix(count=6, seed=4, nmin=n, nmax=n + 10)
     for g in gs:
         _check_csr(g)
+
+
+def _golden(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    with open(path) as f:
+        return [int(t) for t in (l.strip() for l in f) if t and not t.startswith("#")]
+
+
+def test_paper_square_grid_sizes():
+    """The grid family of the paper's scaling table: every listed vertex count
+    is a perfect square k*k, and the generator's k x k grid has exactly that
+    many vertices and 2k(k-1) edges (checked on the smallest listed size)."""
+    counts = _golden("table_4_2_square_grid_nodes.txt")
+    assert len(counts) == 20 and counts == sorted(counts)
+    ks = [math.isqrt(n) for n in counts]
+    assert all(k * k == n for k, n in zip(ks, counts))
+    k = ks[0]
+    g = gen.grid(k, k)
+    assert g.n == counts[0] == 326 * 326
+    assert len(g.col) == 2 * (2 * k * (k - 1))  # both directions stored
