@@ -430,18 +430,30 @@ template <class VT>
 __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* xa, VT* xb,
                                                              DevState* st, const double* part,
                                                              int stride, int nslots, int c0,
-                                                             double omega, int* rec) {
+                                                             int tr0, int tr1, double omega,
+                                                             int* rec) {
   __shared__ double lds[block_sum_lds(kTailBlock)];
   if (st->done) return;
   VT* x = st->cur ? xb : xa;
   const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
+  // The first tail colour holds rows [tr0, tr1) (at most kTailRows, one per
+  // thread); its row pointers are requested before the partial slots are
+  // added, so that the two round trips overlap.
+  const int i0 = tr0 + threadIdx.x;
+  int p0 = 0, p1 = 0;
+  if (i0 < tr1) {
+    p0 = L.rp[i0];
+    p1 = L.rp[i0 + 1];
+  }
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   sum_slots<kNP>(part, stride, nslots, S);
-  for (int c = c0; c < L.ncol; ++c) {
+  if (i0 < tr1) row_gs_batched<VT>(i0, p0, p1, L, x, tr0, mu, inv_s, rho, omega, S);
+  __syncthreads();  // the next colour reads this colour's new values
+  for (int c = c0 + 1; c < L.ncol; ++c) {
     const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-      row_gs<VT>(i, L, x, r0, mu, inv_s, rho, omega, S);
-    __syncthreads();  // the next colour reads this colour's new values
+      row_gs_batched<VT>(i, L.rp[i], L.rp[i + 1], L, x, r0, mu, inv_s, rho, omega, S);
+    __syncthreads();
   }
   const double t = block_sum_spread<kNP>(S, lds);
   if (threadIdx.x >= 64) return;

@@ -90,6 +90,72 @@ __device__ inline void row_gs(int i, const LevelDesc& L, VT* __restrict__ x, int
   acc[4] += e;
 }
 
+// row_gs with the row's pointers given and its neighbours fetched kRowB at a
+// time (every index and weight load of a batch, then every gather): the same
+// terms added in the same order, for the rows a single block sweeps.
+constexpr int kRowB = 8;
+
+template <class VT>
+__device__ inline void row_gs_batched(int i, int p0, int p1, const LevelDesc& L,
+                                      VT* __restrict__ x, int lower_end, double mu,
+                                      double inv_s, double rho, double omega,
+                                      double (&acc)[kNP]) {
+  const auto* __restrict__ w = WSel<VT>::w(L);
+  const int* __restrict__ col = L.col;
+  const double xo = ((double)x[i] - mu) * inv_s;
+  double num = 0.0, den = 0.0;
+  for (int pb = p0; pb < p1; pb += kRowB) {
+    int jj[kRowB];
+    double ww[kRowB], xx[kRowB];
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u) {
+      const int q = min(pb + u, p1 - 1);
+      jj[u] = col[q];
+      ww[u] = (double)w[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u) xx[u] = (double)x[jj[u]];
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u)
+      if (pb + u < p1) {
+        num += ww[u] * (jj[u] < lower_end ? xx[u] : (xx[u] - mu) * inv_s);
+        den += ww[u];
+      }
+  }
+  double u = xo;
+  if (den > 0.0) {
+    const double g = (num + rho * xo) / den;
+    u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
+  }
+  const VT us = (VT)u;
+  x[i] = us;
+  const double ud = (double)us;
+  double e = 0.0;
+  for (int pb = p0; pb < p1; pb += kRowB) {
+    int jj[kRowB];
+    double ww[kRowB], xx[kRowB];
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u) {
+      const int q = min(pb + u, p1 - 1);
+      jj[u] = col[q];
+      ww[u] = (double)w[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u) xx[u] = (double)x[jj[u]];
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u)
+      if (pb + u < p1 && jj[u] < lower_end) {
+        const double d = ud - xx[u];
+        e += ww[u] * d * d;
+      }
+  }
+  acc[0] += ud;
+  acc[1] += ud * ud;
+  acc[2] += ud * xo;
+  acc[3] += xo;
+  acc[4] += e;
+}
+
 // Power-iteration step of row i: y_i = sigma xhat_i - (L xhat)_i with
 // (L x)_i = sum_j w_ij (x_i - x_j).  Accumulates {sum y, sum y^2,
 // sum y xhat_i, sum xhat_i}.
@@ -486,7 +552,8 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
         }
         if (ct < L.ncol)
           k_finish_gs_tail<VT><<<1, kTailBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride, nslots,
-                                                        ct, omega, rec);
+                                                        ct, Lh.cptr_h[ct], Lh.cptr_h[ct + 1],
+                                                        omega, rec);
         else
           k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec);
       } else {

@@ -11,7 +11,13 @@
   Erdos-Renyi graphs with pendant vertices): one FP32-mixed batched launch;
   every item that reaches residual <= 1e-6 has its eigenvalue within 1e-5 of
   the FP64 oracle on the same schedule, and at least 20 of the 24 items do.
+* The smallest square grid of the paper's scaling table (326 x 326, unit
+  weights): FP32-mixed and FP64 solves with the benchmark's parameters reach
+  residual <= 1e-6 and their eigenvalues lie within the Kato-Temple bound
+  r^2 / (2 lambda_2 - lambda) of lambda_2 = 2 - 2 cos(pi / 326).
 """
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -92,3 +98,17 @@ def test_batch_mix_sample_against_oracle(fv, ctx, orc):
             assert ro.residual <= 2e-6, g.name
         h.free()
     assert converged >= 20, converged
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_paper_square_grid_closed_form(fv, ctx, prec):
+    k = 326
+    g = gen.grid(k, k)
+    print(f"case grid{k}x{k} {prec}", flush=True)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=25)
+    r = fv.fiedler_solve(ctx, h, prec=prec, **BENCH_SOLVE)
+    lam2 = 2 - 2 * math.cos(math.pi / k)  # a double eigenvalue; the next one is 2 lam2
+    assert r.residual <= 1e-6
+    res_cpu = cpu_residual(g, r.x, r.lam)
+    assert res_cpu <= 1.01e-6
+    assert abs(r.lam - lam2) <= res_cpu ** 2 / (2 * lam2 - r.lam) * 1.01

@@ -466,6 +466,22 @@ def test_coarsest_stops_at_first_step_below_tolerance(orc, tol):
 TIGHT = dict(tol_cos=1e-10, tol_res=1e-9, max_gs=2000, max_pi=50, max_outer=20000)
 
 
+def test_paper_square_grid_within_kato_temple(orc):
+    """The smallest square grid of the paper's scaling table (326 x 326 = 106,276
+    vertices, unit weights) with the SOR-accelerated parameters used for the
+    large workloads: residual <= 1e-6, and the eigenvalue within the
+    Kato-Temple bound r^2 / (lambda_next - lambda) of the double eigenvalue
+    2 - 2 cos(pi/326), the next distinct one being twice that."""
+    k = 326
+    g = gen.grid(k, k)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=25)
+    r = h.solve(seed=1, tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1,
+                max_outer=400, tol_coarse=1e-6)
+    lam2 = 2 - 2 * math.cos(math.pi / k)
+    assert r.status == 0 and r.residual <= 1e-6
+    assert abs(r.lam - lam2) <= r.residual ** 2 / (2 * lam2 - r.lam)
+
+
 @pytest.mark.parametrize("n", [2, 3, 5, 9, 16, 33, 64])
 def test_path_closed_form(orc, n):
     g = gen.path(n)
