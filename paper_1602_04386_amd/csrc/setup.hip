@@ -43,8 +43,11 @@ __device__ inline void wave_flag(int* flag) {
 }
 
 // Round kernels walk the vertices with a grid-stride loop over at most
-// kRoundGrid blocks, so that rounds which exit at once stay cheap.
-constexpr int kRoundGrid = 1024;
+// kRoundGrid blocks: one vertex per thread up to a million vertices, since a
+// working round is a chain of dependent loads per vertex (4096 instead of 1024
+// blocks cut the rounds' kernel time per build by ~0.16 ms), while a round
+// that exits at once still costs only its launch.
+constexpr int kRoundGrid = 4096;
 static inline int round_grid(int n) { return std::min(nblk(n), kRoundGrid); }
 
 
