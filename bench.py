@@ -543,7 +543,7 @@ def main():
     ap.add_argument("--probe-sweeps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one process drives one GPU here; multi-GPU runs are not supported, so --gpus must be 1"}))
         sys.exit(2)
     if args.counters_probe:
         print(json.dumps(run_counters_probe(args)))
