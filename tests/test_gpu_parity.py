@@ -104,6 +104,34 @@ def test_free_run_schedule_loose_coarsest(fv, ctx, orc, name):
     assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
 
 
+DEGENERATE = {
+    "no_smoothing": dict(max_gs=0, max_pi=5, tol_res=0.0),
+    "no_power_steps": dict(max_gs=20, max_pi=0, tol_res=0.0),
+    "no_finest_rounds": dict(max_gs=20, max_pi=1, tol_res=1e-6, max_outer=0),
+    "plain_gauss_seidel_rounds": dict(omega=1.0, max_gs=10, max_pi=1, tol_res=1e-3,
+                                      max_outer=30),
+    "single_sweep_cap": dict(omega=1.9, max_gs=1, max_pi=1, tol_res=1e-4, max_outer=40),
+}
+
+
+@pytest.mark.parametrize("name", ["c1_grid32x24", "grid256x250u"])
+@pytest.mark.parametrize("params", list(DEGENERATE))
+def test_degenerate_phase_limits(fv, ctx, orc, name, params):
+    """Phase caps of zero and one, no finest rounds, and the plain sweep: the
+    free-running GPU schedule equals the oracle's, one-workgroup engine
+    (32x24) and multi-workgroup passes (256x250) alike."""
+    g, nc = graph(name)
+    kw = dict(seed=1, tol_cos=1e-8, **DEGENERATE[params])
+    print(f"case {name} {params}", flush=True)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    ro = oh.solve(**kw)
+    r = fv.fiedler_solve(ctx, h, prec="fp64", **kw)
+    assert r.status == ro.status  # E_NOT_CONVERGED on both when the rounds run out
+    assert r.schedule == ro.counts
+    assert abs(r.lam - ro.lam) <= 1e-10 * abs(ro.lam)
+
+
 def test_c1_closed_form_tight(fv, ctx):
     """32x24 unit grid: lambda_2 = 2 - 2 cos(pi/32) (the small FP64 workload)."""
     g = gen.grid_32x24()
