@@ -11,9 +11,8 @@
  * no fusion, every loop in the order the method states it, library primitives
  * limited to qsort, sqrt and fabs.
  *
- * What the paper leaves open is fixed by the readings listed in the design
- * notes; each function below names the passage it follows and the reading it
- * takes.
+ * Where the paper leaves a choice open, a fixed reading is taken; each
+ * function below names the passage it follows and states the reading it takes.
  */
 #include <math.h>
 #include <stdint.h>
@@ -353,7 +352,9 @@ int32_t or_galerkin(int32_t n, const int32_t* rp, const int32_t* col, const doub
 }
 
 /* ------------------------------------------------------------------------ */
-/* Colouring for the multicolour Gauss-Seidel order.                        */
+/* Colouring for the multicolour Gauss-Seidel order (Algorithm 2 visits the  */
+/* rows in a fixed order; this reading visits colour classes in turn, the    */
+/* rows of a class being independent of each other).                          */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
