@@ -111,6 +111,8 @@ DEGENERATE = {
     "plain_gauss_seidel_rounds": dict(omega=1.0, max_gs=10, max_pi=1, tol_res=1e-3,
                                       max_outer=30),
     "single_sweep_cap": dict(omega=1.9, max_gs=1, max_pi=1, tol_res=1e-4, max_outer=40),
+    # met by the cascade alone: the round enqueued ahead of the residual is void
+    "tolerance_met_before_rounds": dict(max_gs=20, max_pi=1, tol_res=1.0, max_outer=50),
 }
 
 
