@@ -979,9 +979,19 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     L0.m = m0;
     L0.col_c = halloc<int>(h, m0);
     L0.w_c = halloc<double>(h, m0);
-    k_extract<<<nblk(n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, Lin->is_adjacency ? 1 : 0,
-                                         L0.rp_c, L0.col_c, L0.w_c);
-    FV_HIP(hipGetLastError());
+    if (Lin->is_adjacency) {
+      // W itself: validation rejected self-loops, so W is the input verbatim
+      // (and rp0 equals the input's row pointers); two copies at full bandwidth
+      // instead of a row-per-thread walk.
+      if (m0 > 0) {
+        FV_HIP(hipMemcpyAsync(L0.col_c, col_in, sizeof(int) * m0, hipMemcpyDeviceToDevice, s));
+        FV_HIP(hipMemcpyAsync(L0.w_c, val_in, sizeof(double) * m0, hipMemcpyDeviceToDevice, s));
+      }
+    } else {
+      k_extract<<<nblk(n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, 0, L0.rp_c, L0.col_c,
+                                           L0.w_c);
+      FV_HIP(hipGetLastError());
+    }
 
     // Scratch sized by level 0 and reused on every level.
     const long long mcap = std::max<long long>(m0, 1);
