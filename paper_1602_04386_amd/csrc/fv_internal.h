@@ -143,13 +143,17 @@ struct Level {
 // Opaque handles of the public ABI.
 namespace fv {
 // Workspace of the single-graph solve: device scratch (grown on demand,
-// counted against the budget) and a small pinned host buffer for flags.  The
-// context owns one; each serving worker owns its own so that solves on
+// counted against the budget), a small pinned host buffer for read-backs, and
+// a mapped, coherent host buffer that the finishing kernels write the phase's
+// stop flag and the finest residual into (hflags_dev is its device address).
+// The context owns one; each serving worker owns its own so that solves on
 // different streams never share it.
 struct SolveScratch {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int* pinned = nullptr;
+  int* hflags = nullptr;
+  int* hflags_dev = nullptr;
 };
 }  // namespace fv
 

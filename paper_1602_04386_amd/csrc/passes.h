@@ -114,10 +114,13 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
 // Opens a phase.  With use_halt set, a phase enqueued after the finest
 // residual met its tolerance starts finished, so the host may enqueue the next
 // finest round before it has read that residual.  *rec receives the phase's
-// step count (the finishing kernels keep it current).
+// step count (the finishing kernels keep it current); *hdone, in mapped host
+// memory, the phase's stop flag (likewise kept current).
 __global__ void k_phase_begin(DevState* st, int cap, int forced, double tol, int use_halt,
-                              int* rec) {
-  st->done = (cap <= 0 || (use_halt && st->halt)) ? 1 : 0;
+                              int* rec, int* hdone) {
+  const int done = (cap <= 0 || (use_halt && st->halt)) ? 1 : 0;
+  st->done = done;
+  *hdone = done;
   *rec = 0;
   st->iters = 0;
   st->cap = cap;
@@ -371,7 +374,8 @@ __device__ inline void sum_slots(const double* part, int stride, int nslots, dou
 }
 
 __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* part, int stride,
-                                                 int nslots, int n, int mode, int* rec) {
+                                                 int nslots, int n, int mode, int* rec,
+                                                 int* hdone) {
   __shared__ double lds[block_sum_lds(kBlock)];
   if ((mode == kFinGS || mode == kFinPI) && st->done) return;
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -414,7 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
   const int it = st->iters + 1;
   st->iters = it;
   *rec = it;
-  st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  st->done = done;
+  *hdone = done;
 }
 
 // Finishing kernel of a sweep whose last colours are small: the block first
@@ -431,7 +437,7 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
                                                              DevState* st, const double* part,
                                                              int stride, int nslots, int c0,
                                                              int tr0, int tr1, double omega,
-                                                             int* rec) {
+                                                             int* rec, int* hdone) {
   __shared__ double lds[block_sum_lds(kTailBlock)];
   if (st->done) return;
   VT* x = st->cur ? xb : xa;
@@ -467,14 +473,16 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
   const int it = st->iters + 1;
   st->iters = it;
   *rec = it;
-  st->done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  st->done = done;
+  *hdone = done;
 }
 
 template <class VT>
 __global__ __launch_bounds__(kBlock) void k_finish_res(LevelDesc L, const VT* xa, const VT* xb,
                                                      DevState* st, const double* part,
                                                      const int* ipart, int nslots,
-                                                     double tol_halt) {
+                                                     double tol_halt, double* hres) {
   __shared__ double lds[block_sum_lds(kBlock)];
   __shared__ int ilds[kBlock / 64];
   double s[1] = {0.0};
@@ -489,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_finish_res(LevelDesc L, const VT* xa
   const VT* x = st->cur ? xb : xa;
   const double res = sqrt(s[0] / st->sumsq);
   st->res = res;
+  *hres = res;
   st->halt = (tol_halt > 0.0 && res <= tol_halt) ? 1 : 0;
   st->sign_idx = c;
   const double xv = c < INT_MAX ? ((double)x[L.perm[c]] - st->mu) * st->inv_s : 1.0;

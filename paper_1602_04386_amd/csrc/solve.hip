@@ -504,14 +504,20 @@ static Workspace carve(void* base, size_t nmax, int maxcol) {
 
 // Host side of the early stop.  The host enqueues a phase in chunks of
 // kChunk steps and reads the phase's done flag after each, but it enqueues
-// chunk k+1 before it waits for the flag of chunk k: the device always has
-// queued work while the host waits, and a phase that has ended leaves at most
-// one chunk of launches that return at once.
+// chunk k+1 before it waits for chunk k: the device always has queued work
+// while the host waits, and a phase that has ended leaves at most one chunk of
+// launches that return at once.  The finishing kernels write the flag (and
+// the finest residual) into mapped host memory, so no copy enters the stream;
+// once the event after chunk k has completed, the flag holds the state after
+// chunk k or later, and a later state of the same phase is as good (the flag
+// only goes from 0 to 1 within a phase).
 struct HostSync {
-  int* flags;        // pinned host memory: two done flags, then the residual
-  hipEvent_t ev[2];  // flag slot k is valid once ev[k] has completed
-  hipEvent_t ev_res;
-  double* res() const { return reinterpret_cast<double*>(flags + 8); }
+  volatile int* hdone;     // host view of the flag
+  volatile double* hres;   // host view of the residual
+  int* hdone_dev;          // device addresses of the same
+  double* hres_dev;
+  hipEvent_t ev[2];        // recorded after chunk k (alternating)
+  hipEvent_t ev_res;       // recorded after the residual pass
 };
 
 constexpr int kChunk = 2;
@@ -527,7 +533,8 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
                             int forced, int cap, double tol, double omega, hipStream_t s,
                             HostSync& hs, int* rec, bool use_halt, BeforeWait before_wait) {
   const int lim = forced >= 0 ? forced : cap;
-  k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol, use_halt ? 1 : 0, rec);
+  k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol, use_halt ? 1 : 0, rec,
+                                hs.hdone_dev);
   VT* xa = static_cast<VT*>(W.xa);
   VT* xb = static_cast<VT*>(W.xb);
   // Trailing colours with at most kTailRows rows in all are swept by the
@@ -553,13 +560,15 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
         if (ct < L.ncol)
           k_finish_gs_tail<VT><<<1, kTailBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride, nslots,
                                                         ct, Lh.cptr_h[ct], Lh.cptr_h[ct + 1],
-                                                        omega, rec);
+                                                        omega, rec, hs.hdone_dev);
         else
-          k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec);
+          k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec,
+                                        hs.hdone_dev);
       } else {
         const int nb = nblk(L.n);
         k_pi_tile<VT><<<nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
-        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, L.n, kFinPI, rec);
+        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, L.n, kFinPI, rec,
+                                      hs.hdone_dev);
       }
     }
     FV_HIP(hipGetLastError());
@@ -575,10 +584,7 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
     enqueue(k);
     enq += k;
     const bool more = enq < lim;
-    if (more) {
-      FV_HIP(hipMemcpyAsync(hs.flags + slot, &W.st->done, sizeof(int), hipMemcpyDeviceToHost, s));
-      FV_HIP(hipEventRecord(hs.ev[slot], s));
-    }
+    if (more) FV_HIP(hipEventRecord(hs.ev[slot], s));
     if (first) {
       first = false;
       if (before_wait()) return true;
@@ -586,7 +592,7 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
     if (!more) break;
     if (prev >= 0) {
       FV_HIP(hipEventSynchronize(hs.ev[prev]));
-      if (hs.flags[prev]) break;
+      if (*hs.hdone) break;
     }
     prev = slot;
     slot ^= 1;
@@ -666,6 +672,9 @@ void release_scratch(fv_context* ctx, SolveScratch& sc) {
   release_scratch_device(ctx, sc);
   if (sc.pinned) (void)hipHostFree(sc.pinned);
   sc.pinned = nullptr;
+  if (sc.hflags) (void)hipHostFree(sc.hflags);
+  sc.hflags = nullptr;
+  sc.hflags_dev = nullptr;
 }
 
 template <class VT>
@@ -684,6 +693,11 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
     sc.ws_bytes = need;
   }
   if (!sc.pinned) FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&sc.pinned), 256, hipHostMallocDefault));
+  if (!sc.hflags) {
+    FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&sc.hflags), 256,
+                         hipHostMallocMapped | hipHostMallocCoherent));
+    FV_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&sc.hflags_dev), sc.hflags, 0));
+  }
   Workspace W = carve(sc.ws, nmax, maxcol);
   int* pinned = sc.pinned;
 
@@ -757,7 +771,10 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
     int ri = elen;
     auto next_forced = [&]() -> int { return (o->replay && ri < replay_len) ? o->replay[ri++] : -1; };
     HostSync hsync;
-    hsync.flags = pinned;
+    hsync.hdone = sc.hflags;
+    hsync.hres = reinterpret_cast<volatile double*>(sc.hflags + 8);
+    hsync.hdone_dev = sc.hflags_dev;
+    hsync.hres_dev = reinterpret_cast<double*>(sc.hflags_dev + 8);
     FV_HIP(hipEventCreateWithFlags(&hsync.ev[0], hipEventDisableTiming));
     FV_HIP(hipEventCreateWithFlags(&hsync.ev[1], hipEventDisableTiming));
     FV_HIP(hipEventCreateWithFlags(&hsync.ev_res, hipEventDisableTiming));
@@ -786,7 +803,8 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
             L, static_cast<const VT*>(W.xa), static_cast<const VT*>(W.xb), static_cast<VT*>(W.xa),
             static_cast<VT*>(W.xb), W.st, W.part, W.stride);
       }
-      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F.n, kFinProlong, nullptr);
+      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F.n, kFinProlong, nullptr,
+                                    nullptr);
       FV_HIP(hipGetLastError());
       run_phase_multi<VT>(true, F, L, W, next_forced(), o->max_gs, o->tol_cos, o->omega, s, hsync,
                           rec_slot(), false, no_wait);
@@ -803,9 +821,10 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
       const VT* xa = static_cast<const VT*>(W.xa);
       const VT* xb = static_cast<const VT*>(W.xb);
       k_rq_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.stride);
-      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F0.n, kFinRQ, nullptr);
+      k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F0.n, kFinRQ, nullptr, nullptr);
       k_res_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.ipart);
-      k_finish_res<VT><<<1, kBlock, 0, s>>>(L0, xa, xb, W.st, W.part, W.ipart, nb, tol_halt);
+      k_finish_res<VT><<<1, kBlock, 0, s>>>(L0, xa, xb, W.st, W.part, W.ipart, nb, tol_halt,
+                                            hsync.hres_dev);
       FV_HIP(hipGetLastError());
     };
     rq_res();
@@ -819,7 +838,6 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
         fp = next_forced();
       } else {
         if (!(o->tol_res > 0.0) || outer >= o->max_outer) break;
-        FV_HIP(hipMemcpyAsync(hsync.res(), &W.st->res, sizeof(double), hipMemcpyDeviceToHost, s));
         FV_HIP(hipEventRecord(hsync.ev_res, s));
         fg = fp = -1;
         spec = true;
@@ -828,7 +846,7 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
       auto residual_met = [&]() -> bool {
         if (!spec) return false;
         FV_HIP(hipEventSynchronize(hsync.ev_res));
-        return *hsync.res() <= o->tol_res;
+        return *hsync.hres <= o->tol_res;
       };
       if (run_phase_multi<VT>(true, F0, L0, W, fg, o->max_gs, o->tol_cos, o->omega, s, hsync,
                               rec_slot(), spec, residual_met)) {
