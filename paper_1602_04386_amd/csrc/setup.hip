@@ -857,6 +857,21 @@ static int read_int(const int* d, hipStream_t s, int* pinned) {
   return *pinned;
 }
 
+// The per-level maxima of the degree (as 64-bit words) and every level's
+// colour ranges, packed into out in one launch, so that the end of a build
+// reads them back with a single copy.
+struct LevelRanges {
+  const int* cptr[FV_MAX_LEVELS];
+  int len[FV_MAX_LEVELS];
+  int off[FV_MAX_LEVELS];
+};
+__global__ void k_gather_ranges(LevelRanges R, int nlev, const unsigned long long* dmax,
+                                int ndm, unsigned long long* out_dm, int* out) {
+  for (int k = threadIdx.x; k < ndm; k += blockDim.x) out_dm[k] = dmax[k];
+  for (int l = 0; l < nlev; ++l)
+    for (int k = threadIdx.x; k < R.len[l]; k += blockDim.x) out[R.off[l] + k] = R.cptr[l][k];
+}
+
 // Copies up to 8 device ints into out[0..7] (one launch, so that one
 // read-back returns them all).
 struct IntSrc {
@@ -1204,17 +1219,34 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         FV_HIP(hipGetLastError());
       }
     }
-    // Read back the shifts and colour ranges of every level at once.
+    // Read back the shifts and colour ranges of every level at once: one
+    // gather into a staging block, one copy.
+    LevelRanges R;
+    std::memset(&R, 0, sizeof(R));
+    int total = 0;
+    for (int k = 0; k < J; ++k) {
+      R.cptr[k] = h->lv[k].cptr;
+      R.len[k] = h->lv[k].ncol + 1;
+      R.off[k] = total;
+      total += R.len[k];
+    }
+    const size_t dm_bytes = sizeof(unsigned long long) * (J + 1);
+    unsigned char* stage = tmp.get<unsigned char>(dm_bytes + sizeof(int) * total);
+    k_gather_ranges<<<1, kBlock, 0, s>>>(R, J, dmax, J + 1,
+                                         reinterpret_cast<unsigned long long*>(stage),
+                                         reinterpret_cast<int*>(stage + dm_bytes));
+    FV_HIP(hipGetLastError());
+    std::vector<unsigned char> host(dm_bytes + sizeof(int) * total);
+    FV_HIP(hipMemcpyAsync(host.data(), stage, host.size(), hipMemcpyDeviceToHost, s));
+    FV_HIP(hipStreamSynchronize(s));
     std::vector<unsigned long long> dm(J + 1);
-    FV_HIP(hipMemcpyAsync(dm.data(), dmax, sizeof(unsigned long long) * (J + 1),
-                          hipMemcpyDeviceToHost, s));
+    std::memcpy(dm.data(), host.data(), dm_bytes);
     for (int k = 0; k < J; ++k) {
       Level& F = h->lv[k];
       F.cptr_h.assign(F.ncol + 1, 0);
-      FV_HIP(hipMemcpyAsync(F.cptr_h.data(), F.cptr, sizeof(int) * (F.ncol + 1),
-                            hipMemcpyDeviceToHost, s));
+      std::memcpy(F.cptr_h.data(), host.data() + dm_bytes + sizeof(int) * R.off[k],
+                  sizeof(int) * R.len[k]);
     }
-    FV_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < J; ++k) {  // drop the empty last classes the recolouring left
       Level& F = h->lv[k];
       while (F.ncol > 1 && F.cptr_h[F.ncol - 1] == F.n) --F.ncol;
