@@ -265,6 +265,76 @@ struct EngineCtx {
   int* cptr;    // LDS, kEngineMaxCol + 1 entries: the current level's colour ranges
 };
 
+// Sum over lanes 0..31 of a wave whose lanes 32..63 hold zeros: the same
+// value as wave_sum (whose upper half adds two exact zeros) with half the
+// read-outs.
+__device__ inline double wave_sum_low32(double v) {
+  v = row_sum16(v);
+  auto lane_val = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  return lane_val(0) + lane_val(16);
+}
+
+// The power-iteration steps of the one-wavefront coarsest solve, lane i
+// holding x_i (lanes >= n hold 0).  R > 0: row i of W in R registers (columns
+// j >= n are zero), n <= R <= 32; R = 0: rows read from LDS, any n <= 64.
+// Runs until the stop test passes (cv = 1), max_it steps, or exactly forced
+// steps; returns the steps taken and leaves the iterate in x.
+template <int R>
+__device__ int coarsest_steps(__attribute__((address_space(3))) const double* Wd, int n, int base,
+                              bool has, double sigma, double tol, int max_it, int forced,
+                              double& x, int& cv) {
+  auto bcast = [](double v, int j) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), j),
+                            __builtin_amdgcn_readlane(__double2loint(v), j));
+  };
+  auto sum = [](double v) { return R > 0 ? wave_sum_low32(v) : wave_sum(v); };
+  double wr[R > 0 ? R : 1];
+#pragma unroll
+  for (int j = 0; j < R; ++j) wr[j] = j < n ? Wd[j * n + base] : 0.0;
+  int it = 0;
+  cv = 0;
+  for (;;) {
+    double l = 0.0;
+    if (R > 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) l += wr[j] * (x - bcast(x, j));
+    } else {
+      for (int j = 0; j < n; ++j) l += Wd[j * n + base] * (x - bcast(x, j));
+    }
+    l = has ? l : 0.0;
+    // The shifted step does not depend on the stop test, so its mean is
+    // reduced together with the Rayleigh quotient.
+    double y = has ? sigma * x - l : 0.0;
+    const double rho = sum(x * l);
+    const double my = sum(y) / n;
+    y = has ? y - my : 0.0;
+    if (forced >= 0) {
+      if (it >= forced) {
+        cv = 1;
+        break;
+      }
+    } else {
+      const double r = l - rho * x;
+      const double rr = sum(r * r);
+      const double yy = sum(y * y);
+      if (sqrt(rr) <= tol * sigma) {
+        cv = 1;
+        break;
+      }
+      if (it >= max_it) break;
+      x = y * (1.0 / sqrt(yy));
+      ++it;
+      continue;
+    }
+    x = y * (1.0 / sqrt(sum(y * y)));
+    ++it;
+  }
+  return it;
+}
+
 // Coarsest solve in FP64 (Algorithm 3, Step 2): power iteration on
 // sigma I - L with projection, from the seeded start, stopping when
 // ||L x - rho x|| <= tol sigma or at the cap (forced >= 0: exactly forced
@@ -299,55 +369,15 @@ __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int 
       double m = wave_sum(x) / n;
       x = has ? x - m : 0.0;
       x *= 1.0 / sqrt(wave_sum(x * x));
-      // Up to 32 vertices (the usual coarsest size) the row is also held in
-      // registers, so an iteration touches no memory at all.
-      constexpr int kRegRow = 32;
-      double wr[kRegRow];
-#pragma unroll
-      for (int j = 0; j < kRegRow; ++j) wr[j] = j < n ? Wd[j * n + base] : 0.0;
-      auto bcast = [](double v, int j) {
-        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), j),
-                                __builtin_amdgcn_readlane(__double2loint(v), j));
-      };
       int cv = 0;
-      for (;;) {
-        double l = 0.0;
-        if (n <= kRegRow) {
-          // Columns j >= n have wr[j] = 0 and x_j = 0: exact zeros added after
-          // the real terms, so no per-column branch is needed.
-#pragma unroll
-          for (int j = 0; j < kRegRow; ++j) l += wr[j] * (x - bcast(x, j));
-        } else {
-          for (int j = 0; j < n; ++j) l += Wd[j * n + base] * (x - bcast(x, j));
-        }
-        l = has ? l : 0.0;
-        // The shifted step does not depend on the stop test, so its mean is
-        // reduced together with the Rayleigh quotient.
-        double y = has ? sigma * x - l : 0.0;
-        const double rho = wave_sum(x * l);
-        const double my = wave_sum(y) / n;
-        y = has ? y - my : 0.0;
-        if (forced >= 0) {
-          if (it >= forced) {
-            cv = 1;
-            break;
-          }
-        } else {
-          const double r = l - rho * x;
-          const double rr = wave_sum(r * r);
-          const double yy = wave_sum(y * y);
-          if (sqrt(rr) <= tol * sigma) {
-            cv = 1;
-            break;
-          }
-          if (it >= max_it) break;
-          x = y * (1.0 / sqrt(yy));
-          ++it;
-          continue;
-        }
-        x = y * (1.0 / sqrt(wave_sum(y * y)));
-        ++it;
-      }
+      // Up to 32 vertices (the usual coarsest size) the row is also held in
+      // registers, so an iteration touches no memory at all; the row length is
+      // rounded up to 8, 16, 24 or 32 (the padding columns add exact zeros).
+      if (n <= 8) it = coarsest_steps<8>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
+      else if (n <= 16) it = coarsest_steps<16>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
+      else if (n <= 24) it = coarsest_steps<24>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
+      else if (n <= 32) it = coarsest_steps<32>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
+      else it = coarsest_steps<0>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
       if (has) out[lane] = x;
       if (lane == 0) {
         s_it = it;
