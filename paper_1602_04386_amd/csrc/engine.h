@@ -37,14 +37,37 @@ struct LView {
 
 // ---- per-row arithmetic on a view (same operation order as row_gs & co.) --
 
-// Neighbours of a row fetched per batch: the batch's column indices and
-// weights are loaded first (indices past the row end repeat its last entry and
-// get weight 0, so no load is conditional), then the neighbour values; the
-// first batch's values stay in registers for the edge-energy pass.  The sums
-// take the same terms in the same order as a plain loop (the padding adds
-// exact zeros at the end).  Eight entries cover most coarse rows in one batch
-// (four left the engine's sweeps 8 % slower: a second dependent round trip).
+// Neighbours of a row are fetched in batches of kRowU entries: the batch's
+// column indices and weights are loaded first (indices past the row end
+// repeat its last entry, so no load is conditional), then the neighbour
+// values, and only then is any of them used.  The scheduling barriers keep
+// the compiler from interleaving loads and uses (it otherwise waits for each
+// weight before issuing the next load: one memory round trip per entry).
+// The first batch's values stay in registers for the edge-energy pass; later
+// batches are fetched again for it.  The sums take the same terms in the same
+// order as a plain loop over the row (padding entries add exact zeros at the
+// end).  Eight entries cover most coarse rows in one batch (four left the
+// engine's sweeps 8 % slower: a second dependent round trip).
 constexpr int kRowU = 8;
+
+template <class VT, class V, class XP>
+__device__ __forceinline__ void vrow_batch(const V& L, XP x, int pb, int p1, int (&jj)[kRowU],
+                                           double (&ww)[kRowU], double (&xx)[kRowU]) {
+  VT wr[kRowU], xr[kRowU];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) jj[u] = L.col[min(pb + u, p1 - 1)];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) wr[u] = L.w[min(pb + u, p1 - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) xr[u] = x[jj[u]];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) {
+    ww[u] = pb + u < p1 ? (double)wr[u] : 0.0;
+    xx[u] = (double)xr[u];
+  }
+}
 
 template <class VT, class V, class XP>
 __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, double mu, double inv_s,
@@ -57,14 +80,7 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
   for (int pb = p0; pb < p1; pb += kRowU) {
     int jj[kRowU];
     double ww[kRowU], xx[kRowU];
-#pragma unroll
-    for (int u = 0; u < kRowU; ++u) {
-      const int q = min(pb + u, p1 - 1);
-      jj[u] = L.col[q];
-      ww[u] = pb + u < p1 ? (double)L.w[q] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kRowU; ++u) xx[u] = (double)x[jj[u]];
+    vrow_batch<VT>(L, x, pb, p1, jj, ww, xx);
 #pragma unroll
     for (int u = 0; u < kRowU; ++u) {
       num += ww[u] * (jj[u] < lower_end ? xx[u] : (xx[u] - mu) * inv_s);
@@ -93,11 +109,14 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
       const double d = ud - x0[k];
       e += (j0[k] < lower_end ? w0[k] : 0.0) * d * d;
     }
-  for (int p = p0 + kRowU; p < p1; ++p) {
-    const int j = L.col[p];
-    if (j < lower_end) {
-      const double d = ud - (double)x[j];
-      e += (double)L.w[p] * d * d;
+  for (int pb = p0 + kRowU; pb < p1; pb += kRowU) {
+    int jj[kRowU];
+    double ww[kRowU], xx[kRowU];
+    vrow_batch<VT>(L, x, pb, p1, jj, ww, xx);
+#pragma unroll
+    for (int k = 0; k < kRowU; ++k) {
+      const double d = ud - xx[k];
+      e += (jj[k] < lower_end ? ww[k] : 0.0) * d * d;
     }
   }
   acc[0] += ud;

@@ -22,7 +22,15 @@
 // through the lost occupancy.
 template <class WT, class XT>
 constexpr int tile_cap() { return 2048; }
-constexpr int kStageU = 8;  // staged entries per thread and load round
+constexpr int kStageU = 8;  // staging slots per thread: kStageU * kBlock = the tile capacity
+
+// Waves per SIMD that a tile kernel's LDS leaves room for: six FP32 tiles
+// (25 KB each) or three FP64 tiles fit a CU.  The kernels ask the compiler for
+// that many so that registers never cut the occupancy below what LDS allows
+// (at 86 registers the FP32 sweep ran five blocks per CU, and the 1,488-block
+// colours of the 1024 x 1000 grid then needed a second round of blocks).
+template <class VT>
+constexpr int tile_waves() { return sizeof(VT) == 4 ? 6 : 3; }
 
 template <class WT, class XT>
 struct TileLds {
@@ -32,6 +40,38 @@ struct TileLds {
   WT w[kCap];
   XT x[kCap];
 };
+
+// Stages a chunk of cnt <= U * kBlock entries starting at CSR position p_lo:
+// thread t takes entries u * kBlock + t (u < U).  Every load and LDS store is
+// unconditional (positions past the chunk repeat its last entry and land in
+// LDS slots that no row reads), and all index and weight loads come before
+// all gathers: the chunk costs two memory round trips.  With loads or stores
+// under per-entry conditions the compiler moves loads next to their
+// conditional use and waits for each before issuing the next.
+template <int U, class WT, class XT, class G>
+__device__ __forceinline__ void stage_chunk(const int* __restrict__ col,
+                                            const WT* __restrict__ w, int p_lo, int cnt,
+                                            TileLds<WT, XT>& T, G gather) {
+  static_assert(U * kBlock <= TileLds<WT, XT>::kCap, "staging slots exceed the tile");
+  const int t = threadIdx.x;
+  int cc[U];
+  WT ww[U];
+  XT xx[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) cc[u] = col[p_lo + min(u * kBlock + t, cnt - 1)];
+#pragma unroll
+  for (int u = 0; u < U; ++u) ww[u] = w[p_lo + min(u * kBlock + t, cnt - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < U; ++u) xx[u] = gather(cc[u]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    T.col[u * kBlock + t] = cc[u];
+    T.w[u * kBlock + t] = ww[u];
+    T.x[u * kBlock + t] = xx[u];
+  }
+}
 
 // Walks the rows [rs, re) (re - rs <= kBlock) of a tile chunk by chunk.  For
 // each chunk it stages the CSR slice and gather(col) in LDS, then calls
@@ -75,33 +115,14 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
       if (T.rp[mid] - p_lo <= T.kCap) a = mid; else b = mid - 1;
     }
     const int hi = a, cnt = T.rp[hi] - p_lo;
-    // kStageU entries per thread per round: all index and weight loads of the
-    // round are issued first, then all gathers, so a round costs two memory
-    // round trips instead of two per entry.
-    for (int base = 0; base < cnt; base += kStageU * kBlock) {
-      int cc[kStageU];
-      WT ww[kStageU];
-#pragma unroll
-      for (int u = 0; u < kStageU; ++u) {
-        const int k = base + u * kBlock + t;
-        cc[u] = k < cnt ? col[p_lo + k] : 0;
-        ww[u] = k < cnt ? w[p_lo + k] : WT(0);
-      }
-      XT xx[kStageU];
-#pragma unroll
-      for (int u = 0; u < kStageU; ++u) {
-        const int k = base + u * kBlock + t;
-        xx[u] = k < cnt ? gather(cc[u]) : XT(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kStageU; ++u) {
-        const int k = base + u * kBlock + t;
-        if (k < cnt) {
-          T.col[k] = cc[u];
-          T.w[k] = ww[u];
-          T.x[k] = xx[u];
-        }
-      }
+    // A chunk with at most half the slots filled takes the narrow form, so no
+    // load is wasted on the common short tiles.
+    if (cnt <= 0) {
+      // rows without entries: nothing to stage
+    } else if (cnt <= (kStageU / 2) * kBlock) {
+      stage_chunk<kStageU / 2>(col, w, p_lo, cnt, T, gather);
+    } else {
+      stage_chunk<kStageU>(col, w, p_lo, cnt, T, gather);
     }
     __syncthreads();
     if (t >= lo && t < hi) body(t, T.rp[t] - p_lo, T.rp[t + 1] - p_lo);
@@ -139,7 +160,7 @@ __device__ inline void store_block_sum(double (&S)[kNP], double* lds, double* pa
 // ---- smoothing sweep, one colour -------------------------------------------
 
 template <class VT>
-__global__ __launch_bounds__(kBlock) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
+__global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride,
                                                   int slot_base, double omega) {
   __shared__ TileLds<VT, VT> T;
@@ -196,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_tile(LevelDesc L, int r0, int r1,
 // ---- power step ------------------------------------------------------------
 
 template <class VT>
-__global__ __launch_bounds__(kBlock) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
+__global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride) {
   __shared__ TileLds<VT, VT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
@@ -238,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
 // ---- prolongation ----------------------------------------------------------
 
 template <class SRC, class VT>
-__global__ __launch_bounds__(kBlock) void k_prolong_tile(LevelDesc L, const SRC* xc_a,
+__global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_prolong_tile(LevelDesc L, const SRC* xc_a,
                                                        const SRC* xc_b, VT* xf_a, VT* xf_b,
                                                        const DevState* st, double* part,
                                                        int stride) {
