@@ -137,6 +137,21 @@ def grid(rows: int, cols: int, weights: str = "unit", seed: int = 0, lo: float =
     return _csr_from_undirected(rows * cols, a, b, w, f"grid{rows}x{cols}")
 
 
+def grid_with_hub(rows: int, cols: int, stride: int, seed: int = 0) -> Graph:
+    """rows x cols 5-point grid (weights U[0.5, 1.5] as ``grid(..., "uniform",
+    seed)``) plus one hub vertex, id rows*cols, joined to every stride-th grid
+    vertex with weight 1: a graph with one very long row among short ones."""
+    g = grid(rows, cols, "uniform", seed=seed)
+    n0 = rows * cols
+    r = np.repeat(np.arange(n0, dtype=np.int64), np.diff(g.rowptr))
+    upper = g.col > r
+    a = np.concatenate([r[upper], np.arange(0, n0, stride, dtype=np.int64)])
+    b = np.concatenate([g.col[upper].astype(np.int64),
+                        np.full(len(range(0, n0, stride)), n0, dtype=np.int64)])
+    w = np.concatenate([g.w[upper], np.ones(len(range(0, n0, stride)))])
+    return _csr_from_undirected(n0 + 1, a, b, w, f"grid{rows}x{cols}hub{stride}")
+
+
 def largest_component(g: Graph) -> Graph:
     """Largest connected component, vertices relabelled in their original order."""
     from scipy.sparse import csr_matrix

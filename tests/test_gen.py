@@ -51,6 +51,23 @@ def test_grid_structure():
     assert gu.w[gu.rowptr[0] + 1] == 0.5 + u0[1]  # edge (0,10)
 
 
+def test_grid_with_hub_structure():
+    g = gen.grid_with_hub(16, 10, 4, seed=3)
+    _check_csr(g)
+    deg = np.diff(g.rowptr)
+    hub = g.n - 1
+    assert g.n == 161 and deg[hub] == 40
+    assert np.array_equal(g.col[g.rowptr[hub]:], np.arange(0, 160, 4))
+    assert np.all(g.w[g.rowptr[hub]:] == 1.0)
+    # the grid part keeps the grid's edges and weights
+    gu = gen.grid(16, 10, "uniform", seed=3)
+    for v in (0, 5, 77, 159):
+        row = dict(zip(g.col[g.rowptr[v]:g.rowptr[v + 1]], g.w[g.rowptr[v]:g.rowptr[v + 1]]))
+        ref = dict(zip(gu.col[gu.rowptr[v]:gu.rowptr[v + 1]], gu.w[gu.rowptr[v]:gu.rowptr[v + 1]]))
+        assert {k: x for k, x in row.items() if k != hub} == ref
+        assert (hub in row) == (v % 4 == 0)
+
+
 def test_grid_c2_sizes():
     g = gen.grid_1024x1000()
     assert g.n == 1024000 and g.m == 4091952

@@ -27,6 +27,9 @@ CASES = {
     "er3000": (lambda: gen.erdos_renyi(3000, 6 / 2999, 11), 25),
     "rgg20k": (lambda: gen.rgg(20000, 5), 25),
     "grid256x250u": (lambda: gen.grid(256, 250, "uniform", seed=2), 25),
+    # a 3,200-entry row on a multi-workgroup level (longer than a tile's
+    # staging capacity: the row takes the direct path) beside short rows
+    "gridhub128x100": (lambda: gen.grid_with_hub(128, 100, 4, seed=6), 25),
 }
 _graphs = {}
 
