@@ -133,9 +133,9 @@ __device__ __forceinline__ Scal vsweep(const V& L, XP x, Scal s, double omega, E
     const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
       vrow_gs<VT>(i, L, x, r0, s.mu, s.inv_s, s.rho, omega, acc);
-    __syncthreads();
+    if (c + 1 < L.ncol) __syncthreads();  // the last colour: block_allsum's barrier
   }
-  block_sum<kNP>(acc, E.lds);
+  block_allsum<kNP>(acc, E.red, E.flip);
   return after_gs(acc, L.n);
 }
 
@@ -158,8 +158,7 @@ __device__ __forceinline__ Scal vpi_step(const V& L, XP x, VT* y, Scal s, Engine
     acc[2] += yd * xo;
     acc[3] += xo;
   }
-  __syncthreads();
-  block_sum<kNP>(acc, E.lds);
+  block_allsum<kNP>(acc, E.red, E.flip);  // its barrier also orders the y writes
   for (int i = threadIdx.x; i < L.n; i += blockDim.x) x[i] = y[i];
   __syncthreads();
   Scal r = after_gs(acc, L.n);
@@ -185,8 +184,7 @@ __device__ __forceinline__ Scal vprolong(const V& L, const SRC* xc, XP xf, Scal 
     acc[1] += v * v;
     acc[4] += 0.5 * e;
   }
-  __syncthreads();
-  block_sum<kNP>(acc, E.lds);
+  block_allsum<kNP>(acc, E.red, E.flip);  // its barrier also orders the xf writes
   return after_prolong(acc, L.n);
 }
 
@@ -493,7 +491,9 @@ __global__ __launch_bounds__(NT) void k_engine(const GraphTask* tasks, int ntask
   __shared__ int ilds[NT / 64];
   __shared__ int s_cptr[kEngineMaxCol + 1];
   __shared__ int s_task;
-  EngineCtx E{lds, ilds, fv_dyn_lds, lds_cap, lds_cap * (int)sizeof(VT), s_cptr};
+  __shared__ double red[2 * block_sum_lds(NT)];
+  EngineCtx E{lds, ilds, fv_dyn_lds, lds_cap, lds_cap * (int)sizeof(VT), s_cptr,
+              (__attribute__((address_space(3))) double*)red, 0};
   for (;;) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(queue, 1u);
     __syncthreads();

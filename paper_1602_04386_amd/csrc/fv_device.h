@@ -135,6 +135,30 @@ __device__ inline void block_sum(double (&v)[NP], double* lds) {
   __syncthreads();
 }
 
+// The same totals as block_sum, bit for bit, with one barrier: every wave
+// (instead of wave 0 alone) reads the row sums and adds them with the same
+// wave_sum.  buf holds two regions of block_sum_lds(blockDim.x) doubles used
+// alternately (flip toggles on every call, and every thread makes the same
+// calls), so a call never overwrites row sums that a slower wave may still be
+// reading from the previous call; two calls on one region are separated by
+// the barrier of the call between them.  Every thread must call.
+template <int NP>
+__device__ inline void block_allsum(double (&v)[NP], __attribute__((address_space(3))) double* buf,
+                                    int& flip) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __attribute__((address_space(3))) double* lds = buf + flip * block_sum_lds((int)blockDim.x);
+  flip ^= 1;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) v[k] = row_sum16(v[k]);
+  if ((lane & 15) == 0)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) lds[(wid * 4 + (lane >> 4)) * NP + k] = v[k];
+  __syncthreads();
+  const int nr = nw * 4;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) v[k] = wave_sum(lane < nr ? lds[lane * NP + k] : 0.0);
+}
+
 // Sum of NP values over the block for a single consumer: thread k < NP
 // returns the block total of value k (other threads return 0).  Rows of 16
 // lanes are summed with DPP as in block_sum; thread k then adds the block's

@@ -263,6 +263,8 @@ struct EngineCtx {
   int cap;      // capacity in vector entries
   int bytes;    // size in bytes
   int* cptr;    // LDS, kEngineMaxCol + 1 entries: the current level's colour ranges
+  __attribute__((address_space(3))) double* red;  // 2 * block_sum_lds(threads) doubles
+  int flip;     // block_allsum's region toggle
 };
 
 // Sum over lanes 0..31 of a wave whose lanes 32..63 hold zeros: the same
