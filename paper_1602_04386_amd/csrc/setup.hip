@@ -432,7 +432,8 @@ __global__ __launch_bounds__(kLocalBlock) void k_match_local(int n, const int* r
 }
 
 // Smallest colour >= 0 that no neighbour in col[a, b) has in c (-1: none).
-__device__ inline int first_fit(int a, int b, const int* col, const int* c) {
+template <class IP, class CP>
+__device__ inline int first_fit(int a, int b, IP col, CP c) {
   for (int base = 0;; base += 64) {
     unsigned long long mask = 0;
     for (int p = a; p < b; ++p) {
@@ -443,14 +444,74 @@ __device__ inline int first_fit(int a, int b, const int* col, const int* c) {
   }
 }
 
+// Neighbours loaded per batch by the colouring kernels: all column indices of
+// a batch, then all their colours, before any is used (a row of up to eight
+// neighbours costs two dependent loads instead of two per neighbour).
+// Positions past the row end repeat its last neighbour, which changes
+// neither a wait test nor a set of used colours.
+constexpr int kNbU = 8;
+
+template <class IP, class CP>
+__device__ inline void load_nb(int pb, int b, IP col, CP c, int (&u)[kNbU], int (&cu)[kNbU]) {
+#pragma unroll
+  for (int k = 0; k < kNbU; ++k) u[k] = col[min(pb + k, b - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < kNbU; ++k) cu[k] = c[u[k]];
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// first_fit with batched loads: the colours below 64 that the neighbours
+// use, as a bit mask; the rare full mask falls back to first_fit.
+template <class IP, class CP>
+__device__ inline int first_fit_batched(int a, int b, IP col, CP c) {
+  unsigned long long mask = 0;
+  for (int pb = a; pb < b; pb += kNbU) {
+    int u[kNbU], cu[kNbU];
+    load_nb(pb, b, col, c, u, cu);
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k)
+      if (cu[k] >= 0 && cu[k] < 64) mask |= 1ULL << cu[k];
+  }
+  return mask != ~0ULL ? __builtin_ctzll(~mask) : first_fit(a, b, col, c);
+}
+
+// One Jones-Plassmann test of uncoloured vertex v with row [a, b): returns
+// true when an uncoloured neighbour of higher priority (ties: smaller index)
+// makes v wait; otherwise *fit is v's first-fit colour.  The colours read for
+// the test are final for every coloured neighbour (each has higher priority,
+// and no lower-priority neighbour can be coloured before v), so the first fit
+// is taken from the same loads.
+template <class IP, class CP>
+__device__ inline bool jp_try(int v, int a, int b, IP col, CP colour, uint32_t seed, int* fit) {
+  const uint32_t pv = colour_priority(v, seed);
+  bool wait = false;
+  unsigned long long mask = 0;
+  for (int pb = a; pb < b; pb += kNbU) {
+    int u[kNbU], cu[kNbU];
+    load_nb(pb, b, col, colour, u, cu);
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) {
+      if (cu[k] < 0) {
+        const uint32_t pu = colour_priority(u[k], seed);
+        wait = wait || pu > pv || (pu == pv && u[k] < v);
+      } else if (cu[k] < 64) {
+        mask |= 1ULL << cu[k];
+      }
+    }
+  }
+  if (wait) return true;
+  *fit = mask != ~0ULL ? __builtin_ctzll(~mask) : first_fit(a, b, col, colour);
+  return false;
+}
+
 // The whole Jones-Plassmann colouring of a small level in one workgroup,
 // then the iterated-greedy pass (cnew: scratch of n); *maxc receives the
-// largest colour.
-__global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* rp, const int* col,
-                                                            uint32_t seed, int* colour, int* cnew,
-                                                            int* maxc, int* err) {
-  __shared__ int waiting;
-  __shared__ int lmax[kLocalBlock / 64];
+// largest colour.  IP / CP are the pointer types of the CSR and of the two
+// colour arrays (LDS when the level fits, global otherwise).
+template <class IP, class CP>
+__device__ void colour_local_body(int n, IP rp, IP col, uint32_t seed, CP colour, CP cnew,
+                                  int* maxc, int* err, int& waiting, int* lmax) {
   for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = -1;
   __syncthreads();
   for (int round = 0;; ++round) {
@@ -458,31 +519,12 @@ __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* 
     __syncthreads();
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       if (colour[v] >= 0) continue;
-      const uint32_t pv = colour_priority(v, seed);
-      const int a = rp[v], b = rp[v + 1];
-      bool wait = false;
-      for (int p = a; p < b && !wait; ++p) {
-        const int u = col[p];
-        if (colour[u] < 0) {
-          const uint32_t pu = colour_priority(u, seed);
-          wait = pu > pv || (pu == pv && u < v);
-        }
-      }
-      if (wait) {
+      int fit;
+      if (jp_try(v, rp[v], rp[v + 1], col, colour, seed, &fit)) {
         waiting = 1;
         continue;
       }
-      for (int base = 0;; base += 64) {
-        unsigned long long mask = 0;
-        for (int p = a; p < b; ++p) {
-          const int c = colour[col[p]];
-          if (c >= base && c < base + 64) mask |= 1ULL << (c - base);
-        }
-        if (mask != ~0ULL) {
-          colour[v] = base + __builtin_ctzll(~mask);
-          break;
-        }
-      }
+      colour[v] = fit;
     }
     __syncthreads();
     if (!waiting) break;
@@ -500,7 +542,7 @@ __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* 
   __syncthreads();
   for (int c = m; c >= 0; --c) {
     for (int v = threadIdx.x; v < n; v += blockDim.x)
-      if (colour[v] == c) cnew[v] = first_fit(rp[v], rp[v + 1], col, cnew);
+      if (colour[v] == c) cnew[v] = first_fit_batched(rp[v], rp[v + 1], col, cnew);
     __syncthreads();
   }
   int m2 = -1;
@@ -510,6 +552,41 @@ __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, const int* 
   }
   m2 = block_max_int(m2, lmax);
   if (threadIdx.x == 0) *maxc = m2;
+}
+
+// Bytes of dynamic LDS that k_colour_local stages a level into: row
+// pointers, column indices and both colour arrays.  Levels whose CSR does
+// not fit run on global memory.
+__host__ __device__ inline size_t colour_local_lds(int n, long long m) {
+  return 4 * ((size_t)n + 1) + 4 * (size_t)m + 8 * (size_t)n;
+}
+constexpr size_t kColourLocalLds = 144 * 1024;
+
+// lds_bytes: the dynamic LDS the launch provides (0: none).  With the level
+// in LDS every neighbour test is an LDS access instead of a dependent global
+// load (the largest local level coloured in ~140 us on global memory).
+__global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, long long m, const int* rp,
+                                                            const int* col, uint32_t seed,
+                                                            int* colour, int* cnew, int* maxc,
+                                                            int* err, int lds_bytes) {
+  extern __shared__ __align__(16) unsigned char cl_dyn[];
+  __shared__ int waiting;
+  __shared__ int lmax[kLocalBlock / 64];
+  using lint = __attribute__((address_space(3))) int*;
+  if (lds_bytes > 0 && colour_local_lds(n, m) <= (size_t)lds_bytes) {
+    lint lrp = (lint)(reinterpret_cast<int*>(cl_dyn));
+    lint lcol = lrp + (n + 1);
+    lint lc = lcol + m;
+    lint lnew = lc + n;
+    for (int k = threadIdx.x; k <= n; k += blockDim.x) lrp[k] = rp[k];
+    for (long long k = threadIdx.x; k < m; k += blockDim.x) lcol[k] = col[k];
+    __syncthreads();
+    colour_local_body(n, lrp, lcol, seed, lc, lnew, maxc, err, waiting, lmax);
+    __syncthreads();
+    for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = lc[v];
+  } else {
+    colour_local_body(n, rp, col, seed, colour, cnew, maxc, err, waiting, lmax);
+  }
 }
 
 // Aggregates (Algorithm 1): pairs; an unmatched vertex joins the aggregate of
@@ -565,7 +642,7 @@ __global__ void k_agg_q(int n, const int* root, const int* minmem, const int* id
 __global__ void k_recolour_class(int n, const int* __restrict__ rp, const int* __restrict__ col,
                                  const int* __restrict__ old, int* cnew, int c) {
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    if (old[v] == c) cnew[v] = first_fit(rp[v], rp[v + 1], col, cnew);
+    if (old[v] == c) cnew[v] = first_fit_batched(rp[v], rp[v + 1], col, cnew);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,31 +656,12 @@ __global__ void k_colour_round(int n, const int* rp, const int* col, uint32_t se
   bool wait_any = false;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     if (colour[v] >= 0) continue;
-    const uint32_t pv = colour_priority(v, seed);
-    const int a = rp[v], b = rp[v + 1];
-    bool wait = false;
-    for (int p = a; p < b && !wait; ++p) {
-      const int u = col[p];
-      if (colour[u] < 0) {
-        const uint32_t pu = colour_priority(u, seed);
-        wait = pu > pv || (pu == pv && u < v);
-      }
-    }
-    if (wait) {
+    int fit;
+    if (jp_try(v, rp[v], rp[v + 1], col, colour, seed, &fit)) {
       wait_any = true;
       continue;
     }
-    for (int base = 0;; base += 64) {
-      unsigned long long mask = 0;
-      for (int p = a; p < b; ++p) {
-        const int c = colour[col[p]];
-        if (c >= base && c < base + 64) mask |= 1ULL << (c - base);
-      }
-      if (mask != ~0ULL) {
-        colour[v] = base + __builtin_ctzll(~mask);
-        break;
-      }
-    }
+    colour[v] = fit;
   }
   if (__ballot(wait_any) != 0ULL && (threadIdx.x & 63) == 0) *active = 1;
 }
@@ -915,6 +973,16 @@ void free_hierarchy(fv_hierarchy* h) {
 
 size_t hierarchy_nmax(const fv_hierarchy* h) { return h->levels ? (size_t)h->lv[0].n : 0; }
 
+// Allows k_colour_local more than the 64 KiB of dynamic LDS a launch gets by
+// default; done once per process.
+static void enable_colour_local_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    FV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colour_local),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kColourLocalLds));
+  });
+}
+
 fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_opts* o,
                               hipStream_t s) {
   if (!Lin) throw Error(FV_E_INVALID, "null graph");
@@ -1104,8 +1172,11 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         // one workgroup runs every round of both loops
         k_match_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr, lflag + 2);
         aggregate();
-        k_colour_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, lseed, F.colour_c, cnew,
-                                                 lflag + 1, lflag + 2);
+        const size_t cl_bytes = colour_local_lds(fn, F.m);
+        const int cl_lds = cl_bytes <= kColourLocalLds ? (int)cl_bytes : 0;
+        if (cl_lds > 64 * 1024) enable_colour_local_lds();
+        k_colour_local<<<1, kLocalBlock, cl_lds, s>>>(fn, F.m, F.rp_c, F.col_c, lseed, F.colour_c,
+                                                      cnew, lflag + 1, lflag + 2, cl_lds);
         FV_HIP(hipGetLastError());
       } else {
         match_rounds(8);
