@@ -339,6 +339,40 @@ __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, con
   if (threadIdx.x == 0) atomicMax(dmax, (unsigned long long)__double_as_longlong(d));
 }
 
+// Neighbours loaded per batch by the matching and colouring kernels: every
+// column index and weight of a batch, then the state of those neighbours,
+// before any is used (a row of up to eight neighbours costs two dependent
+// loads instead of two per neighbour).
+constexpr int kNbU = 8;
+
+// v's best free neighbour in the strict edge order (-1: none).  Positions
+// past the row end repeat its last entry: an edge is never strictly before
+// itself, so a repeat changes nothing.
+__device__ inline int pick_best(int v, int a, int b, const int* col, const double* w,
+                                const int* mate) {
+  int best = -1;
+  double bw = 0.0;
+  for (int pb = a; pb < b; pb += kNbU) {
+    int u[kNbU], mu[kNbU];
+    double wu[kNbU];
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) u[k] = col[min(pb + k, b - 1)];
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) wu[k] = w[min(pb + k, b - 1)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) mu[k] = mate[u[k]];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k)
+      if (mu[k] == -1 && (best < 0 || edge_before(wu[k], v, u[k], bw, v, best))) {
+        best = u[k];
+        bw = wu[k];
+      }
+  }
+  return best;
+}
+
 // ---------------------------------------------------------------------------
 // Heavy-edge matching by locally dominant rounds: every free vertex points at
 // its best free neighbour in the strict edge order; mutual pointers match.
@@ -353,18 +387,7 @@ __global__ void k_match_pick(int n, const int* rp, const int* col, const double*
   if (prev && *prev == 0) return;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     if (mate[v] != -1) continue;
-    int best = -1;
-    double bw = 0.0;
-    for (int p = rp[v]; p < rp[v + 1]; ++p) {
-      int u = col[p];
-      if (mate[u] != -1) continue;
-      double wu = w[p];
-      if (best < 0 || edge_before(wu, v, u, bw, v, best)) {
-        best = u;
-        bw = wu;
-      }
-    }
-    ptr[v] = best;
+    ptr[v] = pick_best(v, rp[v], rp[v + 1], col, w, mate);
   }
 }
 
@@ -399,18 +422,7 @@ __global__ __launch_bounds__(kLocalBlock) void k_match_local(int n, const int* r
   for (int round = 0;; ++round) {
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
       if (mate[v] != -1) continue;
-      int best = -1;
-      double bw = 0.0;
-      for (int p = rp[v]; p < rp[v + 1]; ++p) {
-        const int u = col[p];
-        if (mate[u] != -1) continue;
-        const double wu = w[p];
-        if (best < 0 || edge_before(wu, v, u, bw, v, best)) {
-          best = u;
-          bw = wu;
-        }
-      }
-      ptr[v] = best;
+      ptr[v] = pick_best(v, rp[v], rp[v + 1], col, w, mate);
     }
     if (threadIdx.x == 0) pending = 0;
     __syncthreads();
@@ -444,13 +456,9 @@ __device__ inline int first_fit(int a, int b, IP col, CP c) {
   }
 }
 
-// Neighbours loaded per batch by the colouring kernels: all column indices of
-// a batch, then all their colours, before any is used (a row of up to eight
-// neighbours costs two dependent loads instead of two per neighbour).
-// Positions past the row end repeat its last neighbour, which changes
-// neither a wait test nor a set of used colours.
-constexpr int kNbU = 8;
-
+// A batch of kNbU neighbours for the colouring kernels: all column indices,
+// then all their colours.  Positions past the row end repeat its last
+// neighbour, which changes neither a wait test nor a set of used colours.
 template <class IP, class CP>
 __device__ inline void load_nb(int pb, int b, IP col, CP c, int (&u)[kNbU], int (&cu)[kNbU]) {
 #pragma unroll
