@@ -328,15 +328,22 @@ __global__ void k_extract(int n, const int* __restrict__ rp, const int* __restri
 // ---------------------------------------------------------------------------
 // Shift sigma = 2 max_i d_i, d_i summed in row order.
 // ---------------------------------------------------------------------------
+// Rows are strided over at most kDegreeGrid blocks: one atomicMax per block,
+// and atomics on one address serialise (one block per 256 rows of a
+// 1M-vertex level took ~50 us, nearly all of it in the atomics).
+constexpr int kDegreeGrid = 512;
+
 __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, const double* w,
                                                      unsigned long long* dmax) {
   __shared__ double lds[kBlock / 64];
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double d = 0.0;
-  if (i < n)
+  double m = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double d = 0.0;
     for (int p = rp[i]; p < rp[i + 1]; ++p) d += w[p];
-  d = block_max(d, lds);
-  if (threadIdx.x == 0) atomicMax(dmax, (unsigned long long)__double_as_longlong(d));
+    m = fmax(m, d);
+  }
+  m = block_max(m, lds);
+  if (threadIdx.x == 0) atomicMax(dmax, (unsigned long long)__double_as_longlong(m));
 }
 
 // Neighbours loaded per batch by the matching and colouring kernels: every
@@ -1120,7 +1127,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     int l = 0;
     for (;;) {
       Level& F = h->lv[l];
-      k_degree_max<<<nblk(F.n), kBlock, 0, s>>>(F.n, F.rp_c, F.w_c, dmax + l);
+      k_degree_max<<<std::min(nblk(F.n), kDegreeGrid), kBlock, 0, s>>>(F.n, F.rp_c, F.w_c, dmax + l);
       FV_HIP(hipGetLastError());
       if (F.n <= n_coarse || l + 1 >= max_levels) break;
       const int fn = F.n;
