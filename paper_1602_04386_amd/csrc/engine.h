@@ -6,6 +6,8 @@
 // parameters, so the compiler emits LDS instructions (ds_read/ds_write) when
 // the data sits in LDS rather than generic flat accesses:
 //   * vector and CSR in LDS (small levels: everything stays on chip),
+//   * vector, column indices and row pointers in LDS, weights from global
+//     memory (L2-resident),
 //   * vector in LDS, CSR read from global memory (L2-resident),
 //   * everything in global memory.
 // Between levels the vector passes through one of two global buffers, which
@@ -259,6 +261,8 @@ template <class VT>
 using XView = LView<lds_ptr<VT>, const int*, const VT*>;
 template <class VT>
 using SView = LView<lds_ptr<VT>, lds_ptr<const int>, lds_ptr<const VT>>;
+template <class VT>
+using IView = LView<lds_ptr<VT>, lds_ptr<const int>, const VT*>;
 
 // The colour ranges of the level in LDS (when there are at most kEngineMaxCol
 // colours): every colour step reads its bounds, and a global load there would
@@ -300,6 +304,22 @@ __device__ __forceinline__ bool stage_csr(const LevelDesc& D, EngineCtx& E, size
   if (r_off + (size_t)(D.n + 1) * 4 > (size_t)E.bytes) return false;
   unsigned char* base = static_cast<unsigned char*>(E.xl);
   wg_copy(reinterpret_cast<VT*>(base + w_off), WSel<VT>::w(D), (int)D.m);
+  wg_copy(reinterpret_cast<int*>(base + c_off), D.col, (int)D.m);
+  wg_copy(reinterpret_cast<int*>(base + r_off), D.rp, D.n + 1);
+  return true;
+}
+
+// When the whole CSR does not fit: the vector, the column indices and the row
+// pointers (in that order) without the weights.  A row's weight loads then
+// come from L2 alongside its index loads from LDS instead of after a row
+// pointer load from L2.  Returns true when staged.
+template <class VT>
+__device__ __forceinline__ bool stage_index(const LevelDesc& D, EngineCtx& E, size_t& c_off,
+                                            size_t& r_off) {
+  c_off = ((size_t)D.n * sizeof(VT) + 15) & ~(size_t)15;
+  r_off = c_off + (((size_t)D.m * 4 + 15) & ~(size_t)15);
+  if (r_off + (size_t)(D.n + 1) * 4 > (size_t)E.bytes) return false;
+  unsigned char* base = static_cast<unsigned char*>(E.xl);
   wg_copy(reinterpret_cast<int*>(base + c_off), D.col, (int)D.m);
   wg_copy(reinterpret_cast<int*>(base + r_off), D.rp, D.n + 1);
   return true;
@@ -397,6 +417,10 @@ __device__ void engine_run(const GraphTask& T, EngineCtx& E) {
         if (src64) run_level<VT>(L, xl, xa64, G(gfree), s, T, fg, fp, g, p, E);
         else run_level<VT>(L, xl, G(gsrc), G(gfree), s, T, fg, fp, g, p, E);
         if (keep) final_mode = 2;
+      } else if (!keep && !src64 && stage_index<VT>(D, E, co, ro)) {
+        IView<VT> L = make_view<IView<VT>>(D, stage_cptr(D, E), (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + ro)),
+            (lds_ptr<const int>)(reinterpret_cast<const int*>(lbase + co)), WSel<VT>::w(D));
+        run_level<VT>(L, xl, G(gsrc), G(gfree), s, T, fg, fp, g, p, E);
       } else {
         XView<VT> L = make_view<XView<VT>>(D, stage_cptr(D, E), (const int*)D.rp, (const int*)D.col,
                                            WSel<VT>::w(D));
