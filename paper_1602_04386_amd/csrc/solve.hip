@@ -92,7 +92,9 @@ __device__ inline void row_gs(int i, const LevelDesc& L, VT* __restrict__ x, int
 
 // row_gs with the row's pointers given and its neighbours fetched kRowB at a
 // time (every index and weight load of a batch, then every gather): the same
-// terms added in the same order, for the rows a single block sweeps.
+// terms added in the same order, for the rows a single block sweeps.  The
+// first batch stays in registers for the edge-energy pass (most rows have at
+// most kRowB entries, so that pass issues no loads).
 constexpr int kRowB = 8;
 
 template <class VT>
@@ -104,9 +106,9 @@ __device__ inline void row_gs_batched(int i, int p0, int p1, const LevelDesc& L,
   const int* __restrict__ col = L.col;
   const double xo = ((double)x[i] - mu) * inv_s;
   double num = 0.0, den = 0.0;
-  for (int pb = p0; pb < p1; pb += kRowB) {
-    int jj[kRowB];
-    double ww[kRowB], xx[kRowB];
+  int j0[kRowB];
+  double w0[kRowB], x0[kRowB];
+  auto batch = [&](int pb, int (&jj)[kRowB], double (&ww)[kRowB], double (&xx)[kRowB]) {
 #pragma unroll
     for (int u = 0; u < kRowB; ++u) {
       const int q = min(pb + u, p1 - 1);
@@ -115,11 +117,23 @@ __device__ inline void row_gs_batched(int i, int p0, int p1, const LevelDesc& L,
     }
 #pragma unroll
     for (int u = 0; u < kRowB; ++u) xx[u] = (double)x[jj[u]];
+  };
+  for (int pb = p0; pb < p1; pb += kRowB) {
+    int jj[kRowB];
+    double ww[kRowB], xx[kRowB];
+    batch(pb, jj, ww, xx);
 #pragma unroll
     for (int u = 0; u < kRowB; ++u)
       if (pb + u < p1) {
         num += ww[u] * (jj[u] < lower_end ? xx[u] : (xx[u] - mu) * inv_s);
         den += ww[u];
+      }
+    if (pb == p0)
+#pragma unroll
+      for (int u = 0; u < kRowB; ++u) {
+        j0[u] = jj[u];
+        w0[u] = ww[u];
+        x0[u] = xx[u];
       }
   }
   double u = xo;
@@ -131,17 +145,17 @@ __device__ inline void row_gs_batched(int i, int p0, int p1, const LevelDesc& L,
   x[i] = us;
   const double ud = (double)us;
   double e = 0.0;
-  for (int pb = p0; pb < p1; pb += kRowB) {
+  if (p1 > p0)
+#pragma unroll
+    for (int u = 0; u < kRowB; ++u)
+      if (p0 + u < p1 && j0[u] < lower_end) {
+        const double d = ud - x0[u];
+        e += w0[u] * d * d;
+      }
+  for (int pb = p0 + kRowB; pb < p1; pb += kRowB) {
     int jj[kRowB];
     double ww[kRowB], xx[kRowB];
-#pragma unroll
-    for (int u = 0; u < kRowB; ++u) {
-      const int q = min(pb + u, p1 - 1);
-      jj[u] = col[q];
-      ww[u] = (double)w[q];
-    }
-#pragma unroll
-    for (int u = 0; u < kRowB; ++u) xx[u] = (double)x[jj[u]];
+    batch(pb, jj, ww, xx);
 #pragma unroll
     for (int u = 0; u < kRowB; ++u)
       if (pb + u < p1 && jj[u] < lower_end) {
