@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <initializer_list>
 
 #include "fv_device.h"
 #include "fv_internal.h"
@@ -49,6 +50,7 @@ __device__ inline void wave_flag(int* flag) {
 // that exits at once still costs only its launch.
 constexpr int kRoundGrid = 4096;
 static inline int round_grid(int n) { return std::min(nblk(n), kRoundGrid); }
+
 
 
 // ---------------------------------------------------------------------------
@@ -227,6 +229,41 @@ struct BigRow {
 __global__ void k_fill_int(int* a, long long n, int v) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
+}
+
+// Several int arrays filled by one launch (each fill of a level's scratch
+// arrays was a launch of its own).
+constexpr int kFillMax = 8;
+struct FillSet {
+  int* p[kFillMax];
+  long long n[kFillMax];
+  int v[kFillMax];
+  int k;
+};
+__global__ void k_fill_multi(FillSet f) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int a = 0; a < f.k; ++a)
+    if (i < f.n[a]) f.p[a][i] = f.v[a];
+}
+
+struct FillItem {
+  int* p;
+  long long n;
+  int v;
+};
+// Fills every listed array (p[0, n) = v) in one launch.
+static void fill_multi(hipStream_t s, std::initializer_list<FillItem> items) {
+  FillSet f{};
+  long long nmax = 0;
+  for (const FillItem& it : items) {
+    if (f.k == kFillMax) throw Error(FV_E_DEVICE, "too many arrays for one fill");
+    f.p[f.k] = it.p;
+    f.n[f.k] = it.n;
+    f.v[f.k] = it.v;
+    ++f.k;
+    nmax = std::max(nmax, it.n);
+  }
+  if (nmax > 0) k_fill_multi<<<nblk(nmax), kBlock, 0, s>>>(f);
 }
 __global__ void k_iota(int* a, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1136,11 +1173,14 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // aggregate count, in one read-back when the first batches suffice.
       const bool local = fn <= kLocalMaxN;
       int mr = 0, cr = 0;
-      if (!local) {
-        k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(mflag, kRoundCap, 0);
-        k_fill_int<<<nblk(kRoundCap), kBlock, 0, s>>>(cflag, kRoundCap, 0);
-        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(mate, fn, -1);
-      }
+      F.colour_c = halloc<int>(h, fn);
+      // The level's scratch in one launch: round flags, matching and colour
+      // state, and the Galerkin term counters (nc < fn terms rows).
+      if (!local)
+        fill_multi(s, {{mflag, kRoundCap, 0}, {cflag, kRoundCap, 0}, {mate, fn, -1},
+                       {F.colour_c, fn, -1}, {cnew, fn, -1}, {tcount, fn, 0}, {tfill, fn, 0}});
+      else
+        fill_multi(s, {{tcount, fn, 0}, {tfill, fn, 0}});
       auto match_rounds = [&](int b) {
         if (mr + b > kRoundCap) throw Error(FV_E_DEVICE, "matching did not terminate");
         for (int r = mr; r < mr + b; ++r) {
@@ -1153,9 +1193,8 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         FV_HIP(hipGetLastError());
       };
       auto aggregate = [&]() {
-        FV_HIP(hipMemsetAsync(lflag, 0, sizeof(int), s));
+        fill_multi(s, {{lflag, 1, 0}, {minmem, fn, INT_MAX}});
         k_agg_root<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, root, lflag);
-        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(minmem, fn, INT_MAX);
         k_agg_minmem<<<nblk(fn), kBlock, 0, s>>>(fn, root, minmem);
         FV_HIP(hipGetLastError());
         sc.enqueue(LeaderFlag{root, minmem}, fn, id, true);
@@ -1182,7 +1221,6 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         FV_HIP(hipMemcpyAsync(pin_i, gath, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
         FV_HIP(hipStreamSynchronize(s));
       };
-      F.colour_c = halloc<int>(h, fn);
       if (local) {
         // one workgroup runs every round of both loops
         k_match_local<<<1, kLocalBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, mate, ptr, lflag + 2);
@@ -1196,7 +1234,6 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       } else {
         match_rounds(8);
         aggregate();
-        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(F.colour_c, fn, -1);
         colour_rounds(16);
       }
       read_back();
@@ -1216,7 +1253,6 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // ranges are read back at the end of the build.
       F.ncol = pin_i[3] + 1;
       if (!local) {
-        k_fill_int<<<nblk(fn), kBlock, 0, s>>>(cnew, fn, -1);
         for (int c = F.ncol - 1; c >= 0; --c)
           k_recolour_class<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.colour_c, cnew,
                                                              c);
@@ -1235,8 +1271,6 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // Galerkin coarse graph
       Level& Cl = h->lv[l + 1];
       Cl.n = nc;
-      FV_HIP(hipMemsetAsync(tcount, 0, sizeof(int) * (nc + 1), s));
-      FV_HIP(hipMemsetAsync(tfill, 0, sizeof(int) * nc, s));
       k_gal_count<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.q_c, tcount);
       FV_HIP(hipGetLastError());
       sc.enqueue(FromArray{tcount}, nc, tstart, true);
