@@ -844,15 +844,15 @@ __device__ inline bool term_less(int J1, int a1, int b1, int J2, int a2, int b2)
   return b1 < b2;
 }
 
-// Rows with at most 64 terms: one wavefront per row, rank sort in registers.
-__global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, const int* tstart,
-                                                         const int* tJ, const int* ta,
-                                                         const int* tb, const double* tw,
-                                                         int* cJ, double* cw, int* uniq) {
-  __shared__ int sJ[kBlock / 64][64];
-  __shared__ double sw[kBlock / 64][64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int I = blockIdx.x * (kBlock / 64) + wave;
+// Coarse row I with at most 64 terms sorted by one wavefront: each lane ranks
+// its term against the row's others (broadcast with readlane), the terms go
+// to LDS in rank order, and each run of equal J is summed in that order.
+// Every thread of the block calls (one barrier); rows with more terms, and
+// I >= nc, leave their wave idle.
+__device__ inline void gal_row64(int I, int nc, const int* tstart, const int* tJ, const int* ta,
+                                 const int* tb, const double* tw, int* sJ, double* sw, int* cJ,
+                                 double* cw, int* uniq) {
+  const int lane = threadIdx.x & 63;
   int s = 0, T = 0;
   if (I < nc) {
     s = tstart[I];
@@ -877,22 +877,102 @@ __global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, const int* ts
     if (term_less(J2, a2, b2, myJ, mya, myb)) ++rank;
   }
   if (active && lane < T) {
-    sJ[wave][rank] = myJ;
-    sw[wave][rank] = myw;
+    sJ[rank] = myJ;
+    sw[rank] = myw;
   }
   __syncthreads();
   bool head = false;
-  if (active && lane < T) head = lane == 0 || sJ[wave][lane] != sJ[wave][lane - 1];
+  if (active && lane < T) head = lane == 0 || sJ[lane] != sJ[lane - 1];
   unsigned long long mask = __ballot(head);
   if (head) {
     int pos = __popcll(mask & ((1ULL << lane) - 1ULL));
-    int J = sJ[wave][lane];
+    int J = sJ[lane];
     double sum = 0.0;
-    for (int p = lane; p < T && sJ[wave][p] == J; ++p) sum += sw[wave][p];
+    for (int p = lane; p < T && sJ[p] == J; ++p) sum += sw[p];
     cJ[s + pos] = J;
     cw[s + pos] = sum;
   }
   if (active && lane == 0) uniq[I] = __popcll(mask);
+  __syncthreads();  // the next call reuses sJ / sw
+}
+
+// Lane value of the lane k places further round its row of 16 (DPP row_ror).
+template <int K>
+__device__ inline int row_ror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + K, 0xf, 0xf, false);
+}
+
+// Rows with at most 64 terms.  With packed set, a block of four waves takes
+// 16 consecutive rows, four per wave: when each of the 16 has at most 16
+// terms (the common case on large levels: a pair of fine rows of a 5-point
+// grid gives six), a wave sorts its four rows at once in rows of 16 lanes,
+// ranking each term against the 15 others of its row by DPP rotations;
+// otherwise it sorts them one after another across all 64 lanes.  Without
+// packed (levels with few rows, where latency decides), one row per wave.
+// Same ranks, same sums either way.
+constexpr int kGalPackedRows = 32768;  // coarse rows from which packed pays
+
+__global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, int packed, const int* tstart,
+                                                         const int* tJ, const int* ta,
+                                                         const int* tb, const double* tw,
+                                                         int* cJ, double* cw, int* uniq) {
+  __shared__ int sJ[kBlock / 64][64];
+  __shared__ double sw[kBlock / 64][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (!packed) {
+    gal_row64(blockIdx.x * (kBlock / 64) + wave, nc, tstart, tJ, ta, tb, tw, sJ[wave], sw[wave],
+              cJ, cw, uniq);
+    return;
+  }
+  const int I0 = (blockIdx.x * (kBlock / 64) + wave) * 4;  // the wave's first row
+  const int g = lane >> 4, l16 = lane & 15;
+  const int I = I0 + g;
+  int s = 0, T = 0;
+  if (I < nc) {
+    s = tstart[I];
+    T = tstart[I + 1] - s;
+  }
+  if (!__syncthreads_and(T <= 16)) {
+    for (int r = 0; r < 4; ++r)
+      gal_row64(I0 + r, nc, tstart, tJ, ta, tb, tw, sJ[wave], sw[wave], cJ, cw, uniq);
+    return;
+  }
+  const bool mine = I < nc && l16 < T;
+  int myJ = INT_MAX, mya = 0, myb = 0;
+  double myw = 0.0;
+  if (mine) {
+    myJ = tJ[s + l16];
+    mya = ta[s + l16];
+    myb = tb[s + l16];
+    myw = tw[s + l16];
+  }
+  int rank = 0;
+  // Padding lanes hold (INT_MAX, 0, 0), after every real term of the row.
+#define FV_RANK_STEP(K) \
+  rank += term_less(row_ror<K>(myJ), row_ror<K>(mya), row_ror<K>(myb), myJ, mya, myb) ? 1 : 0;
+  FV_RANK_STEP(1) FV_RANK_STEP(2) FV_RANK_STEP(3) FV_RANK_STEP(4) FV_RANK_STEP(5)
+  FV_RANK_STEP(6) FV_RANK_STEP(7) FV_RANK_STEP(8) FV_RANK_STEP(9) FV_RANK_STEP(10)
+  FV_RANK_STEP(11) FV_RANK_STEP(12) FV_RANK_STEP(13) FV_RANK_STEP(14) FV_RANK_STEP(15)
+#undef FV_RANK_STEP
+  int* rJ = sJ[wave] + g * 16;
+  double* rw = sw[wave] + g * 16;
+  if (mine) {
+    rJ[rank] = myJ;
+    rw[rank] = myw;
+  }
+  __syncthreads();
+  bool head = false;
+  if (mine) head = l16 == 0 || rJ[l16] != rJ[l16 - 1];
+  const unsigned long long rowmask = (__ballot(head) >> (g * 16)) & 0xFFFFULL;
+  if (head) {
+    const int pos = __popcll(rowmask & ((1ULL << l16) - 1ULL));
+    const int J = rJ[l16];
+    double sum = 0.0;
+    for (int p = l16; p < T && rJ[p] == J; ++p) sum += rw[p];
+    cJ[s + pos] = J;
+    cw[s + pos] = sum;
+  }
+  if (I < nc && l16 == 0) uniq[I] = __popcll(rowmask);
 }
 
 // Rows with more than 64 terms: one workgroup per listed row, rank sort into
@@ -1276,8 +1356,11 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       sc.enqueue(FromArray{tcount}, nc, tstart, true);
       k_gal_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, F.q_c, tstart, tfill, tJ,
                                              ta, tb, tw);
-      k_gal_rows_small<<<nblk(nc, kBlock / 64), kBlock, 0, s>>>(nc, tstart, tJ, ta, tb, tw, cJ, cw,
-                                                                 uniq);
+      {
+        const int packed = nc >= kGalPackedRows ? 1 : 0;
+        k_gal_rows_small<<<nblk(nc, (packed ? 4 : 1) * (kBlock / 64)), kBlock, 0, s>>>(
+            nc, packed, tstart, tJ, ta, tb, tw, cJ, cw, uniq);
+      }
       FV_HIP(hipGetLastError());
       sc.enqueue(BigRow{tstart}, nc, lpos, true);
       k_list_fill<<<nblk(nc), kBlock, 0, s>>>(nc, tstart, lpos, list);
