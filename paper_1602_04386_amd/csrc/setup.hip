@@ -806,15 +806,42 @@ __global__ void k_qs(int n, const int* perm, const int* q, const int* perm_next,
 // max(v,j)) and each run of equal J is summed sequentially in that order, so
 // W_c(I,J) and W_c(J,I) add the same fine weights in the same order.
 // ---------------------------------------------------------------------------
+// A batch of a row's neighbours for the Galerkin kernels: column indices and
+// weights, then the neighbours' aggregates (positions past the row end repeat
+// its last entry; callers skip them).
+__device__ inline void gal_batch(int pb, int b, const int* __restrict__ col,
+                                 const double* __restrict__ w, const int* __restrict__ q,
+                                 int (&jj)[kNbU], int (&JJ)[kNbU], double (&ww)[kNbU]) {
+#pragma unroll
+  for (int k = 0; k < kNbU; ++k) jj[k] = col[min(pb + k, b - 1)];
+  if (w)
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) ww[k] = w[min(pb + k, b - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < kNbU; ++k) JJ[k] = q[jj[k]];
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 __global__ void k_gal_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
                             const int* __restrict__ q, int* __restrict__ tcount) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  int I = q[v], c = 0;
-  for (int p = rp[v]; p < rp[v + 1]; ++p) c += q[col[p]] != I;
+  const int I = q[v], a = rp[v], b = rp[v + 1];
+  int c = 0;
+  for (int pb = a; pb < b; pb += kNbU) {
+    int jj[kNbU], JJ[kNbU];
+    double ww[kNbU];
+    gal_batch(pb, b, col, nullptr, q, jj, JJ, ww);
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) c += (pb + k < b && JJ[k] != I) ? 1 : 0;
+  }
   if (c) atomicAdd(&tcount[I], c);
 }
 
+// The terms of fine row v, in CSR order, at v's place in its coarse row's
+// list.  The first batch of neighbours stays in registers between the count
+// and the fill (a grid row fits in one batch).
 __global__ void k_gal_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
                            const double* __restrict__ w, const int* __restrict__ q,
                            const int* __restrict__ tstart, int* __restrict__ tfill,
@@ -822,19 +849,43 @@ __global__ void k_gal_fill(int n, const int* __restrict__ rp, const int* __restr
                            double* __restrict__ tw) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  int I = q[v], c = 0;
-  for (int p = rp[v]; p < rp[v + 1]; ++p) c += q[col[p]] != I;
+  const int I = q[v], a = rp[v], b = rp[v + 1];
+  int j0[kNbU], J0[kNbU];
+  double w0[kNbU];
+  int c = 0;
+  for (int pb = a; pb < b; pb += kNbU) {
+    int jj[kNbU], JJ[kNbU];
+    double ww[kNbU];
+    gal_batch(pb, b, col, w, q, jj, JJ, ww);
+#pragma unroll
+    for (int k = 0; k < kNbU; ++k) c += (pb + k < b && JJ[k] != I) ? 1 : 0;
+    if (pb == a)
+#pragma unroll
+      for (int k = 0; k < kNbU; ++k) {
+        j0[k] = jj[k];
+        J0[k] = JJ[k];
+        w0[k] = ww[k];
+      }
+  }
   if (!c) return;
   int k = tstart[I] + atomicAdd(&tfill[I], c);
-  for (int p = rp[v]; p < rp[v + 1]; ++p) {
-    int j = col[p];
-    int J = q[j];
-    if (J == I) continue;
+  auto emit = [&](int j, int J, double wv) {
     tJ[k] = J;
     ta[k] = v < j ? v : j;
     tb[k] = v < j ? j : v;
-    tw[k] = w[p];
+    tw[k] = wv;
     ++k;
+  };
+#pragma unroll
+  for (int u = 0; u < kNbU; ++u)
+    if (a + u < b && J0[u] != I) emit(j0[u], J0[u], w0[u]);
+  for (int pb = a + kNbU; pb < b; pb += kNbU) {
+    int jj[kNbU], JJ[kNbU];
+    double ww[kNbU];
+    gal_batch(pb, b, col, w, q, jj, JJ, ww);
+#pragma unroll
+    for (int u = 0; u < kNbU; ++u)
+      if (pb + u < b && JJ[u] != I) emit(jj[u], JJ[u], ww[u]);
   }
 }
 
