@@ -30,6 +30,10 @@ CASES = {
     # a 3,200-entry row on a multi-workgroup level (longer than a tile's
     # staging capacity: the row takes the direct path) beside short rows
     "gridhub128x100": (lambda: gen.grid_with_hub(128, 100, 4, seed=6), 25),
+    # level 1 (4,173 rows) fits the engine's LDS with its column indices and
+    # row pointers but not its FP32 weights: the engine reads only those from
+    # global memory
+    "grid96x96u": (lambda: gen.grid(96, 96, "uniform", seed=9), 25),
 }
 _graphs = {}
 
