@@ -50,7 +50,9 @@ typedef enum {
                                 x, lambda and stats are still filled */
   FV_E_DEVICE = -8,          /* HIP runtime error */
   FV_E_UNKNOWN_TICKET = -9,  /* fv_poll: ticket never issued or already collected */
-  FV_E_BUSY = -10            /* server queue full */
+  FV_E_BUSY = -10,           /* server queue full */
+  FV_E_SCRATCH = -11         /* fv_fiedler_solve_noalloc: the graph needs more than the
+                                fixed scratch of FV_NOALLOC_SCRATCH_BYTES */
 } fv_status;
 
 typedef enum {
@@ -202,6 +204,33 @@ fv_status fv_fiedler_solve_batch(fv_context* ctx, int32_t count, const fv_hierar
                                  const fv_solve_opts* opts, double* const* x_out,
                                  int32_t x_on_device, double* lambda_out, fv_solve_stats* stats,
                                  fv_status* item_status);
+
+/* Bytes of the fixed device scratch behind fv_fiedler_solve_noalloc (per GPU,
+ * held from the first use of the library on that GPU until the process ends).
+ * It holds the solve's workspace: two vectors and one FP64 scratch vector of
+ * the finest level's size (8 bytes per vertex each), the per-block partial
+ * sums and the device state, so graphs of up to about 1.3 million vertices
+ * fit. */
+#define FV_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same solve as
+ * fv_fiedler_solve -- same kernels, same arithmetic, bitwise the same results
+ * -- with no device or host allocation.  Its workspace is the fixed scratch
+ * above instead of context memory, and the context's host buffers and events
+ * (made by fv_context_create) are reused; nothing is counted against the
+ * context's HBM budget.  The hierarchy, opts and outputs are as for
+ * fv_fiedler_solve (x_out on the host or, with x_on_device, on the device).
+ * Every call on one GPU shares that GPU's scratch and the context's host
+ * buffers: calls that overlap on one GPU (other threads, other contexts, other
+ * streams) race and must be serialised by the caller.  The scratch keeps the
+ * last call's contents; the solve clears what it needs.  Errors: as
+ * fv_fiedler_solve, plus FV_E_SCRATCH when the hierarchy's workspace exceeds
+ * FV_NOALLOC_SCRATCH_BYTES (nothing runs). */
+fv_status fv_fiedler_solve_noalloc(fv_context* ctx, const fv_hierarchy* h,
+                                   const fv_solve_opts* opts, double* x_out,
+                                   int32_t x_on_device, double* lambda_out,
+                                   fv_solve_stats* stats);
 
 /* ---- Serving: continuous batching of Fiedler requests over one GPU ---- */
 

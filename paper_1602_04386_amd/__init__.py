@@ -23,9 +23,11 @@ FV_SCHEDULE_CAP = 1024
 
 STATUS = {0: "OK", 1: "PENDING", -1: "E_INVALID", -2: "E_NOT_SYMMETRIC", -3: "E_NOT_LAPLACIAN",
           -4: "E_ISOLATED", -5: "E_NOMEM", -6: "E_BUDGET", -7: "E_NOT_CONVERGED",
-          -8: "E_DEVICE", -9: "E_UNKNOWN_TICKET", -10: "E_BUSY"}
+          -8: "E_DEVICE", -9: "E_UNKNOWN_TICKET", -10: "E_BUSY", -11: "E_SCRATCH"}
 OK, PENDING, E_INVALID, E_NOT_SYMMETRIC, E_NOT_LAPLACIAN, E_ISOLATED = 0, 1, -1, -2, -3, -4
 E_NOMEM, E_BUDGET, E_NOT_CONVERGED, E_DEVICE, E_UNKNOWN_TICKET, E_BUSY = -5, -6, -7, -8, -9, -10
+E_SCRATCH = -11
+NOALLOC_SCRATCH_BYTES = 32 << 20  # FV_NOALLOC_SCRATCH_BYTES
 PREC = {"fp64": 0, "fp32": 1, "fp32_mixed": 1}
 
 
@@ -79,7 +81,7 @@ class fv_result(C.Structure):
 EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
            "fv_context_destroy", "fv_build_hierarchy", "fv_hierarchy_info", "fv_hierarchy_bytes",
            "fv_hierarchy_export_level", "fv_free_hierarchy", "fv_fiedler_solve",
-           "fv_fiedler_solve_batch", "fv_server_create", "fv_submit", "fv_poll",
+           "fv_fiedler_solve_noalloc", "fv_fiedler_solve_batch", "fv_server_create", "fv_submit", "fv_poll",
            "fv_server_destroy", "fv_status_str"]
 
 _lib = None
@@ -116,6 +118,8 @@ def lib() -> C.CDLL:
         L.fv_fiedler_solve.argtypes = [vp, vp, C.POINTER(fv_solve_opts), vp, C.c_int32,
                                        C.POINTER(C.c_double), C.POINTER(fv_solve_stats)]
         L.fv_fiedler_solve.restype = C.c_int
+        L.fv_fiedler_solve_noalloc.argtypes = L.fv_fiedler_solve.argtypes
+        L.fv_fiedler_solve_noalloc.restype = C.c_int
         L.fv_fiedler_solve_batch.argtypes = [vp, C.c_int32, vp, C.POINTER(fv_solve_opts), vp,
                                              C.c_int32, vp, vp, vp]
         L.fv_fiedler_solve_batch.restype = C.c_int
@@ -341,6 +345,18 @@ def _stats_to_result(st, x, lam, S: fv_solve_stats) -> SolveResult:
 def fiedler_solve(ctx: Context, h: Hierarchy, x_out=None, **kw) -> SolveResult:
     """fv_fiedler_solve.  x_out: optional device tensor of n float64; otherwise
     a host numpy array is returned."""
+    return _solve(lib().fv_fiedler_solve, "fv_fiedler_solve", ctx, h, x_out, **kw)
+
+
+def fiedler_solve_noalloc(ctx: Context, h: Hierarchy, x_out=None, **kw) -> SolveResult:
+    """fv_fiedler_solve_noalloc: the same solve on the library's fixed device
+    scratch, allocating nothing.  Raises FiedlerError(E_SCRATCH) when the
+    hierarchy needs more than NOALLOC_SCRATCH_BYTES."""
+    return _solve(lib().fv_fiedler_solve_noalloc, "fv_fiedler_solve_noalloc", ctx, h, x_out,
+                  **kw)
+
+
+def _solve(fn, name, ctx, h, x_out, **kw) -> SolveResult:
     o, keep = solve_opts(**kw)
     n0 = h.n[0]
     if x_out is None:
@@ -351,11 +367,10 @@ def fiedler_solve(ctx: Context, h: Hierarchy, x_out=None, **kw) -> SolveResult:
         xp, on_dev = x_out.data_ptr(), 1
     lam = C.c_double()
     S = fv_solve_stats()
-    st = lib().fv_fiedler_solve(ctx.handle, h._h, C.byref(o), xp, on_dev, C.byref(lam),
-                                C.byref(S))
+    st = fn(ctx.handle, h._h, C.byref(o), xp, on_dev, C.byref(lam), C.byref(S))
     del keep
     if st not in (OK, E_NOT_CONVERGED):
-        raise FiedlerError(st, "fv_fiedler_solve")
+        raise FiedlerError(st, name)
     return _stats_to_result(st, x, lam.value, S)
 
 

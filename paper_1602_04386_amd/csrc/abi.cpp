@@ -162,6 +162,7 @@ const char* fv_status_str(fv_status st) {
     case FV_E_DEVICE: return "device error";
     case FV_E_UNKNOWN_TICKET: return "unknown ticket";
     case FV_E_BUSY: return "server queue full";
+    case FV_E_SCRATCH: return "graph exceeds the fixed scratch of the allocation-free solve";
   }
   return "unknown status";
 }
@@ -180,6 +181,17 @@ fv_status fv_context_create(int device, size_t hbm_budget_bytes, fv_context** ou
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
       delete c;
       return FV_E_DEVICE;
+    }
+    try {
+      // Host buffers and events of the context's solves, and the device
+      // address of the allocation-free solve's scratch on this device.
+      fv::scratch_host_init(c->scratch);
+      (void)fv::noalloc_scratch_init(device);
+    } catch (...) {
+      fv::release_scratch(c, c->scratch);
+      (void)hipStreamDestroy(c->stream);
+      delete c;
+      throw;
     }
     *out = c;
     return FV_OK;
@@ -283,6 +295,22 @@ fv_status fv_fiedler_solve(fv_context* ctx, const fv_hierarchy* h, const fv_solv
   FV_GUARD({
     FV_HIP(hipSetDevice(ctx->device));
     return fv::solve_one(ctx, h, &o, x_out, x_on_device, lambda_out, stats);
+  })
+}
+
+fv_status fv_fiedler_solve_noalloc(fv_context* ctx, const fv_hierarchy* h,
+                                   const fv_solve_opts* opts, double* x_out,
+                                   int32_t x_on_device, double* lambda_out,
+                                   fv_solve_stats* stats) {
+  if (!ctx || !h || !x_out || h->ctx != ctx) return FV_E_INVALID;
+  fv_solve_opts o;
+  fv_solve_opts_default(&o);
+  if (opts) o = *opts;
+  fv_status st = check_solve_opts(&o);
+  if (st != FV_OK) return st;
+  FV_GUARD({
+    FV_HIP(hipSetDevice(ctx->device));
+    return fv::solve_noalloc(ctx, h, &o, x_out, x_on_device, lambda_out, stats);
   })
 }
 

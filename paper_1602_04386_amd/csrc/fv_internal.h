@@ -154,6 +154,10 @@ struct SolveScratch {
   int* pinned = nullptr;
   int* hflags = nullptr;
   int* hflags_dev = nullptr;
+  // Events of a solve: start and end of the timed region, the two chunk
+  // events of the early stop, and the event after a residual pass.
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_chunk[2] = {nullptr, nullptr},
+             ev_res = nullptr;
 };
 }  // namespace fv
 
@@ -210,6 +214,15 @@ fv_status solve_one_with(fv_context* ctx, SolveScratch& sc, const fv_hierarchy* 
                          const fv_solve_opts* o, double* x_out, int x_on_device,
                          double* lambda_out, fv_solve_stats* stats, hipStream_t s);
 void release_scratch(fv_context* ctx, SolveScratch& sc);
+// Pinned and mapped host buffers and events of a workspace (created once).
+void scratch_host_init(SolveScratch& sc);
+// Device address of the fixed scratch of the allocation-free solve on the
+// current device (looked up once per device; fv_context_create calls it).
+void* noalloc_scratch_init(int device);
+// fv_fiedler_solve without any allocation: the workspace is the fixed scratch.
+fv_status solve_noalloc(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
+                        double* x_out, int x_on_device, double* lambda_out,
+                        fv_solve_stats* stats);
 fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* h,
                       const fv_solve_opts* o, double* const* x_out, int x_on_device,
                       double* lambda_out, fv_solve_stats* stats, fv_status* item_status,

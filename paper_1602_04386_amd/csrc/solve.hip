@@ -721,30 +721,38 @@ void release_scratch(fv_context* ctx, SolveScratch& sc) {
   if (sc.hflags) (void)hipHostFree(sc.hflags);
   sc.hflags = nullptr;
   sc.hflags_dev = nullptr;
+  for (hipEvent_t* e : {&sc.ev_t0, &sc.ev_t1, &sc.ev_chunk[0], &sc.ev_chunk[1], &sc.ev_res}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
 }
 
-template <class VT>
-static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarchy* h,
-                             const fv_solve_opts* o, double* x_out, int x_on_device,
-                             double* lambda_out, fv_solve_stats* stats, hipStream_t s) {
-  const int J = h->levels - 1;
-  const size_t nmax = hierarchy_nmax(h);
-  int maxcol = 1;
-  for (int l = 0; l < h->levels; ++l) maxcol = std::max(maxcol, h->lv[l].ncol);
-  const size_t need = solve_workspace_bytes(nmax, maxcol);
-  if (sc.ws_bytes < need) {
-    (void)hipDeviceSynchronize();  // the old workspace may be in use on any stream
-    release_scratch_device(ctx, sc);
-    sc.ws = dev_alloc(ctx, need, nullptr);
-    sc.ws_bytes = need;
-  }
-  if (!sc.pinned) FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&sc.pinned), 256, hipHostMallocDefault));
+void scratch_host_init(SolveScratch& sc) {
+  if (!sc.pinned)
+    FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&sc.pinned), 256, hipHostMallocDefault));
   if (!sc.hflags) {
     FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&sc.hflags), 256,
                          hipHostMallocMapped | hipHostMallocCoherent));
     FV_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&sc.hflags_dev), sc.hflags, 0));
   }
-  Workspace W = carve(sc.ws, nmax, maxcol);
+  if (!sc.ev_t0) FV_HIP(hipEventCreate(&sc.ev_t0));
+  if (!sc.ev_t1) FV_HIP(hipEventCreate(&sc.ev_t1));
+  for (hipEvent_t* e : {&sc.ev_chunk[0], &sc.ev_chunk[1], &sc.ev_res})
+    if (!*e) FV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+}
+
+// The solve proper on the workspace ws (at least solve_workspace_bytes of the
+// hierarchy) with the host buffers and events of sc (scratch_host_init done).
+template <class VT>
+static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const fv_hierarchy* h,
+                             const fv_solve_opts* o, double* x_out, int x_on_device,
+                             double* lambda_out, fv_solve_stats* stats, hipStream_t s) {
+  (void)ctx;
+  const int J = h->levels - 1;
+  const size_t nmax = hierarchy_nmax(h);
+  int maxcol = 1;
+  for (int l = 0; l < h->levels; ++l) maxcol = std::max(maxcol, h->lv[l].ncol);
+  Workspace W = carve(ws, nmax, maxcol);
   int* pinned = sc.pinned;
 
   // Split: levels whose vector fits the engine's LDS go to the one-workgroup
@@ -765,16 +773,7 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
   }
   // Output staging for a host x_out: lx, free once the residual is done.
   double* out_dev = x_on_device ? x_out : W.lx;
-  hipEvent_t e0, e1;
-  FV_HIP(hipEventCreate(&e0));
-  FV_HIP(hipEventCreate(&e1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-    }
-  } eg{e0, e1};
+  hipEvent_t e0 = sc.ev_t0, e1 = sc.ev_t1;
   FV_HIP(hipEventRecord(e0, s));
 
   GraphTask T;
@@ -821,17 +820,9 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
     hsync.hres = reinterpret_cast<volatile double*>(sc.hflags + 8);
     hsync.hdone_dev = sc.hflags_dev;
     hsync.hres_dev = reinterpret_cast<double*>(sc.hflags_dev + 8);
-    FV_HIP(hipEventCreateWithFlags(&hsync.ev[0], hipEventDisableTiming));
-    FV_HIP(hipEventCreateWithFlags(&hsync.ev[1], hipEventDisableTiming));
-    FV_HIP(hipEventCreateWithFlags(&hsync.ev_res, hipEventDisableTiming));
-    struct SyncGuard {
-      HostSync& h;
-      ~SyncGuard() {
-        (void)hipEventDestroy(h.ev[0]);
-        (void)hipEventDestroy(h.ev[1]);
-        (void)hipEventDestroy(h.ev_res);
-      }
-    } sg{hsync};
+    hsync.ev[0] = sc.ev_chunk[0];
+    hsync.ev[1] = sc.ev_chunk[1];
+    hsync.ev_res = sc.ev_res;
     int nrec = 0;  // phases recorded in W.rec; the spare slot takes any overflow
     auto rec_slot = [&]() { return W.rec + std::min(nrec++, FV_SCHEDULE_CAP); };
     auto no_wait = [] { return false; };
@@ -948,12 +939,71 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, const fv_hierarc
   return status;
 }
 
+static size_t workspace_need(const fv_hierarchy* h) {
+  int maxcol = 1;
+  for (int l = 0; l < h->levels; ++l) maxcol = std::max(maxcol, h->lv[l].ncol);
+  return solve_workspace_bytes(hierarchy_nmax(h), maxcol);
+}
+
 fv_status solve_one_with(fv_context* ctx, SolveScratch& sc, const fv_hierarchy* h,
                          const fv_solve_opts* o, double* x_out, int x_on_device,
                          double* lambda_out, fv_solve_stats* stats, hipStream_t s) {
+  const size_t need = workspace_need(h);
+  if (sc.ws_bytes < need) {
+    // The old workspace may still be read by work queued on s.
+    FV_HIP(hipStreamSynchronize(s));
+    release_scratch_device(ctx, sc);
+    sc.ws = dev_alloc(ctx, need, nullptr);
+    sc.ws_bytes = need;
+  }
+  scratch_host_init(sc);
   if (o->prec == FV_PREC_FP32_MIXED)
-    return solve_one_t<float>(ctx, sc, h, o, x_out, x_on_device, lambda_out, stats, s);
-  return solve_one_t<double>(ctx, sc, h, o, x_out, x_on_device, lambda_out, stats, s);
+    return solve_one_t<float>(ctx, sc, sc.ws, h, o, x_out, x_on_device, lambda_out, stats, s);
+  return solve_one_t<double>(ctx, sc, sc.ws, h, o, x_out, x_on_device, lambda_out, stats, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace is a fixed device array of this file.
+// Each device holds its own copy from the first use of the library on it
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: that name is a host-side stand-in, not a device address.
+// The address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FV_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;
+
+void* noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  FV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(FV_E_DEVICE, "no device address for the fixed scratch");
+  g_scratch_ptr[device] = p;
+  return p;
+}
+
+fv_status solve_noalloc(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
+                        double* x_out, int x_on_device, double* lambda_out,
+                        fv_solve_stats* stats) {
+  if (workspace_need(h) > (size_t)FV_NOALLOC_SCRATCH_BYTES) return FV_E_SCRATCH;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(ctx->device);
+    if (it != g_scratch_ptr.end()) ws = it->second;
+  }
+  SolveScratch& sc = ctx->scratch;
+  // Both were set up by fv_context_create; nothing is created here.
+  if (!ws || !sc.pinned || !sc.hflags || !sc.ev_t0 || !sc.ev_res)
+    throw Error(FV_E_DEVICE, "context set-up incomplete");
+  hipStream_t s = o->stream ? static_cast<hipStream_t>(o->stream) : ctx->stream;
+  if (o->prec == FV_PREC_FP32_MIXED)
+    return solve_one_t<float>(ctx, sc, ws, h, o, x_out, x_on_device, lambda_out, stats, s);
+  return solve_one_t<double>(ctx, sc, ws, h, o, x_out, x_on_device, lambda_out, stats, s);
 }
 
 fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
