@@ -10,6 +10,7 @@ from __future__ import annotations
 import atexit
 import ctypes as C
 import os
+import sys
 import weakref
 from dataclasses import dataclass, field
 
@@ -197,6 +198,8 @@ class Context:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return  # _close_all_contexts has run; never call HIP this late
         try:
             self.close()
         except Exception:
@@ -264,6 +267,8 @@ class Hierarchy:
     close = free
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -453,6 +458,8 @@ class Server:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

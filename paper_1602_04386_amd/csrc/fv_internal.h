@@ -203,7 +203,9 @@ void budget_release(fv_context* ctx, size_t bytes);
 // Setup (setup.hip).
 fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opts* o,
                               hipStream_t s);
-void free_hierarchy(fv_hierarchy* h);
+// sync_device: wait for every stream first (solves on any stream may still
+// read the levels); false when the caller knows no queued work uses h.
+void free_hierarchy(fv_hierarchy* h, bool sync_device = true);
 size_t hierarchy_nmax(const fv_hierarchy* h);
 
 // Solve (solve.hip).

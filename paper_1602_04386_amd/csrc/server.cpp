@@ -56,6 +56,14 @@ struct fv_server {
   uint64_t next_ticket = 1;
   uint64_t use_clock = 0;
   int inflight = 0;
+  // Deadlock-free waiting for memory: `holders` workers have an admitted batch
+  // (and may hold hierarchies and workspaces until it ends); `waiters` of them
+  // are blocked, waiting for memory or for another worker's build of the same
+  // graph.  `released` counts events that can free memory (a batch ended, a
+  // build ended, a hierarchy was evicted).
+  int holders = 0;
+  int waiters = 0;
+  uint64_t released = 0;
 };
 
 namespace {
@@ -69,14 +77,33 @@ bool evict_one(fv_server* s) {
         (victim == s->cache.end() || it->second.last_use < victim->second.last_use))
       victim = it;
   if (victim == s->cache.end()) return false;
-  fv::free_hierarchy(victim->second.h);
+  // refs == 0: every batch that used it has ended, and a batch ends only after
+  // its stream has finished, so no device work reads it any more.
+  fv::free_hierarchy(victim->second.h, /*sync_device=*/false);
   s->cache.erase(victim);
+  ++s->released;
   return true;
 }
 
-// Runs f(); on FV_E_BUDGET evicts cached hierarchies or waits for in-flight
-// work to release memory, then retries.  Gives up when nothing else holds
-// memory.
+// True while another worker holds an admitted batch and is not blocked itself:
+// that worker will end its batch (or give up) and release memory, so waiting
+// for it cannot deadlock.  Caller holds s->mu and is a holder.
+bool others_progress(const fv_server* s) { return s->holders - s->waiters - 1 > 0; }
+
+// Blocks (caller holds lk on s->mu) until the next release event, counted as
+// a waiter meanwhile.
+void wait_release(fv_server* s, std::unique_lock<std::mutex>& lk) {
+  const uint64_t seen = s->released;
+  ++s->waiters;
+  s->cv.wait(lk, [&] { return s->released != seen; });
+  --s->waiters;
+}
+
+// Runs f(); on FV_E_BUDGET evicts cached hierarchies not in use, or waits for
+// another worker's batch to release memory, then retries.  Gives up (rethrows)
+// when nothing can be evicted and no other worker is making progress: the
+// memory is then held by this worker's own batch, by blocked workers, or
+// outside the server, and waiting could last forever.
 template <class F>
 auto with_budget(fv_server* s, F f) -> decltype(f()) {
   for (;;) {
@@ -86,8 +113,8 @@ auto with_budget(fv_server* s, F f) -> decltype(f()) {
       if (e.st != FV_E_BUDGET) throw;
       std::unique_lock<std::mutex> lk(s->mu);
       if (evict_one(s)) continue;
-      if (s->inflight <= 1) throw;  // only this work holds memory
-      s->cv.wait_for(lk, std::chrono::milliseconds(1));
+      if (!others_progress(s)) throw;
+      wait_release(s, lk);
     }
   }
 }
@@ -121,6 +148,7 @@ void worker_main(fv_server* s, int share) {
         batch.push_back(t);
       }
       s->inflight += (int)batch.size();
+      ++s->holders;
     }
     // Hierarchies: cache hit, or build on this worker's stream.
     std::vector<fv_hierarchy*> hs(batch.size(), nullptr);
@@ -149,7 +177,9 @@ void worker_main(fv_server* s, int share) {
               r->res.cache_hit = 1;
               break;
             }
-            s->cv.wait_for(lk, std::chrono::milliseconds(1));
+            // Another worker builds this graph; its build ends with a
+            // release event (success or failure).
+            wait_release(s, lk);
           }
         }
       }
@@ -178,6 +208,7 @@ void worker_main(fv_server* s, int share) {
         } else {
           s->cache.erase(gid);
         }
+        ++s->released;
         s->cv.notify_all();
       } else {
         owned[k] = hs[k] ? 1 : 0;
@@ -258,10 +289,12 @@ void worker_main(fv_server* s, int share) {
         auto it = s->cache.find(r.req.graph_id);
         if (it != s->cache.end() && hs[k] == it->second.h) it->second.refs--;
       } else if (owned[k]) {
-        fv::free_hierarchy(hs[k]);
+        fv::free_hierarchy(hs[k], /*sync_device=*/false);  // this batch's stream has finished
       }
     }
     s->inflight -= (int)batch.size();
+    --s->holders;
+    ++s->released;
     s->cv.notify_all();
   }
   (void)hipStreamSynchronize(stream);

@@ -1144,11 +1144,11 @@ static void free_level(fv_hierarchy* h, Level& L) {
   L = Level();
 }
 
-void free_hierarchy(fv_hierarchy* h) {
+void free_hierarchy(fv_hierarchy* h, bool sync_device) {
   if (!h) return;
   // Solves on any stream may still read the levels; wait for them before the
   // blocks go back to the cache (hipFree would synchronise the same way).
-  (void)hipDeviceSynchronize();
+  if (sync_device) (void)hipDeviceSynchronize();
   for (int l = 0; l < FV_MAX_LEVELS; ++l) free_level(h, h->lv[l]);
   if (h->d_desc) dev_free(h->ctx, h->d_desc, sizeof(LevelDesc) * FV_MAX_LEVELS, &h->bytes);
   delete h;
@@ -1536,7 +1536,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     FV_HIP(hipStreamSynchronize(s));
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    free_hierarchy(h);
+    free_hierarchy(h, /*sync_device=*/false);  // only this build's stream used it
     throw;
   }
   return h;

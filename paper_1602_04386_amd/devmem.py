@@ -6,11 +6,30 @@ can be passed wherever the binding accepts a device array.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 
 import numpy as np
 
 _hip = None
+
+# Arrays still alive are freed by an exit handler of this module: Python runs
+# its atexit handlers before the C library's exit handlers, among them the HIP
+# runtime's own teardown, after which a hipFree from a finaliser (__del__ during
+# interpreter shutdown) touches a runtime that no longer exists and aborts the
+# process.
+_live: "weakref.WeakSet[DeviceArray]" = weakref.WeakSet()
+
+
+@atexit.register
+def _free_all():
+    for a in list(_live):
+        try:
+            a.free()
+        except Exception:
+            pass
 
 
 def hip():
@@ -50,6 +69,7 @@ class DeviceArray:
         if st != 0:
             raise MemoryError(f"hipMalloc failed ({st})")
         self._p = p
+        _live.add(self)
         self.shape = (self.count,)
         if src is not None and self.count:
             self._check(hip().hipMemcpy(self._p, src.ctypes.data, src.nbytes, _H2D))
@@ -74,6 +94,10 @@ class DeviceArray:
             self._p = None
 
     def __del__(self):
+        # During interpreter shutdown the exit handler above has already freed
+        # every live array; never call into HIP from a late finaliser.
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:

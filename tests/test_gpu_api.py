@@ -121,3 +121,69 @@ def test_server_busy_and_unknown_ticket(fv, ctx):
         srv.poll(987654321)
     assert e.value.status == fv.E_UNKNOWN_TICKET
     srv.close()
+
+
+def test_server_tight_budget_many_workers_finishes(fv):
+    """Four workers under a budget of about 1.5 hierarchies: workers that hold
+    hierarchies while others need memory must not wait on each other forever.
+    Every request ends with a status; the successful ones equal the batch
+    results, the others report E_BUDGET."""
+    print("server tight budget, 4 workers", flush=True)
+    gs = [gen.grid(60 + 6 * k, 50, "uniform", seed=40 + k) for k in range(6)]
+    kw = dict(prec="fp32", tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1,
+              max_outer=50)
+    ref_ctx = fv.Context(0)
+    hs = [fv.build_hierarchy_graph(ref_ctx, g, n_coarse=8) for g in gs]
+    hbytes = max(h.device_bytes() for h in hs)
+    ref = fv.fiedler_solve_batch(ref_ctx, hs, **kw)
+    ref_ctx.close()
+    ctx = fv.Context(0)
+    srv = fv.Server(ctx, max_inflight=4, hbm_budget_bytes=int(hbytes * 1.5), n_coarse=8, **kw)
+    order = [k % len(gs) for k in range(24)]
+    tk = [srv.submit(k, gs[k]) for k in order]
+    out = _wait(srv, tk, limit=100)
+    srv.close()
+    ctx.close()
+    assert len(out) == len(tk), f"{len(tk) - len(out)} requests never finished"
+    ok = 0
+    for k, t in zip(order, tk):
+        st = out[t][0]["status"]
+        assert st in (fv.OK, fv.E_BUDGET), st
+        if st == fv.OK:
+            ok += 1
+            assert np.array_equal(out[t][1], ref[k].x)
+    assert ok >= 1
+
+
+def test_process_exit_with_objects_left_open(fv):
+    """A program that ends with a context, a hierarchy, a server and device
+    arrays still open exits cleanly: the binding's exit handlers release them
+    while the HIP runtime still works (a hipFree from a finaliser after the
+    runtime's own teardown aborted the process with std::bad_variant_access)."""
+    import os
+    import subprocess
+    import sys
+    import textwrap
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = textwrap.dedent(f"""
+        import sys
+        sys.path.insert(0, {root!r})
+        import numpy as np
+        import gen
+        import paper_1602_04386_amd as fv
+        from paper_1602_04386_amd.devmem import DeviceArray
+        ctx = fv.Context(0)
+        g = gen.grid(64, 48, "uniform", seed=7)
+        h = fv.build_hierarchy_graph(ctx, g, n_coarse=8)
+        x = DeviceArray(dtype=np.float64, count=g.n)
+        r = fv.fiedler_solve(ctx, h, x_out=x, prec="fp32", max_outer=5, tol_res=1e-6)
+        y = DeviceArray(np.arange(10.0))
+        srv = fv.Server(ctx, max_inflight=2, n_coarse=8, prec="fp32", max_outer=3)
+        t = srv.submit(1, g)
+        print("left open", r.lam, flush=True)
+    """)
+    print("exit-with-open-objects subprocess", flush=True)
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, (p.returncode, p.stdout[-2000:], p.stderr[-2000:])
+    assert "left open" in p.stdout
