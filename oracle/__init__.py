@@ -64,6 +64,10 @@ def lib():
         L.or_colour.argtypes = [C.c_int32, i32p, i32p, C.c_uint32, i32p]
         L.or_recolour.restype = C.c_int32
         L.or_recolour.argtypes = [C.c_int32, i32p, i32p, C.c_int32, i32p]
+        L.or_colour_two.restype = C.c_int32
+        L.or_colour_two.argtypes = [C.c_int32, i32p, i32p, i32p]
+        L.or_level_colouring.restype = C.c_int32
+        L.or_level_colouring.argtypes = [C.c_int32, i32p, i32p, C.c_uint32, C.c_int32, i32p]
         L.or_sigma.restype = C.c_double
         L.or_sigma.argtypes = [C.c_int32, i32p, f64p]
         L.or_pi_apply.restype = None
@@ -179,6 +183,26 @@ def recolour(n, rowptr, col, colour_in, ncol):
     """One iterated-greedy pass over a colouring; returns (colour, count)."""
     c = np.array(colour_in, dtype=np.int32, copy=True)
     k = lib().or_recolour(n, _i32(rowptr), _i32(col), ncol, c)
+    assert k >= 0
+    return c, k
+
+
+def colour_two(n, rowptr, col):
+    """Two-colouring of a bipartite graph (each component's smallest vertex
+    colour 0); returns (colour, count) with count 0 when the graph has an odd
+    cycle."""
+    c = np.zeros(n, np.int32)
+    k = lib().or_colour_two(n, _i32(rowptr), _i32(col), c)
+    assert k >= 0
+    return c, k
+
+
+def level_colouring(n, rowptr, col, level_seed, finest=True):
+    """The smoother's colouring of a level: two colours when the finest level
+    is bipartite, else first-fit in priority order plus one iterated-greedy
+    pass."""
+    c = np.zeros(n, np.int32)
+    k = lib().or_level_colouring(n, _i32(rowptr), _i32(col), level_seed, int(finest), c)
     assert k >= 0
     return c, k
 

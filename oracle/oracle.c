@@ -448,6 +448,63 @@ int32_t or_recolour(int32_t n, const int32_t* rp, const int32_t* col, int32_t nc
   return k;
 }
 
+/*
+ * Two-colouring of a bipartite level: breadth-first search from the smallest
+ * unvisited vertex of each connected component, which takes colour 0, every
+ * vertex at odd distance from it colour 1.  A connected bipartite graph has
+ * exactly two proper 2-colourings, swapped, so fixing the colour of each
+ * component's smallest vertex makes the result unique.  Returns the number of
+ * colours (2, or 1 for a level without edges), or 0 when some edge joins two
+ * vertices of the same colour (an odd cycle: the level is not bipartite, and
+ * colour[] is then meaningless).  This is the optimal colouring of a bipartite
+ * level: the classic red-black order of Gauss-Seidel on a 5-point grid.
+ */
+int32_t or_colour_two(int32_t n, const int32_t* rp, const int32_t* col, int32_t* colour) {
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!queue) return OR_E_NOMEM;
+  for (int32_t v = 0; v < n; ++v) colour[v] = -1;
+  int32_t ncol = n > 0 ? 1 : 0;
+  for (int32_t s = 0; s < n; ++s) {
+    if (colour[s] >= 0) continue;
+    int32_t head = 0, tail = 0;
+    colour[s] = 0;
+    queue[tail++] = s;
+    while (head < tail) {
+      const int32_t v = queue[head++];
+      for (int64_t p = rp[v]; p < rp[v + 1]; ++p) {
+        const int32_t u = col[p];
+        if (colour[u] < 0) {
+          colour[u] = 1 - colour[v];
+          ncol = 2;
+          queue[tail++] = u;
+        }
+      }
+    }
+  }
+  free(queue);
+  for (int32_t v = 0; v < n; ++v)
+    for (int64_t p = rp[v]; p < rp[v + 1]; ++p)
+      if (colour[col[p]] == colour[v]) return 0;
+  return ncol;
+}
+
+/*
+ * The colouring of a level for the smoother: on the finest level (two != 0)
+ * the two-colouring when the level is bipartite; otherwise first-fit in
+ * priority order followed by one iterated-greedy pass.  Coarse levels are not
+ * tested: aggregation makes them non-bipartite in practice (an aggregate of
+ * two neighbours and a common neighbour of both form a triangle).  Returns the
+ * number of colours.
+ */
+int32_t or_level_colouring(int32_t n, const int32_t* rp, const int32_t* col, uint32_t level_seed,
+                           int32_t two, int32_t* colour) {
+  int32_t k = two ? or_colour_two(n, rp, col, colour) : 0;
+  if (k != 0) return k;
+  k = or_colour(n, rp, col, level_seed, colour);
+  if (k > 0) k = or_recolour(n, rp, col, k, colour);
+  return k;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Level operators.                                                          */
 /* ------------------------------------------------------------------------ */
@@ -648,8 +705,9 @@ void or_hier_free(void* hp) {
 /*
  * Builds the hierarchy from the adjacency W of the finest graph: while the
  * level has more than n_coarse vertices, aggregate (matching + attach), form
- * the Galerkin coarse graph, and colour the level for the smoother (first-fit
- * in priority order, then one iterated-greedy pass).  The loop
+ * the Galerkin coarse graph, and colour the level for the smoother (the
+ * two-colouring of a bipartite finest level; otherwise first-fit in priority
+ * order, then one iterated-greedy pass).  The loop
  * also stops when the next level would have fewer than 2 vertices or would not
  * be smaller, and at max_levels levels.
  */
@@ -685,9 +743,8 @@ void* or_hier_build(int32_t n, const int32_t* rp, const int32_t* col, const doub
     if (nc < 2 || nc >= F->n) { free(q); break; }
     F->q = q;
     F->colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
-    F->ncolours = or_colour(F->n, F->rp, F->col, or_level_seed(colour_seed, l), F->colour);
-    if (F->ncolours > 0)
-      F->ncolours = or_recolour(F->n, F->rp, F->col, F->ncolours, F->colour);
+    F->ncolours = or_level_colouring(F->n, F->rp, F->col, or_level_seed(colour_seed, l),
+                                     l == 0, F->colour);
     or_level* C = &h->lv[l + 1];
     C->n = nc;
     C->rp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nc + 1));

@@ -233,7 +233,7 @@ __global__ void k_fill_int(int* a, long long n, int v) {
 
 // Several int arrays filled by one launch (each fill of a level's scratch
 // arrays was a launch of its own).
-constexpr int kFillMax = 8;
+constexpr int kFillMax = 12;
 struct FillSet {
   int* p[kFillMax];
   long long n[kFillMax];
@@ -557,13 +557,239 @@ __device__ inline bool jp_try(int v, int a, int b, IP col, CP colour, uint32_t s
   return false;
 }
 
+// ---------------------------------------------------------------------------
+// Two-colouring of a bipartite level (the optimal colouring when there is one;
+// on a 5-point grid the red-black order).  A union-find forest with parities:
+// word W[v] = 2 * parent(v) + (colour of v xor colour of its parent), a root
+// holding 2 v.  Each edge {u, v} is united with "different colours": when the
+// roots differ, the larger root is hooked under the smaller one by a
+// compare-and-swap that succeeds only while it is still a root, with the link
+// parity that makes u and v differ.  Parents only ever point to smaller
+// indices, so the forest has no cycles, and a root's word changes once (when
+// it is hooked), so a failed swap means another edge made progress.  Every
+// parity relation, once stored, stays true (path compression stores a
+// vertex's relation to an ancestor), so the end result does not depend on the
+// order in which edges were united: a component's root is its smallest vertex
+// (colour 0) and every vertex's colour is its parity to the root -- the unique
+// two-colouring of a connected bipartite graph with that vertex at colour 0.
+// An edge whose ends end up with equal colours (an odd cycle) marks the level
+// as not bipartite.  Scope: the memory scope of the atomics (agent for a level
+// spread over the grid, workgroup for one workgroup's LDS).
+// ---------------------------------------------------------------------------
+template <int Scope, class WP>
+__device__ inline unsigned uf_find(WP W, unsigned x, unsigned* parity) {
+  unsigned par = 0, cur = x;
+  for (;;) {
+    const unsigned w = __hip_atomic_load(&W[cur], __ATOMIC_RELAXED, Scope);
+    if ((w >> 1) == cur) break;
+    par ^= w & 1u;
+    cur = w >> 1;
+  }
+  // x is not a root: store its relation to the root found (still an ancestor)
+  if (cur != x) __hip_atomic_store(&W[x], (cur << 1) | par, __ATOMIC_RELAXED, Scope);
+  *parity = par;
+  return cur;
+}
+
+// Unites u and v as differently coloured; returns false when they are already
+// in one tree with equal colours (an odd cycle).
+template <int Scope, class WP>
+__device__ inline bool uf_unite_diff(WP W, unsigned u, unsigned v) {
+  for (;;) {
+    unsigned pu, pv;
+    unsigned ru = uf_find<Scope>(W, u, &pu);
+    unsigned rv = uf_find<Scope>(W, v, &pv);
+    if (ru == rv) return pu != pv;
+    if (ru < rv) {
+      const unsigned t = ru, tp = pu;
+      ru = rv;
+      pu = pv;
+      rv = t;
+      pv = tp;
+    }
+    unsigned expected = ru << 1;
+    const unsigned desired = (rv << 1) | (pu ^ pv ^ 1u);
+    if (__hip_atomic_compare_exchange_strong(&W[ru], &expected, desired, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, Scope))
+      return true;
+  }
+}
+
+// Multi-workgroup form: the same forest built in bulk-synchronous rounds
+// (hooking and compression, after Shiloach and Vishkin) instead of
+// concurrent unions.  Round: every tree root fu adjacent (through an edge
+// {u, v} with f(u) = fu) to a tree with a smaller parent fv hooks under the
+// smallest such fv, with the link parity p(u) ^ p(v) ^ 1 that makes u and v
+// differ; then every vertex's path is compressed to its root.  Hooks only go
+// to smaller indices (no cycles), roots change only in the hook kernel, and
+// the rounds end when a hook kernel hooks nothing: one tree per component,
+// rooted at its smallest vertex, whose colour is 0.  On a grid the first round
+// already joins everything under vertex 0, but into paths as long as a row
+// plus a column; compression therefore runs in launches of at most kBipHops
+// jumps per vertex (each launch shortens every path by that factor, since it
+// also follows the jumps other vertices stored).  A level with a triangle is
+// not bipartite; it is recognised first and skips the rest.  An edge whose
+// ends get equal colours (a longer odd cycle) sets bad as well.
+constexpr int kBipHops = 32;
+
+// bad = 1 when some edge {v, u} closes a triangle with a w > u (rows sorted).
+__global__ void k_bip_triangle(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                               int* bad) {
+  bool tri = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n && !tri;
+       v += gridDim.x * blockDim.x) {
+    const int a0 = rp[v], a1 = rp[v + 1];
+    for (int p = a0; p < a1 && !tri; ++p) {
+      const int u = col[p];
+      if (u <= v) continue;
+      int i = p + 1, j = rp[u];  // N(v) beyond u, N(u): sorted merge
+      const int j1 = rp[u + 1];
+      while (i < a1 && j < j1) {
+        const int x = col[i], y = col[j];
+        if (x == y) {
+          tri = true;
+          break;
+        }
+        if (x < y) ++i; else ++j;
+      }
+    }
+  }
+  if (__ballot(tri) != 0ULL && (threadIdx.x & 63) == 0) *bad = 1;
+}
+
+__global__ void k_bip_init(int n, unsigned* W) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    W[v] = (unsigned)v << 1;
+}
+
+// One hooking step.  *work is set when this round has work for its
+// compression launches: a root was hooked, or the previous round's
+// compression left paths unfinished (prev_more).  The round has nothing to do
+// when the previous one had no work (prev_work == 0), and the rounds are over
+// once a round ends with *work == 0.
+__global__ void k_bip_hook(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                           unsigned* W, const int* bad, int* work, const int* prev_work,
+                           const int* prev_more) {
+  if (*bad || (prev_work && *prev_work == 0)) return;  // uniform over the grid
+  const bool pending = prev_more && *prev_more;
+  bool any = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const unsigned wv = W[v];
+    const unsigned fu = wv >> 1;
+    if ((W[fu] >> 1) != fu) continue;  // v's parent is not a root (yet)
+    unsigned best = fu, bpar = 0;
+    for (int p = rp[v], e = rp[v + 1]; p < e; ++p) {
+      const unsigned wu = W[col[p]];
+      const unsigned fv = wu >> 1;
+      if (fv < best) {
+        best = fv;
+        bpar = (wv ^ wu ^ 1u) & 1u;
+      }
+    }
+    if (best < fu) {
+      W[fu] = (best << 1) | bpar;  // one 32-bit word: parent and parity together
+      any = true;
+    }
+  }
+  if ((__ballot(any) != 0ULL || (pending && blockIdx.x == 0)) && (threadIdx.x & 63) == 0)
+    *work = 1;
+}
+
+// Up to kBipHops jumps towards the root per vertex (roots do not change inside
+// this kernel).  *more is set when some vertex has not reached its root;
+// go: the flag that says this launch has work (the round hooked something,
+// or the previous compression launch left paths unfinished).
+__global__ void k_bip_compress(int n, unsigned* W, const int* bad, const int* go, int* more) {
+  if (*bad || *go == 0) return;
+  bool left = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    unsigned w = W[v];
+    int h = 0;
+    for (;; ++h) {
+      const unsigned f = w >> 1;
+      const unsigned wf = W[f];
+      if ((wf >> 1) == f) break;
+      if (h == kBipHops) {
+        left = true;
+        break;
+      }
+      w = (wf & ~1u) | ((w ^ wf) & 1u);
+    }
+    if (h > 0) W[v] = w;
+  }
+  if (__ballot(left) != 0ULL && (threadIdx.x & 63) == 0) *more = 1;
+}
+
+// Every vertex points at its root now: its colour is its parity bit.
+__global__ void k_bip_check(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const unsigned* __restrict__ W, int* bad) {
+  if (*bad) return;
+  bool clash = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const unsigned w = W[v];
+    for (int p = rp[v], e = rp[v + 1]; p < e; ++p) clash = clash || ((W[col[p]] ^ w) & 1u) == 0;
+  }
+  if (__ballot(clash) != 0ULL && (threadIdx.x & 63) == 0) *bad = 1;
+}
+
+__global__ void k_bip_commit(int n, const unsigned* __restrict__ W, int* colour, const int* bad) {
+  if (*bad) return;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    colour[v] = (int)(W[v] & 1u);
+}
+
+// One-workgroup form over n vertices (W and colour in LDS or global memory):
+// returns true and leaves the two-colouring in colour when the level is
+// bipartite.  Every thread of the block must call; bad is a shared flag.
+template <class IP, class CP, class WP>
+__device__ bool two_colour_local(int n, IP rp, IP col, CP colour, WP W, int& bad) {
+  if (threadIdx.x == 0) bad = 0;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) W[v] = (unsigned)v << 1;
+  __syncthreads();
+  for (int v = threadIdx.x; v < n; v += blockDim.x) {
+    if (__hip_atomic_load(&bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+    for (int p = rp[v], e = rp[v + 1]; p < e; ++p) {
+      const int u = col[p];
+      if (u > v && !uf_unite_diff<__HIP_MEMORY_SCOPE_WORKGROUP>(W, (unsigned)v, (unsigned)u)) {
+        __hip_atomic_store(&bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if (bad) return false;  // uniform: read after the barrier
+  for (int v = threadIdx.x; v < n; v += blockDim.x) {
+    unsigned p;
+    (void)uf_find<__HIP_MEMORY_SCOPE_WORKGROUP>(W, (unsigned)v, &p);
+    colour[v] = (int)p;
+  }
+  __syncthreads();
+  bool clash = false;
+  for (int v = threadIdx.x; v < n; v += blockDim.x)
+    for (int p = rp[v], e = rp[v + 1]; p < e; ++p) clash = clash || colour[col[p]] == colour[v];
+  if (clash) bad = 1;
+  __syncthreads();
+  return !bad;
+}
+
 // The whole Jones-Plassmann colouring of a small level in one workgroup,
 // then the iterated-greedy pass (cnew: scratch of n); *maxc receives the
 // largest colour.  IP / CP are the pointer types of the CSR and of the two
 // colour arrays (LDS when the level fits, global otherwise).
-template <class IP, class CP>
-__device__ void colour_local_body(int n, IP rp, IP col, uint32_t seed, CP colour, CP cnew,
-                                  int* maxc, int* err, int& waiting, int* lmax) {
+template <class IP, class CP, class WP>
+__device__ void colour_local_body(int n, IP rp, IP col, uint32_t seed, int two, CP colour,
+                                  CP cnew, WP W, int* maxc, int* err, int& waiting, int* lmax) {
+  // With `two` (the finest level) a bipartite level takes its two-colouring
+  // (W: n words of scratch, the same memory as cnew); first fit and the
+  // iterated-greedy pass colour every other level.
+  if (two && two_colour_local(n, rp, col, colour, W, waiting)) {
+    int m = -1;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) m = max(m, colour[v]);
+    m = block_max_int(m, lmax);
+    if (threadIdx.x == 0) *maxc = m;
+    return;
+  }
+  __syncthreads();
   for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = -1;
   __syncthreads();
   for (int round = 0;; ++round) {
@@ -619,12 +845,13 @@ constexpr size_t kColourLocalLds = 144 * 1024;
 // load (the largest local level coloured in ~140 us on global memory).
 __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, long long m, const int* rp,
                                                             const int* col, uint32_t seed,
-                                                            int* colour, int* cnew, int* maxc,
-                                                            int* err, int lds_bytes) {
+                                                            int two, int* colour, int* cnew,
+                                                            int* maxc, int* err, int lds_bytes) {
   extern __shared__ __align__(16) unsigned char cl_dyn[];
   __shared__ int waiting;
   __shared__ int lmax[kLocalBlock / 64];
   using lint = __attribute__((address_space(3))) int*;
+  using luint = __attribute__((address_space(3))) unsigned*;
   if (lds_bytes > 0 && colour_local_lds(n, m) <= (size_t)lds_bytes) {
     lint lrp = (lint)(reinterpret_cast<int*>(cl_dyn));
     lint lcol = lrp + (n + 1);
@@ -633,11 +860,12 @@ __global__ __launch_bounds__(kLocalBlock) void k_colour_local(int n, long long m
     for (int k = threadIdx.x; k <= n; k += blockDim.x) lrp[k] = rp[k];
     for (long long k = threadIdx.x; k < m; k += blockDim.x) lcol[k] = col[k];
     __syncthreads();
-    colour_local_body(n, lrp, lcol, seed, lc, lnew, maxc, err, waiting, lmax);
+    colour_local_body(n, lrp, lcol, seed, two, lc, lnew, (luint)lnew, maxc, err, waiting, lmax);
     __syncthreads();
     for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = lc[v];
   } else {
-    colour_local_body(n, rp, col, seed, colour, cnew, maxc, err, waiting, lmax);
+    colour_local_body(n, rp, col, seed, two, colour, cnew, reinterpret_cast<unsigned*>(cnew),
+                      maxc, err, waiting, lmax);
   }
 }
 
@@ -1267,6 +1495,8 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     int* minmem = tmp.get<int>(n);
     int* id = tmp.get<int>(n + 1);
     int* cnew = tmp.get<int>(n);  // the recolouring pass's output
+    unsigned* bipw = tmp.get<unsigned>(n);  // union-find words of the two-colouring
+    int* bipbad = tmp.get<int>(1);           // the level is not bipartite
     int* tcount = tmp.get<int>(n + 1);
     int* tstart = tmp.get<int>(n + 1);
     int* tfill = tmp.get<int>(n);
@@ -1287,6 +1517,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     constexpr int kRoundCap = 4096;
     int* mflag = tmp.get<int>(kRoundCap);
     int* cflag = tmp.get<int>(kRoundCap);
+    int* bflag = tmp.get<int>(kRoundCap);  // per hooking round: something was hooked
     // [0] aggregation error, [1] largest colour, [2] a one-workgroup loop
     // overran, [3] always 0
     int* lflag = flags + 4;
@@ -1309,9 +1540,10 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // state, and the Galerkin term counters (nc < fn terms rows).
       if (!local)
         fill_multi(s, {{mflag, kRoundCap, 0}, {cflag, kRoundCap, 0}, {mate, fn, -1},
-                       {F.colour_c, fn, -1}, {cnew, fn, -1}, {tcount, fn, 0}, {tfill, fn, 0}});
+                       {F.colour_c, fn, -1}, {cnew, fn, -1}, {tcount, fn, 0}, {tfill, fn, 0},
+                       {bipbad, 1, 0}, {bflag, kRoundCap, 0}});
       else
-        fill_multi(s, {{tcount, fn, 0}, {tfill, fn, 0}});
+        fill_multi(s, {{tcount, fn, 0}, {tfill, fn, 0}, {bipbad, 1, 0}});
       auto match_rounds = [&](int b) {
         if (mr + b > kRoundCap) throw Error(FV_E_DEVICE, "matching did not terminate");
         for (int r = mr; r < mr + b; ++r) {
@@ -1331,6 +1563,41 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         sc.enqueue(LeaderFlag{root, minmem}, fn, id, true);
       };
       const uint32_t lseed = level_seed(cseed, l);
+      // A bipartite finest level is two-coloured before the first-fit rounds,
+      // which then find every vertex coloured and stop after one round.
+      int br = 0;
+      // Hooking rounds: per round r, flag bflag[S r] (the round has work) and
+      // bflag[S r + c + 1] (its compression launch c left paths unfinished),
+      // S = kBipStride; kBipCompress compression launches per round finish
+      // paths of up to kBipHops^3 links, and a longer one carries over to the
+      // next round as work.
+      constexpr int kBipCompress = 3;
+      constexpr int kBipStride = 1 + kBipCompress;
+      auto two_colour_rounds = [&](int b) {
+        if ((br + b) * kBipStride > kRoundCap)
+          throw Error(FV_E_DEVICE, "two-colouring did not terminate");
+        if (br == 0) {
+          k_bip_triangle<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, bipbad);
+          k_bip_init<<<round_grid(fn), kBlock, 0, s>>>(fn, bipw);
+        }
+        for (int r = br; r < br + b; ++r) {
+          int* f = bflag + r * kBipStride;
+          k_bip_hook<<<round_grid(fn), kBlock, 0, s>>>(
+              fn, F.rp_c, F.col_c, bipw, bipbad, f, r ? f - kBipStride : nullptr,
+              r ? f - 1 : nullptr);
+          for (int c = 0; c < kBipCompress; ++c)
+            k_bip_compress<<<round_grid(fn), kBlock, 0, s>>>(fn, bipw, bipbad, f + c, f + c + 1);
+        }
+        br += b;
+        FV_HIP(hipGetLastError());
+      };
+      // After the rounds: the edge check and (bipartite) the colouring
+      // itself, which the first-fit rounds then leave alone.
+      auto two_colour_finish = [&]() {
+        k_bip_check<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, bipw, bipbad);
+        k_bip_commit<<<round_grid(fn), kBlock, 0, s>>>(fn, bipw, F.colour_c, bipbad);
+        FV_HIP(hipGetLastError());
+      };
       auto colour_rounds = [&](int b) {
         if (cr + b > kRoundCap) throw Error(FV_E_DEVICE, "colouring did not terminate");
         for (int r = cr; r < cr + b; ++r)
@@ -1347,9 +1614,11 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         // one-workgroup path, whose loops run to the end
         const int* mdone = local ? lflag + 3 : mflag + mr - 1;
         const int* cdone = local ? lflag + 3 : cflag + cr - 1;
+        // the two-colouring rounds are unfinished while the last one had work
+        const int* bdone = (local || br == 0) ? lflag + 3 : bflag + (br - 1) * kBipStride;
         k_gather_ints<<<1, 64, 0, s>>>(
-            IntSrc{{mdone, cdone, lflag, lflag + 1, id + fn, lflag + 2}}, 6, gath);
-        FV_HIP(hipMemcpyAsync(pin_i, gath, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+            IntSrc{{mdone, cdone, lflag, lflag + 1, id + fn, lflag + 2, bipbad, bdone}}, 8, gath);
+        FV_HIP(hipMemcpyAsync(pin_i, gath, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         FV_HIP(hipStreamSynchronize(s));
       };
       if (local) {
@@ -1359,16 +1628,34 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
         const size_t cl_bytes = colour_local_lds(fn, F.m);
         const int cl_lds = cl_bytes <= kColourLocalLds ? (int)cl_bytes : 0;
         if (cl_lds > 64 * 1024) enable_colour_local_lds();
-        k_colour_local<<<1, kLocalBlock, cl_lds, s>>>(fn, F.m, F.rp_c, F.col_c, lseed, F.colour_c,
-                                                      cnew, lflag + 1, lflag + 2, cl_lds);
+        k_colour_local<<<1, kLocalBlock, cl_lds, s>>>(fn, F.m, F.rp_c, F.col_c, lseed,
+                                                      l == 0 ? 1 : 0, F.colour_c, cnew,
+                                                      lflag + 1, lflag + 2, cl_lds);
         FV_HIP(hipGetLastError());
       } else {
         match_rounds(8);
         aggregate();
+        if (l == 0) {
+          two_colour_rounds(2);
+          two_colour_finish();
+        }
         colour_rounds(16);
       }
       read_back();
       if (pin_i[5]) throw Error(FV_E_DEVICE, "matching or colouring did not terminate");
+      if (pin_i[7]) {
+        // The hooking rounds enqueued did not reach the end (rare: very
+        // long trees): finish them, then redo the colouring from scratch.
+        while (pin_i[7]) {
+          two_colour_rounds(8);
+          read_back();
+        }
+        fill_multi(s, {{cflag, kRoundCap, 0}, {F.colour_c, fn, -1}, {bipbad, 1, 0}});
+        cr = 0;
+        two_colour_finish();
+        colour_rounds(16);
+        read_back();
+      }
       while (pin_i[0]) {
         match_rounds(8);
         aggregate();
@@ -1383,7 +1670,9 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // upper bound after the recolouring pass below, trimmed once the colour
       // ranges are read back at the end of the build.
       F.ncol = pin_i[3] + 1;
-      if (!local) {
+      // (the one-workgroup kernel decides and recolours itself)
+      const bool two_coloured = l == 0 && pin_i[6] == 0;
+      if (!local && !two_coloured) {
         for (int c = F.ncol - 1; c >= 0; --c)
           k_recolour_class<<<round_grid(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.colour_c, cnew,
                                                              c);

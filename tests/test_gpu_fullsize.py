@@ -12,7 +12,7 @@
   every item that reaches residual <= 1e-6 has its eigenvalue within 1e-5 of
   the FP64 oracle on the same schedule, and at least 20 of the 24 items do.
 * The smallest square grid of the paper's scaling table (326 x 326, unit
-  weights): FP32-mixed and FP64 solves with the benchmark's parameters reach
+  weights): FP32-mixed and FP64 solves with the square-grid parameters reach
   residual <= 1e-6 and their eigenvalues lie within the Kato-Temple bound
   r^2 / (2 lambda_2 - lambda) of lambda_2 = 2 - 2 cos(pi / 326).
 """
@@ -28,6 +28,7 @@ from test_gpu_parity import compare_structure
 pytestmark = pytest.mark.gpu
 
 from bench import SOLVE as BENCH_SOLVE  # the benchmark's solve parameters
+from bench import SQUARE_SOLVE  # the square-grid scaling workload's
 
 
 def laplacian(g):
@@ -106,7 +107,7 @@ def test_paper_square_grid_closed_form(fv, ctx, prec):
     g = gen.grid(k, k)
     print(f"case grid{k}x{k} {prec}", flush=True)
     h = fv.build_hierarchy_graph(ctx, g, n_coarse=25)
-    r = fv.fiedler_solve(ctx, h, prec=prec, **BENCH_SOLVE)
+    r = fv.fiedler_solve(ctx, h, prec=prec, **SQUARE_SOLVE)
     lam2 = 2 - 2 * math.cos(math.pi / k)  # a double eigenvalue; the next one is 2 lam2
     assert r.residual <= 1e-6
     res_cpu = cpu_residual(g, r.x, r.lam)

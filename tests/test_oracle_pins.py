@@ -330,11 +330,114 @@ def test_recolouring_equals_class_rounds(orc, seed):
     assert np.all(c[rows] != c[g.col])
 
 
-def test_hierarchy_colourings_are_recoloured_first_fit(orc):
-    g = gen.grid(40, 30, "uniform", seed=6)
+def bfs_parity_colouring(n, rp, col):
+    """Independent two-colouring: unweighted distances from each connected
+    component's smallest vertex (scipy's breadth-first shortest paths), taken
+    mod 2; None when an edge joins equal parities (an odd cycle)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components, shortest_path
+
+    A = sp.csr_matrix((np.ones(len(col)), col, rp), shape=(n, n))
+    ncomp, lab = connected_components(A, directed=False)
+    out = np.zeros(n, np.int64)
+    for c in range(ncomp):
+        members = np.nonzero(lab == c)[0]
+        d = shortest_path(A, unweighted=True, directed=False, indices=int(members.min()))
+        out[members] = d[members].astype(np.int64) % 2
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    if np.any(out[rows] == out[col]):
+        return None
+    return out
+
+
+def _cycle(n):
+    a = np.arange(n)
+    return gen._csr_from_undirected(n, a, (a + 1) % n, np.ones(n))
+
+
+def test_two_colouring_closed_forms(orc):
+    # grid r x c, vertex id r*cols + c: the checkerboard (r + c) mod 2
+    g = gen.grid(7, 5)
+    c, k = orc.colour_two(g.n, g.rowptr, g.col)
+    r, cc = np.divmod(np.arange(g.n), 5)
+    assert k == 2 and np.array_equal(c, (r + cc) % 2)
+    # path: alternating from vertex 0
+    g = gen.path(9)
+    c, k = orc.colour_two(g.n, g.rowptr, g.col)
+    assert k == 2 and list(c) == [i % 2 for i in range(9)]
+    # even cycle is bipartite, odd cycle is not
+    g = _cycle(8)
+    assert orc.colour_two(g.n, g.rowptr, g.col)[1] == 2
+    g = _cycle(9)
+    assert orc.colour_two(g.n, g.rowptr, g.col)[1] == 0
+
+
+def _random_bipartite(n, seed, with_odd_edge=False):
+    u = gen.uniform01(seed, 4 * n)
+    side = (u[:n] < 0.5).astype(int)
+    side[0], side[1] = 0, 1
+    a, b = [], []
+    for k in range(n - 1):  # a spanning path that alternates when possible
+        i, j = k, k + 1
+        a.append(i)
+        b.append(j)
+    pairs = set()
+    idx = (u[n:] * n).astype(int)
+    for k in range(0, len(idx) - 1, 2):
+        i, j = int(idx[k]), int(idx[k + 1])
+        if i != j and (side[i] != side[j]):
+            pairs.add((min(i, j), max(i, j)))
+    # the spanning path may join equal sides: keep only cross edges plus a
+    # cross-side chain so that the graph stays bipartite and connected
+    lo = [v for v in range(n) if side[v] == 0]
+    hi = [v for v in range(n) if side[v] == 1]
+    for k in range(max(len(lo), len(hi))):
+        x, y = lo[min(k, len(lo) - 1)], hi[min(k, len(hi) - 1)]
+        pairs.add((min(x, y), max(x, y)))
+    if with_odd_edge:
+        pairs.add((lo[0], lo[1]) if lo[0] < lo[1] else (lo[1], lo[0]))
+    pairs = sorted(pairs)
+    a = np.array([p[0] for p in pairs])
+    b = np.array([p[1] for p in pairs])
+    return gen._csr_from_undirected(n, a, b, np.ones(len(a)))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_two_colouring_equals_bfs_parity(orc, seed):
+    """Random bipartite graphs (and, for odd seeds, the same with one edge
+    inside a side): the oracle's two-colouring equals the distance parity from
+    each component's smallest vertex, and an odd cycle is reported as 0."""
+    g = _random_bipartite(50 + 7 * seed, 900 + seed, with_odd_edge=seed % 2 == 1)
+    c, k = orc.colour_two(g.n, g.rowptr, g.col)
+    ref = bfs_parity_colouring(g.n, g.rowptr, g.col)
+    if ref is None:
+        assert k == 0
+    else:
+        assert k == 2 and np.array_equal(c, ref)
+    # a disconnected bipartite graph: two paths side by side
+    a = np.array([0, 1, 3, 4, 5])
+    b = np.array([1, 2, 4, 5, 6])
+    g2 = gen._csr_from_undirected(7, a, b, np.ones(5))
+    c2, k2 = orc.colour_two(7, g2.rowptr, g2.col)
+    assert k2 == 2 and list(c2) == [0, 1, 0, 0, 1, 0, 1]
+
+
+@pytest.mark.parametrize("kind", ["grid", "path", "rgg"])
+def test_hierarchy_colourings(orc, kind):
+    """The finest level's colouring is its two-colouring when it is bipartite
+    (grids, paths); every other level's, and a non-bipartite finest level's,
+    is first-fit in priority order followed by one iterated-greedy pass."""
+    g = {"grid": lambda: gen.grid(40, 30, "uniform", seed=6), "path": lambda: gen.path(200),
+         "rgg": lambda: gen.rgg(3000, 4)}[kind]()
     h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=8, colour_seed=5)
     for l in range(h.nlevels - 1):
         L = h.level(l)
+        ref = bfs_parity_colouring(L.n, L.rowptr, L.col) if l == 0 else None
+        if l == 0:
+            assert (ref is None) == (kind == "rgg")
+        if ref is not None:
+            assert np.array_equal(L.colour, ref) and L.ncolours == 2, l
+            continue
         c0 = jones_plassmann(L.n, L.rowptr, L.col, orc.level_seed(5, l))
         c = iterated_greedy(L.n, L.rowptr, L.col, c0)
         assert np.array_equal(L.colour, c), l
@@ -468,14 +571,16 @@ TIGHT = dict(tol_cos=1e-10, tol_res=1e-9, max_gs=2000, max_pi=50, max_outer=2000
 
 def test_paper_square_grid_within_kato_temple(orc):
     """The smallest square grid of the paper's scaling table (326 x 326 = 106,276
-    vertices, unit weights) with the SOR-accelerated parameters used for the
-    large workloads: residual <= 1e-6, and the eigenvalue within the
-    Kato-Temple bound r^2 / (lambda_next - lambda) of the double eigenvalue
-    2 - 2 cos(pi/326), the next distinct one being twice that."""
+    vertices, unit weights) with the parameters of the square-grid scaling
+    workload (SOR factor 1.95 on the red-black finest level): residual <= 1e-6,
+    and the eigenvalue within the Kato-Temple bound r^2 / (lambda_next -
+    lambda) of the double eigenvalue 2 - 2 cos(pi/326), the next distinct one
+    being twice that."""
     k = 326
     g = gen.grid(k, k)
     h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=25)
-    r = h.solve(seed=1, tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1,
+    assert h.level(0).ncolours == 2
+    r = h.solve(seed=1, tol_cos=3e-12, tol_res=1e-6, omega=1.95, max_gs=30, max_pi=1,
                 max_outer=400, tol_coarse=1e-6)
     lam2 = 2 - 2 * math.cos(math.pi / k)
     assert r.status == 0 and r.residual <= 1e-6
