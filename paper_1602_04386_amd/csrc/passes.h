@@ -32,10 +32,15 @@ constexpr int kStageU = 8;  // staging slots per thread: kStageU * kBlock = the 
 template <class VT>
 constexpr int tile_waves() { return sizeof(VT) == 4 ? 6 : 3; }
 
-template <class WT, class XT>
+// A tile is RPT * kBlock consecutive rows, RPT per thread (rows t, t + kBlock,
+// ...).  Two rows per thread let a colour of up to twice as many rows run in
+// one round of resident blocks, so that its blocks' dependent load phases are
+// paid once (a second, partial round pays them again).
+template <class WT, class XT, int RPT = 1>
 struct TileLds {
+  static constexpr int kRows = RPT * kBlock;
   static constexpr int kCap = tile_cap<WT, XT>();
-  int rp[kBlock + 1];
+  int rp[kRows + 1];
   int col[kCap];
   WT w[kCap];
   XT x[kCap];
@@ -48,11 +53,11 @@ struct TileLds {
 // all gathers: the chunk costs two memory round trips.  With loads or stores
 // under per-entry conditions the compiler moves loads next to their
 // conditional use and waits for each before issuing the next.
-template <int U, class WT, class XT, class G>
+template <int U, class WT, class XT, int RPT, class G>
 __device__ __forceinline__ void stage_chunk(const int* __restrict__ col,
                                             const WT* __restrict__ w, int p_lo, int cnt,
-                                            TileLds<WT, XT>& T, G gather) {
-  static_assert(U * kBlock <= TileLds<WT, XT>::kCap, "staging slots exceed the tile");
+                                            TileLds<WT, XT, RPT>& T, G gather) {
+  static_assert(U * kBlock <= TileLds<WT, XT, RPT>::kCap, "staging slots exceed the tile");
   const int t = threadIdx.x;
   int cc[U];
   WT ww[U];
@@ -73,31 +78,37 @@ __device__ __forceinline__ void stage_chunk(const int* __restrict__ col,
   }
 }
 
-// Walks the rows [rs, re) (re - rs <= kBlock) of a tile chunk by chunk.  For
+// Walks the rows [rs, re) (re - rs <= T.kRows) of a tile chunk by chunk.  For
 // each chunk it stages the CSR slice and gather(col) in LDS, then calls
-// body(t, a, e) in the thread of every row rs + t of the chunk, [a, e) being
-// that row's entries in T.  A row longer than T.kCap is passed to
-// direct(t) instead.  Every thread of the block must call; the rows of one
-// tile never read values that the body writes.
+// body(tt, k, a, e) for every row rs + tt of the chunk in the thread that owns
+// it (tt = threadIdx.x + k kBlock, k < RPT a compile-time index after
+// unrolling), [a, e) being that row's entries in T.  A row longer than
+// T.kCap is passed to direct(tt) instead.  Every thread of the block must
+// call; the rows of one tile never read values that the body writes.
 // skip (the phase's stop flag, loaded by the caller before this call) is
 // tested only after the row pointers are requested, so that both loads are in
 // flight together; when set, nothing else happens and false is returned.
 // pre() runs in every thread once the row pointer loads are issued and before
-// their values are used: the loads a thread issues there (its own row's
-// value) travel alongside the CSR staging instead of after it.  The block has
-// kBlock threads and re - rs <= kBlock.
-template <class WT, class XT, class P, class G, class B, class D>
+// their values are used: the loads a thread issues there (its own rows'
+// values) travel alongside the CSR staging instead of after it.  The block has
+// kBlock threads.
+template <class WT, class XT, int RPT, class P, class G, class B, class D>
 __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict__ w, int rs,
-                                       int re, TileLds<WT, XT>& T, int skip, P pre, G gather,
-                                       B body, D direct) {
+                                       int re, TileLds<WT, XT, RPT>& T, int skip, P pre,
+                                       G gather, B body, D direct) {
+  constexpr int kRows = TileLds<WT, XT, RPT>::kRows;
   const int nr = re - rs;
   const int t = threadIdx.x;
-  const bool extra = t == 0 && nr == kBlock;  // the pointer past a full tile
-  const int rp_a = t <= nr ? L.rp[rs + t] : 0;
-  const int rp_b = extra ? L.rp[rs + kBlock] : 0;
+  const bool extra = t == 0 && nr == kRows;  // the pointer past a full tile
+  int rp_a[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) rp_a[k] = t + k * kBlock <= nr ? L.rp[rs + t + k * kBlock] : 0;
+  const int rp_b = extra ? L.rp[rs + kRows] : 0;
   pre();
-  if (t <= nr) T.rp[t] = rp_a;
-  if (extra) T.rp[kBlock] = rp_b;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+    if (t + k * kBlock <= nr) T.rp[t + k * kBlock] = rp_a[k];
+  if (extra) T.rp[kRows] = rp_b;
   __syncthreads();
   if (skip) return false;
   const int* __restrict__ col = L.col;
@@ -105,7 +116,7 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
   while (lo < nr) {  // uniform: every bound comes from T.rp
     const int p_lo = T.rp[lo];
     if (T.rp[lo + 1] - p_lo > T.kCap) {
-      if (t == lo) direct(t);
+      if (t == lo % kBlock) direct(lo);
       ++lo;
       continue;
     }
@@ -125,7 +136,11 @@ __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict_
       stage_chunk<kStageU>(col, w, p_lo, cnt, T, gather);
     }
     __syncthreads();
-    if (t >= lo && t < hi) body(t, T.rp[t] - p_lo, T.rp[t + 1] - p_lo);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int tt = t + k * kBlock;
+      if (tt >= lo && tt < hi) body(tt, k, T.rp[tt] - p_lo, T.rp[tt + 1] - p_lo);
+    }
     __syncthreads();
     lo = hi;
   }
@@ -141,7 +156,7 @@ __global__ void k_phase_begin(DevState* st, int cap, int forced, double tol, int
                               int* rec, int* hdone) {
   const int done = (cap <= 0 || (use_halt && st->halt)) ? 1 : 0;
   st->done = done;
-  *hdone = done;
+  *hdone = done;  // the finishing kernels only ever raise it
   *rec = 0;
   st->iters = 0;
   st->cap = cap;
@@ -157,31 +172,83 @@ __device__ inline void store_block_sum(double (&S)[kNP], double* lds, double* pa
   if (threadIdx.x < kNP) part[threadIdx.x * stride + slot] = t;
 }
 
+// ---- finishing kernels (one block) -----------------------------------------
+
+enum FinishMode { kFinGS = 0, kFinPI = 1, kFinProlong = 2, kFinRQ = 3 };
+
+// Adds the partial-slot rows 0 .. NR-1 of slots threadIdx.x, + blockDim.x, ...
+// into S in that order.  The loads of kSlotU consecutive slots are issued
+// before any of their additions, so a large level's thousands of slots cost a
+// few memory round trips per thread instead of one per slot.
+constexpr int kSlotU = 8;
+
+template <int NR>
+__device__ inline void sum_slots(const double* part, int stride, int nslots, double (&S)[kNP]) {
+  for (int s0 = threadIdx.x; s0 < nslots; s0 += blockDim.x * kSlotU) {
+    double v[kSlotU][NR];
+#pragma unroll
+    for (int u = 0; u < kSlotU; ++u) {
+      const int s = s0 + u * blockDim.x;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) v[u][k] = s < nslots ? part[k * stride + s] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSlotU; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) S[k] += v[u][k];
+  }
+}
+
+
+// State update that closes a smoothing sweep (S: the sweep's sums, in wave 0
+// lane 0): next pending normalisation and shift, cosine, step count and the
+// stop decision.
+__device__ inline void close_gs_sweep(DevState* st, const double (&S)[kNP], int n, int* rec,
+                                      int* hdone) {
+  const Scal r = after_gs(S, n);
+  st->mu = r.mu;
+  st->inv_s = r.inv_s;
+  st->cos = r.cos;
+  st->rho = r.rho;
+  const int it = st->iters + 1;
+  st->iters = it;
+  *rec = it;
+  const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  st->done = done;
+  // The host copy only ever goes from 0 (set when the phase opens) to 1: a
+  // write across the bus on every step would hold up the kernel's end.
+  if (done) *hdone = 1;
+}
+
 // ---- smoothing sweep, one colour -------------------------------------------
 
-template <class VT>
+template <class VT, int RPT>
 __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride,
                                                   int slot_base, double omega) {
-  __shared__ TileLds<VT, VT> T;
+  __shared__ TileLds<VT, VT, RPT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
   const int done = st->done;
   VT* x = st->cur ? xb : xa;
   const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int rs = r0 + b * kBlock, re = min(rs + kBlock, r1);
+  const int rs = r0 + b * T.kRows, re = min(rs + T.kRows, r1);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  VT xown = VT(0);
-  const bool ran = for_tile_chunks<VT, VT>(
+  VT xown[RPT];
+  const bool ran = for_tile_chunks<VT, VT, RPT>(
       L, w, rs, re, T, done,
       [&] {
-        if (rs + (int)threadIdx.x < re) xown = x[rs + threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int i = rs + (int)threadIdx.x + k * kBlock;
+          xown[k] = i < re ? x[i] : VT(0);
+        }
       },
       [&](int c) { return x[c]; },
-      [&](int t, int a, int e) {
+      [&](int t, int kk, int a, int e) {
         const int i = rs + t;
-        const double xo = ((double)xown - mu) * inv_s;
+        const double xo = ((double)xown[kk] - mu) * inv_s;
         double num = 0.0, den = 0.0;
         for (int k = a; k < e; ++k) {
           const double wj = (double)T.w[k];
@@ -216,10 +283,10 @@ __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_gs_tile(LevelDesc 
 
 // ---- power step ------------------------------------------------------------
 
-template <class VT>
+template <class VT, int RPT>
 __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride) {
-  __shared__ TileLds<VT, VT> T;
+  __shared__ TileLds<VT, VT, RPT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
   const int done = st->done;
   const int cur = st->cur;
@@ -227,19 +294,23 @@ __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_pi_tile(LevelDesc 
   VT* y = cur ? xa : xb;
   const double mu = st->mu, inv_s = st->inv_s, sigma = L.sigma;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int rs = b * kBlock, re = min(rs + kBlock, L.n);
+  const int rs = b * T.kRows, re = min(rs + T.kRows, L.n);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  VT xown = VT(0);
-  const bool ran = for_tile_chunks<VT, VT>(
+  VT xown[RPT];
+  const bool ran = for_tile_chunks<VT, VT, RPT>(
       L, w, rs, re, T, done,
       [&] {
-        if (rs + (int)threadIdx.x < re) xown = x[rs + threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int i = rs + (int)threadIdx.x + k * kBlock;
+          xown[k] = i < re ? x[i] : VT(0);
+        }
       },
       [&](int c) { return x[c]; },
-      [&](int t, int a, int e) {
+      [&](int t, int kk, int a, int e) {
         const int i = rs + t;
-        const double xi = (double)xown;
+        const double xi = (double)xown[kk];
         double lx = 0.0;
         for (int k = a; k < e; ++k) lx += (double)T.w[k] * (xi - (double)T.x[k]);
         const double xo = (xi - mu) * inv_s;
@@ -258,12 +329,12 @@ __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_pi_tile(LevelDesc 
 
 // ---- prolongation ----------------------------------------------------------
 
-template <class SRC, class VT>
+template <class SRC, class VT, int RPT>
 __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_prolong_tile(LevelDesc L, const SRC* xc_a,
                                                        const SRC* xc_b, VT* xf_a, VT* xf_b,
                                                        const DevState* st, double* part,
                                                        int stride) {
-  __shared__ TileLds<VT, VT> T;
+  __shared__ TileLds<VT, VT, RPT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
   const int cur = st->cur;
   const SRC* xc = cur ? xc_b : xc_a;
@@ -271,19 +342,23 @@ __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_prolong_tile(Level
   const double mu = st->mu, inv_s = st->inv_s;
   const int* __restrict__ qs = L.qs;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int rs = b * kBlock, re = min(rs + kBlock, L.n);
+  const int rs = b * T.kRows, re = min(rs + T.kRows, L.n);
   const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  SRC cown = SRC(0);
-  for_tile_chunks<VT, VT>(
+  SRC cown[RPT];
+  for_tile_chunks<VT, VT, RPT>(
       L, w, rs, re, T, 0,
       [&] {
-        if (rs + (int)threadIdx.x < re) cown = xc[qs[rs + threadIdx.x]];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int i = rs + (int)threadIdx.x + k * kBlock;
+          cown[k] = i < re ? xc[qs[i]] : SRC(0);
+        }
       },
       [&](int c) { return (VT)(((double)xc[qs[c]] - mu) * inv_s); },
-      [&](int t, int a, int e) {
+      [&](int t, int kk, int a, int e) {
         const int i = rs + t;
-        const VT vs = (VT)(((double)cown - mu) * inv_s);
+        const VT vs = (VT)(((double)cown[kk] - mu) * inv_s);
         xf[i] = vs;
         const double v = (double)vs;
         double en = 0.0;
@@ -313,13 +388,13 @@ __global__ __launch_bounds__(kBlock) void k_rq_tile(LevelDesc L, const VT* xa, c
   const int rs = b * kBlock, re = min(rs + kBlock, L.n);
   double a3[3] = {0.0, 0.0, 0.0};
   VT xown = VT(0);
-  for_tile_chunks<double, VT>(
+  for_tile_chunks<double, VT, 1>(
       L, L.w64, rs, re, T, 0,
       [&] {
         if (rs + (int)threadIdx.x < re) xown = x[rs + threadIdx.x];
       },
       [&](int c) { return x[c]; },
-      [&](int t, int a, int e) {
+      [&](int t, int, int a, int e) {
         const int i = rs + t;
         const double xi = ((double)xown - mu) * inv_s;
         double lx = 0.0, en = 0.0;
@@ -367,33 +442,6 @@ __global__ __launch_bounds__(kBlock) void k_res_tile(LevelDesc L, const VT* xa, 
   }
 }
 
-// ---- finishing kernels (one block) -----------------------------------------
-
-enum FinishMode { kFinGS = 0, kFinPI = 1, kFinProlong = 2, kFinRQ = 3 };
-
-// Adds the partial-slot rows 0 .. NR-1 of slots threadIdx.x, + blockDim.x, ...
-// into S in that order.  The loads of kSlotU consecutive slots are issued
-// before any of their additions, so a large level's thousands of slots cost a
-// few memory round trips per thread instead of one per slot.
-constexpr int kSlotU = 8;
-
-template <int NR>
-__device__ inline void sum_slots(const double* part, int stride, int nslots, double (&S)[kNP]) {
-  for (int s0 = threadIdx.x; s0 < nslots; s0 += blockDim.x * kSlotU) {
-    double v[kSlotU][NR];
-#pragma unroll
-    for (int u = 0; u < kSlotU; ++u) {
-      const int s = s0 + u * blockDim.x;
-#pragma unroll
-      for (int k = 0; k < NR; ++k) v[u][k] = s < nslots ? part[k * stride + s] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kSlotU; ++u)
-#pragma unroll
-      for (int k = 0; k < NR; ++k) S[k] += v[u][k];
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* part, int stride,
                                                  int nslots, int n, int mode, int* rec,
                                                  int* hdone) {
@@ -425,6 +473,10 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
     st->rho = st->lambda;
     return;
   }
+  if (mode == kFinGS) {
+    close_gs_sweep(st, S, n, rec, hdone);
+    return;
+  }
   const Scal r = mode == kFinProlong ? after_prolong(S, n) : after_gs(S, n);
   st->mu = r.mu;
   st->inv_s = r.inv_s;
@@ -441,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
   *rec = it;
   const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
   st->done = done;
-  *hdone = done;
+  if (done) *hdone = 1;
 }
 
 // Finishing kernel of a sweep whose last colours are small: the block first
@@ -496,7 +548,7 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
   *rec = it;
   const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
   st->done = done;
-  *hdone = done;
+  if (done) *hdone = 1;
 }
 
 template <class VT>

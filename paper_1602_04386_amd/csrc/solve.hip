@@ -481,6 +481,26 @@ static inline int nblk(long long n, int b = kBlock) {
   return (int)std::max<long long>(1, (n + b - 1) / b);
 }
 
+// Rows per thread of a tile pass over `rows` rows: two when tiles of kBlock
+// rows would need more than one round of resident blocks (the CU count times
+// the blocks per CU that the tile's LDS allows), one otherwise (more, smaller
+// blocks spread a small level over more CUs).  FV_TILE_RPT=1 or 2 forces it.
+template <class VT>
+static int tile_rpt(long long rows) {
+  static const long long one_round = [] {
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    return (long long)ncu * tile_waves<VT>() * kBlock;
+  }();
+  static const int forced = [] {
+    const char* e = std::getenv("FV_TILE_RPT");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (forced == 1 || forced == 2) return forced;
+  return rows > one_round ? 2 : 1;
+}
+
 // Allows an engine instantiation the dynamic LDS it is launched with (more
 // than the 64 KiB default); done once per instantiation and process.
 template <class VT, int NT>
@@ -587,20 +607,29 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
   // finishing block (k_finish_gs_tail) instead of one launch each.
   int ct = L.ncol;
   while (ct > 1 && Lh.cptr_h[L.ncol] - Lh.cptr_h[ct - 1] <= kTailRows) --ct;
-  std::vector<int> nbs(L.ncol);
+  std::vector<int> nbs(L.ncol), rpt(L.ncol);
   int nslots = 0;
   for (int c = 0; c < ct; ++c) {
-    nbs[c] = nblk(Lh.cptr_h[c + 1] - Lh.cptr_h[c]);
+    const int rows = Lh.cptr_h[c + 1] - Lh.cptr_h[c];
+    rpt[c] = tile_rpt<VT>(rows);
+    nbs[c] = nblk(rows, kBlock * rpt[c]);
     nslots += nbs[c];
   }
+  const int pi_rpt = tile_rpt<VT>(L.n);
+  const int pi_nb = nblk(L.n, kBlock * pi_rpt);
   if (nslots > W.stride) throw Error(FV_E_DEVICE, "partial-sum slots exceeded");
   auto enqueue = [&](int k) {
     for (int it = 0; it < k; ++it) {
       if (gs) {
         int base = 0;
         for (int c = 0; c < ct; ++c) {
-          k_gs_tile<VT><<<nbs[c], kBlock, 0, s>>>(L, Lh.cptr_h[c], Lh.cptr_h[c + 1], xa, xb,
-                                                  W.st, W.part, W.stride, base, omega);
+          const int r0 = Lh.cptr_h[c], r1 = Lh.cptr_h[c + 1];
+          if (rpt[c] == 2)
+            k_gs_tile<VT, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
+                                                       base, omega);
+          else
+            k_gs_tile<VT, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
+                                                       base, omega);
           base += nbs[c];
         }
         if (ct < L.ncol)
@@ -611,9 +640,11 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
           k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec,
                                         hs.hdone_dev);
       } else {
-        const int nb = nblk(L.n);
-        k_pi_tile<VT><<<nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
-        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, L.n, kFinPI, rec,
+        if (pi_rpt == 2)
+          k_pi_tile<VT, 2><<<pi_nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
+        else
+          k_pi_tile<VT, 1><<<pi_nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
+        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, pi_nb, L.n, kFinPI, rec,
                                       hs.hdone_dev);
       }
     }
@@ -830,13 +861,19 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
     for (int l = t - 1; l >= 0; --l) {
       const Level& F = h->lv[l];
       const LevelDesc L = host_desc(F);
-      const int nb = nblk(F.n);
+      // (from the FP64 coarsest vector: one row per thread)
+      const int prpt = l == J - 1 ? 1 : tile_rpt<VT>(F.n);
+      const int nb = nblk(F.n, kBlock * prpt);
       if (l == J - 1) {
-        k_prolong_tile<double, VT><<<nb, kBlock, 0, s>>>(
+        k_prolong_tile<double, VT, 1><<<nb, kBlock, 0, s>>>(
             L, static_cast<const double*>(W.xa), static_cast<const double*>(W.xb),
             static_cast<VT*>(W.xa), static_cast<VT*>(W.xb), W.st, W.part, W.stride);
+      } else if (prpt == 2) {
+        k_prolong_tile<VT, VT, 2><<<nb, kBlock, 0, s>>>(
+            L, static_cast<const VT*>(W.xa), static_cast<const VT*>(W.xb), static_cast<VT*>(W.xa),
+            static_cast<VT*>(W.xb), W.st, W.part, W.stride);
       } else {
-        k_prolong_tile<VT, VT><<<nb, kBlock, 0, s>>>(
+        k_prolong_tile<VT, VT, 1><<<nb, kBlock, 0, s>>>(
             L, static_cast<const VT*>(W.xa), static_cast<const VT*>(W.xb), static_cast<VT*>(W.xa),
             static_cast<VT*>(W.xb), W.st, W.part, W.stride);
       }
