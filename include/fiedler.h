@@ -259,6 +259,7 @@ typedef struct {
   double queue_ms;   /* submit -> start of device work */
   double latency_ms; /* submit -> completion */
   int32_t cache_hit;
+  int64_t alg_bytes; /* algorithmic HBM bytes of the solve's refinement passes */
 } fv_result;
 
 fv_status fv_server_create(fv_context* ctx, const fv_server_opts* opts, fv_server** out);

@@ -22,13 +22,63 @@ OK, E_INVALID, E_NOT_SYMMETRIC, E_NOT_LAPLACIAN, E_ISOLATED, E_NOMEM, E_NOT_CONV
     0, -1, -2, -3, -4, -5, -7)
 
 
+# IEEE arithmetic everywhere: no fast-math, no contraction into fused
+# multiply-adds (-std=c99 already implies -ffp-contract=off; stated anyway), so
+# every build computes bitwise the same results.
+_FLAGS = ["-std=c99", "-ffp-contract=off", "-fPIC", "-shared"]
+
+
 def build(force: bool = False) -> str:
-    """Compiles oracle.c with gcc (IEEE arithmetic: no fast-math)."""
+    """Compiles oracle.c with gcc (portable, -O2)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC,
-                               "-lm"])
+        subprocess.check_call(["gcc", "-O2", *_FLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    return _LIB
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and the threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
+def build_native() -> str:
+    """Compiles oracle.c with -O3 -march=native for the timing baseline.  The
+    library's name carries a hash of this host's CPU model and flags, so a copy
+    built on another machine is never loaded here."""
+    import hashlib
+
+    key = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            key = "".join(l for l in f if l.startswith(("model name", "flags")))
+    except OSError:
+        pass
+    tag = hashlib.sha256(key.encode()).hexdigest()[:12]
+    path = os.path.join(_HERE, f"liboracle_native_{tag}.so")
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-march=native", *_FLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
+
+
+def use_native():
+    """Loads the -O3 -march=native build (built here if needed) in place of the
+    portable one; must be called before the first use of the oracle."""
+    global _LIB, _lib
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _LIB = build_native()
     return _LIB
 
 

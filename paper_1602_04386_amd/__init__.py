@@ -76,7 +76,8 @@ class fv_request(C.Structure):
 
 class fv_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("lambda_", C.c_double), ("residual", C.c_double),
-                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("cache_hit", C.c_int32)]
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double), ("cache_hit", C.c_int32),
+                ("alg_bytes", C.c_int64)]
 
 
 EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
@@ -450,7 +451,7 @@ class Server:
         x, _, _ = self._live.pop(ticket)
         return ({"status": r.status, "lambda": r.lambda_, "residual": r.residual,
                  "queue_ms": r.queue_ms, "latency_ms": r.latency_ms,
-                 "cache_hit": bool(r.cache_hit)}, x)
+                 "cache_hit": bool(r.cache_hit), "alg_bytes": r.alg_bytes}, x)
 
     def close(self):
         if self._h:

@@ -247,6 +247,7 @@ void worker_main(fv_server* s, int share) {
     }
     for (size_t j = 0; j < run_k.size(); ++j) st[run_k[j]] = ist[j];
     std::vector<double> solo_lam(solo_k.size(), 0.0), solo_res(solo_k.size(), 0.0);
+    std::vector<long long> solo_bytes(solo_k.size(), 0);
     for (size_t j = 0; j < solo_k.size(); ++j) {
       const size_t k = solo_k[j];
       double* xo;
@@ -261,6 +262,7 @@ void worker_main(fv_server* s, int share) {
                                     &S, stream);
         });
         solo_res[j] = S.residual;  // FV_E_NOT_CONVERGED still fills x and lambda
+        solo_bytes[j] = S.alg_bytes;
       } catch (const fv::Error& e) {
         st[k] = e.st;
       } catch (...) {
@@ -273,11 +275,13 @@ void worker_main(fv_server* s, int share) {
       Request& r = s->reqs[batch[run_k[j]]];
       r.res.lambda = lam[j];
       r.res.residual = stats[j].residual;
+      r.res.alg_bytes = stats[j].alg_bytes;
     }
     for (size_t j = 0; j < solo_k.size(); ++j) {
       Request& r = s->reqs[batch[solo_k[j]]];
       r.res.lambda = solo_lam[j];
       r.res.residual = solo_res[j];
+      r.res.alg_bytes = solo_bytes[j];
     }
     for (size_t k = 0; k < batch.size(); ++k) {
       Request& r = s->reqs[batch[k]];
