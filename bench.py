@@ -387,12 +387,27 @@ def run_batch(args):
     t_setup = time.perf_counter() - t
     log(f"setup of {len(hs)} hierarchies: {t_setup:.2f} s")
 
-    # warm-up on a slice, then the whole batch once in each mode
-    fv.fiedler_solve_batch(ctx, hs[:64], x_out=xs[:64], prec="fp32", **solve)
+    # Warm-up: the autotuner picks the launch configuration for this batch's
+    # size class (timing each candidate on a sample of the batch).
+    tune = {"autotune": 1}
     t = time.perf_counter()
-    rb = fv.fiedler_solve_batch(ctx, hs, x_out=xs, prec="fp32", **solve)
-    t_b32 = time.perf_counter() - t
-    log(f"batched FP32: {t_b32:.2f} s")
+    fv.fiedler_solve_batch(ctx, hs, x_out=xs, prec="fp32", batch=tune, **solve)
+    log(f"autotuned launch: {tune['lds_bytes_used'] >> 10} KiB LDS per workgroup, "
+        f"{tune['grid']} workgroups ({time.perf_counter() - t:.2f} s with tuning)")
+    # The whole batch: default configuration, tuned, and tuned as a captured
+    # hipGraph (captured once, then replayed); every launch gives the same bits.
+    runs = {}
+    for name, opt in (("default", {}), ("tuned", {"autotune": 2}),
+                      ("tuned_captured", {"autotune": 2, "graph": 1}),
+                      ("tuned_replayed", {"autotune": 2, "graph": 1})):
+        t = time.perf_counter()
+        rr = fv.fiedler_solve_batch(ctx, hs, x_out=xs, prec="fp32", batch=opt, **solve)
+        runs[name] = (time.perf_counter() - t, opt, rr)
+        log(f"batched FP32 {name}: {runs[name][0]:.3f} s (launch {opt.get('launch_ms', 0):.1f} ms)")
+    t_b32, _, rb = runs["tuned"]
+    assert runs["tuned_replayed"][1]["replayed"]
+    same_bits = all(a.lam == b.lam and a.schedule == b.schedule
+                    for name in runs for a, b in zip(runs[name][2], rb))
     # Per-graph loops (one fv_fiedler_solve call per graph) on every
     # args.loop_stride-th graph: a uniform sample of the same mix, so that their
     # solves/s estimate the whole batch's in bounded time.
@@ -460,6 +475,12 @@ def run_batch(args):
         "per_graph_fp32": {"value": round(rate32, 2), "unit": "solves/s",
                            "sample": f"every {args.loop_stride}th graph ({len(sub)} graphs)",
                            "seconds": round(t_l32, 3), "converged": conv(r32, sub)},
+        "launch": {"lds_bytes": tune["lds_bytes_used"], "grid": tune["grid"],
+                   "autotuned": tune["tuned"],
+                   "seconds": {k: round(v[0], 4) for k, v in runs.items()},
+                   "device_ms": {k: round(v[1].get("launch_ms", 0.0), 3)
+                                 for k, v in runs.items() if v[1]},
+                   "results_bitwise_equal_across_launches": same_bits},
         "batched_fp32": {"seconds": round(t_b32, 3), "converged": conv(rb, range(count)),
                          "solves_at_tol": n_good, "items": count,
                          "lambda_rel_diff_vs_fp64_max": dl,
@@ -817,7 +838,7 @@ def main():
     ap.add_argument("--scaling-steps", type=int, default=3, help="timed runs per scaling grid")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-runs", type=int, default=5, help="oracle runs for the median")
-    ap.add_argument("--cpu-stride", type=int, default=64,
+    ap.add_argument("--cpu-stride", type=int, default=16,
                     help="batch: the oracle baseline solves every k-th graph")
     ap.add_argument("--cpu-serve-graphs", type=int, default=12,
                     help="serve: the oracle baseline solves this many smallest pool graphs")

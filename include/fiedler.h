@@ -232,6 +232,43 @@ fv_status fv_fiedler_solve_noalloc(fv_context* ctx, const fv_hierarchy* h,
                                    int32_t x_on_device, double* lambda_out,
                                    fv_solve_stats* stats);
 
+/* Launch options of a batch (pattern of the persistent batched launch; not a
+ * paper step).  The launch configuration is the dynamic LDS each workgroup
+ * gets for a graph's level vector and staged CSRs, and with it the number of
+ * resident workgroups; every configuration gives bitwise the same results.
+ * fv_batch_opts_default: no autotuning, no capture, the default LDS. */
+typedef struct {
+  int32_t autotune;  /* 0: default configuration; 1: the autotuner's choice for
+                        the batch's size class (median and largest finest level,
+                        count, mean degree), found on the first call of a class
+                        by timing each candidate LDS size on a sample of the
+                        batch and cached for the process; 2: the cached choice
+                        when there is one, never tuning */
+  int32_t graph;     /* 1: capture the launch sequence (task upload, queue reset,
+                        the persistent launch, read-backs) in a hipGraph, kept by
+                        the context with its buffers and replayed when the next
+                        call repeats the same hierarchies, outputs and options */
+  int64_t lds_bytes; /* > 0: force this LDS per workgroup (bytes, at most 147456) */
+  /* filled in by the call */
+  int64_t lds_bytes_used;
+  int32_t grid;      /* persistent workgroups launched */
+  int32_t tuned;     /* the configuration came from the autotuner */
+  int32_t replayed;  /* the launch replayed a captured graph */
+  double launch_ms;  /* device time from the task upload to the last read-back */
+} fv_batch_opts;
+
+void fv_batch_opts_default(fv_batch_opts* opts);
+
+/* fv_fiedler_solve_batch with launch options (NULL: the defaults); the
+ * results are those of fv_fiedler_solve_batch, bit for bit.  A captured graph
+ * holds its device buffers (counted against the HBM budget) until the next
+ * captured call or fv_context_destroy. */
+fv_status fv_fiedler_solve_batch_ex(fv_context* ctx, int32_t count,
+                                    const fv_hierarchy* const* h, const fv_solve_opts* opts,
+                                    fv_batch_opts* batch, double* const* x_out,
+                                    int32_t x_on_device, double* lambda_out,
+                                    fv_solve_stats* stats, fv_status* item_status);
+
 /* ---- Serving: continuous batching of Fiedler requests over one GPU ---- */
 
 typedef struct {

@@ -64,6 +64,12 @@ class fv_solve_stats(C.Structure):
                 ("t_solve_ms", C.c_double), ("alg_bytes", C.c_int64)]
 
 
+class fv_batch_opts(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("graph", C.c_int32), ("lds_bytes", C.c_int64),
+                ("lds_bytes_used", C.c_int64), ("grid", C.c_int32), ("tuned", C.c_int32),
+                ("replayed", C.c_int32), ("launch_ms", C.c_double)]
+
+
 class fv_server_opts(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("queue_capacity", C.c_int32),
                 ("hbm_budget_bytes", C.c_size_t), ("cache_hierarchies", C.c_int32),
@@ -83,7 +89,8 @@ class fv_result(C.Structure):
 EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
            "fv_context_destroy", "fv_build_hierarchy", "fv_hierarchy_info", "fv_hierarchy_bytes",
            "fv_hierarchy_export_level", "fv_free_hierarchy", "fv_fiedler_solve",
-           "fv_fiedler_solve_noalloc", "fv_fiedler_solve_batch", "fv_server_create", "fv_submit", "fv_poll",
+           "fv_fiedler_solve_noalloc", "fv_fiedler_solve_batch", "fv_fiedler_solve_batch_ex",
+           "fv_batch_opts_default", "fv_server_create", "fv_submit", "fv_poll",
            "fv_server_destroy", "fv_status_str"]
 
 _lib = None
@@ -125,6 +132,12 @@ def lib() -> C.CDLL:
         L.fv_fiedler_solve_batch.argtypes = [vp, C.c_int32, vp, C.POINTER(fv_solve_opts), vp,
                                              C.c_int32, vp, vp, vp]
         L.fv_fiedler_solve_batch.restype = C.c_int
+        L.fv_fiedler_solve_batch_ex.argtypes = [vp, C.c_int32, vp, C.POINTER(fv_solve_opts),
+                                                C.POINTER(fv_batch_opts), vp, C.c_int32, vp, vp,
+                                                vp]
+        L.fv_fiedler_solve_batch_ex.restype = C.c_int
+        L.fv_batch_opts_default.argtypes = [C.POINTER(fv_batch_opts)]
+        L.fv_batch_opts_default.restype = None
         L.fv_server_create.argtypes = [vp, C.POINTER(fv_server_opts), C.POINTER(vp)]
         L.fv_server_create.restype = C.c_int
         L.fv_submit.argtypes = [vp, C.POINTER(fv_request), C.POINTER(C.c_uint64)]
@@ -380,11 +393,20 @@ def _solve(fn, name, ctx, h, x_out, **kw) -> SolveResult:
     return _stats_to_result(st, x, lam.value, S)
 
 
-def fiedler_solve_batch(ctx: Context, hs: list, x_out=None, **kw) -> list:
-    """fv_fiedler_solve_batch; returns one SolveResult per graph.  x_out:
-    optional list of device arrays (n float64 each, data_ptr()); otherwise host
-    numpy arrays are returned."""
+def fiedler_solve_batch(ctx: Context, hs: list, x_out=None, batch=None, **kw) -> list:
+    """fv_fiedler_solve_batch (fv_fiedler_solve_batch_ex when ``batch`` is a
+    dict of launch options: autotune, graph, lds_bytes; the dict then receives
+    the launch's lds_bytes_used, grid, tuned, replayed and launch_ms); returns
+    one SolveResult per graph.  x_out: optional list of device arrays (n
+    float64 each, data_ptr()); otherwise host numpy arrays are returned."""
     o, keep = solve_opts(**kw)
+    bo = None
+    if batch is not None:
+        bo = fv_batch_opts()
+        lib().fv_batch_opts_default(C.byref(bo))
+        bo.autotune = int(batch.get("autotune", 0))
+        bo.graph = int(batch.get("graph", 0))
+        bo.lds_bytes = int(batch.get("lds_bytes", 0))
     count = len(hs)
     if x_out is None:
         xs = [np.zeros(h.n[0]) for h in hs]
@@ -399,8 +421,14 @@ def fiedler_solve_batch(ctx: Context, hs: list, x_out=None, **kw) -> list:
     lam = (C.c_double * count)()
     stats = (fv_solve_stats * count)()
     ist = (C.c_int32 * count)()
-    st = lib().fv_fiedler_solve_batch(ctx.handle, count, hp, C.byref(o), xp, on_dev, lam, stats,
-                                      ist)
+    if bo is None:
+        st = lib().fv_fiedler_solve_batch(ctx.handle, count, hp, C.byref(o), xp, on_dev, lam,
+                                          stats, ist)
+    else:
+        st = lib().fv_fiedler_solve_batch_ex(ctx.handle, count, hp, C.byref(o), C.byref(bo), xp,
+                                             on_dev, lam, stats, ist)
+        batch.update(lds_bytes_used=bo.lds_bytes_used, grid=bo.grid, tuned=bool(bo.tuned),
+                     replayed=bool(bo.replayed), launch_ms=bo.launch_ms)
     del keep
     _check(st, "fv_fiedler_solve_batch")
     return [_stats_to_result(ist[k], xs[k], lam[k], stats[k]) for k in range(count)]

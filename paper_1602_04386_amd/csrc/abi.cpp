@@ -202,6 +202,7 @@ void fv_context_destroy(fv_context* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  fv::release_batch_graph(c);
   fv::release_scratch(c, c->scratch);
   fv::block_trim(c);
   (void)hipStreamDestroy(c->stream);
@@ -314,10 +315,23 @@ fv_status fv_fiedler_solve_noalloc(fv_context* ctx, const fv_hierarchy* h,
   })
 }
 
+void fv_batch_opts_default(fv_batch_opts* o) {
+  if (o) std::memset(o, 0, sizeof(*o));
+}
+
 fv_status fv_fiedler_solve_batch(fv_context* ctx, int32_t count, const fv_hierarchy* const* h,
                                  const fv_solve_opts* opts, double* const* x_out,
                                  int32_t x_on_device, double* lambda_out, fv_solve_stats* stats,
                                  fv_status* item_status) {
+  return fv_fiedler_solve_batch_ex(ctx, count, h, opts, nullptr, x_out, x_on_device, lambda_out,
+                                   stats, item_status);
+}
+
+fv_status fv_fiedler_solve_batch_ex(fv_context* ctx, int32_t count,
+                                    const fv_hierarchy* const* h, const fv_solve_opts* opts,
+                                    fv_batch_opts* batch, double* const* x_out,
+                                    int32_t x_on_device, double* lambda_out,
+                                    fv_solve_stats* stats, fv_status* item_status) {
   if (!ctx || count < 0 || (count > 0 && (!h || !x_out))) return FV_E_INVALID;
   for (int k = 0; k < count; ++k)
     if (!h[k] || !x_out[k] || h[k]->ctx != ctx) return FV_E_INVALID;
@@ -330,7 +344,9 @@ fv_status fv_fiedler_solve_batch(fv_context* ctx, int32_t count, const fv_hierar
   FV_GUARD({
     FV_HIP(hipSetDevice(ctx->device));
     hipStream_t s = o.stream ? static_cast<hipStream_t>(o.stream) : ctx->stream;
-    return fv::solve_batch(ctx, count, h, &o, x_out, x_on_device, lambda_out, stats,
+    if (batch && (batch->autotune < 0 || batch->autotune > 2 || batch->lds_bytes < 0))
+      return FV_E_INVALID;
+    return fv::solve_batch(ctx, count, h, &o, batch, x_out, x_on_device, lambda_out, stats,
                            item_status, s);
   })
 }

@@ -168,6 +168,7 @@ struct fv_context {
   size_t in_use = 0;   // bytes held by live hierarchies and workspaces
   std::mutex mu;       // guards in_use (the server's threads share the context)
   fv::SolveScratch scratch;  // workspace of fv_fiedler_solve
+  void* bgraph = nullptr;    // the last captured batch launch (fv_fiedler_solve_batch_ex)
   // Device blocks released by finished work, kept for reuse so that building
   // and freeing hierarchies does not pay hipMalloc / hipFree every time.
   std::multimap<size_t, void*> cache;      // block size -> block
@@ -178,6 +179,7 @@ struct fv_context {
 
 struct fv_hierarchy {
   fv_context* ctx = nullptr;
+  uint64_t serial = 0;  // unique per built hierarchy in the process (never reused)
   int levels = 0;
   fv::Level lv[FV_MAX_LEVELS];
   fv::LevelDesc* d_desc = nullptr;  // device copy of the level descriptors
@@ -226,9 +228,10 @@ fv_status solve_noalloc(fv_context* ctx, const fv_hierarchy* h, const fv_solve_o
                         double* x_out, int x_on_device, double* lambda_out,
                         fv_solve_stats* stats);
 fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* h,
-                      const fv_solve_opts* o, double* const* x_out, int x_on_device,
-                      double* lambda_out, fv_solve_stats* stats, fv_status* item_status,
-                      hipStream_t s);
+                      const fv_solve_opts* o, fv_batch_opts* bo, double* const* x_out,
+                      int x_on_device, double* lambda_out, fv_solve_stats* stats,
+                      fv_status* item_status, hipStream_t s);
+void release_batch_graph(fv_context* ctx);
 size_t solve_workspace_bytes(size_t nmax, int maxcol);
 
 // Algorithmic bytes of one refinement pass over a level.

@@ -235,8 +235,13 @@ void worker_main(fv_server* s, int share) {
     std::vector<fv_status> ist(run_h.size(), FV_OK);
     if (!run_h.empty()) {
       try {
+        // the autotuner's cached configuration for this size class, if any
+        // (a request never waits for a tuning run)
+        fv_batch_opts bo;
+        fv_batch_opts_default(&bo);
+        bo.autotune = 2;
         with_budget(s, [&] {
-          return fv::solve_batch(s->ctx, (int)run_h.size(), run_h.data(), &s->opts.solve,
+          return fv::solve_batch(s->ctx, (int)run_h.size(), run_h.data(), &s->opts.solve, &bo,
                                  run_x.data(), 0, lam.data(), stats.data(), ist.data(), stream);
         });
       } catch (const fv::Error& e) {

@@ -4,6 +4,8 @@
 // of every level that the refinement kernels read.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -1463,7 +1465,9 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
   if (f & 4) throw Error(FV_E_NOT_SYMMETRIC, "not symmetric");
   if (f & 8) throw Error(FV_E_ISOLATED, "isolated vertex");
 
+  static std::atomic<uint64_t> serials{0};
   fv_hierarchy* h = new fv_hierarchy();
+  h->serial = ++serials;
   h->ctx = ctx;
   try {
     Level& L0 = h->lv[0];

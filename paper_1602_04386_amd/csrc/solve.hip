@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <tuple>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
@@ -1051,12 +1052,146 @@ fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts*
 
 // ---------------------------------------------------------------------------
 // Batch: one persistent launch, one workgroup per graph, largest first.
+//
+// Launch configuration: the dynamic LDS each workgroup gets (a graph's level
+// vector and, when they fit, its staged CSRs) and, following from it, how many
+// workgroups stay resident per CU.  More LDS keeps more levels on chip; less
+// lets more graphs run at once.  The engine's arithmetic is the same whichever
+// memory a level sits in, and a graph's result does not depend on which
+// workgroup takes it, so every configuration gives bitwise the same results:
+// the autotuner below may pick any of them.
 // ---------------------------------------------------------------------------
-fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
-                      const fv_solve_opts* o, double* const* x_out, int x_on_device,
-                      double* lambda_out, fv_solve_stats* stats, fv_status* item_status,
-                      hipStream_t s) {
-  if (count <= 0) return FV_OK;
+static const size_t kBatchLdsCand[] = {32u << 10, 48u << 10, 64u << 10, 96u << 10, 144u << 10};
+constexpr size_t kBatchLdsMax = 144u << 10;
+
+__global__ void k_batch_reset(unsigned* queue) { *queue = 0; }
+
+template <class VT>
+static int batch_grid(int count, size_t lds) {
+  enable_engine_lds<VT, kWGBatch>(kBatchLdsMax);
+  int dev = 0, ncu = 256, per_cu = 1;
+  FV_HIP(hipGetDevice(&dev));
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(&k_engine<VT, kWGBatch>), kWGBatch, lds);
+  return std::min(count, std::max(1, ncu * std::max(per_cu, 1)));
+}
+
+// The autotuner's cache key: precision and the size class of a batch (log2 of
+// the median and largest finest level, log2 of the count, mean degree rounded
+// to a half), process-wide.
+struct TuneKey {
+  int prec, med, mx, cnt, deg;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, med, mx, cnt, deg) < std::tie(o.prec, o.med, o.mx, o.cnt, o.deg);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, size_t> g_tune;
+
+static int ilog2(long long v) {
+  int k = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++k;
+  }
+  return k;
+}
+
+static TuneKey tune_key(int count, const fv_hierarchy* const* hs, int prec) {
+  std::vector<long long> ns(count);
+  long long nn = 0, mm = 0;
+  for (int k = 0; k < count; ++k) {
+    ns[k] = hs[k]->lv[0].n;
+    nn += hs[k]->lv[0].n;
+    mm += hs[k]->lv[0].m;
+  }
+  std::nth_element(ns.begin(), ns.begin() + count / 2, ns.end());
+  const long long med = ns[count / 2];
+  const long long mx = *std::max_element(ns.begin(), ns.end());
+  return TuneKey{prec, ilog2(med), ilog2(mx), ilog2(count), (int)(2.0 * mm / std::max(nn, 1LL))};
+}
+
+// The device and pinned memory of one batch: per-item vectors, outputs,
+// states, schedules, the task table, the queue, and pinned mirrors of the
+// task table and of the read-backs.
+struct BatchBufs {
+  fv_context* ctx = nullptr;
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  size_t o_out = 0, o_st = 0, o_sched = 0, o_slen = 0, o_tasks = 0, o_queue = 0;
+  size_t p_tasks = 0, p_st = 0, p_slen = 0, p_sched = 0, p_out = 0;
+  void release() {
+    if (dev) {
+      block_put(ctx, dev);
+      budget_release(ctx, dev_bytes);
+    }
+    if (pin) (void)hipHostFree(pin);
+    dev = pin = nullptr;
+    dev_bytes = pin_bytes = 0;
+  }
+};
+
+// A captured launch sequence, kept by the context for the next batch call
+// with the same task table and configuration.
+struct BatchGraph {
+  std::vector<unsigned char> key;
+  BatchBufs bufs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    bufs.release();
+    key.clear();
+  }
+};
+
+void release_batch_graph(fv_context* ctx) {
+  if (!ctx->bgraph) return;
+  static_cast<BatchGraph*>(ctx->bgraph)->release();
+  delete static_cast<BatchGraph*>(ctx->bgraph);
+  ctx->bgraph = nullptr;
+}
+
+// Enqueues the batch's launch sequence on s: task table upload (from the
+// pinned mirror), queue reset, the engine, and the read-backs into the pinned
+// mirrors.  No memset node: the reset is a kernel, so the sequence can be
+// captured and replayed.
+template <class VT>
+static void enqueue_batch(const BatchBufs& B, int count, size_t lds, int grid, bool want_sched,
+                          size_t nout, hipStream_t s) {
+  char* base = static_cast<char*>(B.dev);
+  char* pin = static_cast<char*>(B.pin);
+  GraphTask* d_tasks = reinterpret_cast<GraphTask*>(base + B.o_tasks);
+  unsigned* queue = reinterpret_cast<unsigned*>(base + B.o_queue);
+  FV_HIP(hipMemcpyAsync(d_tasks, pin + B.p_tasks, sizeof(GraphTask) * count,
+                        hipMemcpyHostToDevice, s));
+  k_batch_reset<<<1, 1, 0, s>>>(queue);
+  k_engine<VT, kWGBatch><<<grid, kWGBatch, lds, s>>>(d_tasks, count, queue,
+                                                     (int)(lds / sizeof(VT)));
+  FV_HIP(hipGetLastError());
+  FV_HIP(hipMemcpyAsync(pin + B.p_st, base + B.o_st, sizeof(DevState) * count,
+                        hipMemcpyDeviceToHost, s));
+  FV_HIP(hipMemcpyAsync(pin + B.p_slen, base + B.o_slen, sizeof(int) * count,
+                        hipMemcpyDeviceToHost, s));
+  if (want_sched)
+    FV_HIP(hipMemcpyAsync(pin + B.p_sched, base + B.o_sched,
+                          sizeof(int) * FV_SCHEDULE_CAP * count, hipMemcpyDeviceToHost, s));
+  if (nout)
+    FV_HIP(hipMemcpyAsync(pin + B.p_out, base + B.o_out, sizeof(double) * nout,
+                          hipMemcpyDeviceToHost, s));
+}
+
+template <class VT>
+static fv_status solve_batch_t(fv_context* ctx, int count, const fv_hierarchy* const* hs,
+                               const fv_solve_opts* o, fv_batch_opts* bo, double* const* x_out,
+                               int x_on_device, double* lambda_out, fv_solve_stats* stats,
+                               fv_status* item_status, hipStream_t s) {
   // Per-item device memory: xa, xb, lx (8 bytes each per vertex) and, for
   // host outputs, the FP64 result.  States, schedules and schedule lengths of
   // all items are contiguous so that one copy each reads them back.
@@ -1066,112 +1201,231 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
     off[k + 1] = off[k] + align_up(8 * n) * 3;
     xoff[k + 1] = xoff[k] + (x_on_device ? 0 : n);
   }
-  const size_t o_out = off[count];
-  const size_t o_st = o_out + align_up(8 * xoff[count]);
-  const size_t o_sched = o_st + align_up(sizeof(DevState) * count);
-  const size_t o_slen = o_sched + align_up(sizeof(int) * FV_SCHEDULE_CAP * count);
-  const size_t o_tasks = o_slen + align_up(sizeof(int) * count);
-  const size_t o_queue = o_tasks + align_up(sizeof(GraphTask) * count);
-  const size_t bytes = o_queue + 256;
-  budget_reserve(ctx, bytes);
-  char* base = nullptr;
-  try {
-    base = static_cast<char*>(block_get(ctx, bytes));
-  } catch (...) {
-    budget_release(ctx, bytes);
-    throw;
-  }
-  struct Guard {
-    fv_context* c;
-    hipStream_t s;
-    void* p;
-    size_t b;
-    ~Guard() {
-      (void)hipStreamSynchronize(s);
-      block_put(c, p);
-      budget_release(c, b);
-    }
-  } guard{ctx, s, base, bytes};
-  DevState* d_st = reinterpret_cast<DevState*>(base + o_st);
-  int* d_sched = reinterpret_cast<int*>(base + o_sched);
-  int* d_slen = reinterpret_cast<int*>(base + o_slen);
-  double* d_out = reinterpret_cast<double*>(base + o_out);
-  std::vector<GraphTask> tasks(count);
+  const size_t nout = xoff[count];
+  BatchBufs B;
+  B.ctx = ctx;
+  B.o_out = off[count];
+  B.o_st = B.o_out + align_up(8 * nout);
+  B.o_sched = B.o_st + align_up(sizeof(DevState) * count);
+  B.o_slen = B.o_sched + align_up(sizeof(int) * FV_SCHEDULE_CAP * count);
+  B.o_tasks = B.o_slen + align_up(sizeof(int) * count);
+  B.o_queue = B.o_tasks + align_up(sizeof(GraphTask) * count);
+  const size_t dev_bytes = B.o_queue + 256;
+  B.p_tasks = 0;
+  B.p_st = align_up(sizeof(GraphTask) * count);
+  B.p_slen = B.p_st + align_up(sizeof(DevState) * count);
+  B.p_sched = B.p_slen + align_up(sizeof(int) * count);
+  B.p_out = B.p_sched + (stats ? align_up(sizeof(int) * FV_SCHEDULE_CAP * count) : 0);
+  const size_t pin_bytes = B.p_out + align_up(8 * nout);
+
+  // Task table (largest first), addresses relative to a workspace base that
+  // is filled in below, once the workspace is known.
+  std::vector<long long> work(count);
   std::vector<int> order(count);
   for (int k = 0; k < count; ++k) {
-    char* p = base + off[k];
-    const size_t n = hierarchy_nmax(hs[k]);
-    void* xa = p;
-    void* xb = p + align_up(8 * n);
-    double* lx = reinterpret_cast<double*>(p + 2 * align_up(8 * n));
-    double* xo = x_on_device ? x_out[k] : d_out + xoff[k];
-    fill_task(tasks[k], hs[k], o, 0, xa, xb, lx, xo, d_st + k, nullptr, 0,
-              d_sched + (size_t)k * FV_SCHEDULE_CAP, d_slen + k);
-    long long work = 0;
-    for (int l = 0; l < hs[k]->levels; ++l) work += hs[k]->lv[l].m + hs[k]->lv[l].n;
-    tasks[k].work = work;
+    long long w = 0;
+    for (int l = 0; l < hs[k]->levels; ++l) w += hs[k]->lv[l].m + hs[k]->lv[l].n;
+    work[k] = w;
     order[k] = k;
   }
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return tasks[a].work > tasks[b].work; });
-  std::vector<GraphTask> sorted(count);
-  for (int k = 0; k < count; ++k) sorted[k] = tasks[order[k]];
-  GraphTask* d_tasks = reinterpret_cast<GraphTask*>(base + o_tasks);
-  unsigned* queue = reinterpret_cast<unsigned*>(base + o_queue);
-  FV_HIP(hipMemcpyAsync(d_tasks, sorted.data(), sizeof(GraphTask) * count, hipMemcpyHostToDevice, s));
-  FV_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned), s));
-  int dev = 0, ncu = 256;
-  FV_HIP(hipGetDevice(&dev));
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  // As many persistent workgroups as can be resident at once (registers and
-  // the LDS slice for the level vector decide); each takes graphs from the
-  // shared queue until it is empty.
-  int per_cu = 1;
-  if (o->prec == FV_PREC_FP32_MIXED) {
-    enable_engine_lds<float, kWGBatch>(kBatchLds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_engine<float, kWGBatch>), kWGBatch, kBatchLds);
-  } else {
-    enable_engine_lds<double, kWGBatch>(kBatchLds);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_engine<double, kWGBatch>), kWGBatch, kBatchLds);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  auto make_tasks = [&](char* base, std::vector<GraphTask>& sorted) {
+    DevState* d_st = reinterpret_cast<DevState*>(base + B.o_st);
+    int* d_sched = reinterpret_cast<int*>(base + B.o_sched);
+    int* d_slen = reinterpret_cast<int*>(base + B.o_slen);
+    double* d_out = reinterpret_cast<double*>(base + B.o_out);
+    sorted.resize(count);
+    for (int j = 0; j < count; ++j) {
+      const int k = order[j];
+      char* p = base + off[k];
+      const size_t n = hierarchy_nmax(hs[k]);
+      double* xo = x_on_device ? x_out[k] : d_out + xoff[k];
+      fill_task(sorted[j], hs[k], o, 0, p, p + align_up(8 * n),
+                reinterpret_cast<double*>(p + 2 * align_up(8 * n)), xo, d_st + k, nullptr, 0,
+                d_sched + (size_t)k * FV_SCHEDULE_CAP, d_slen + k);
+      sorted[j].work = work[k];
+    }
+  };
+
+  // Launch configuration: forced, the autotuner's cached choice, a tuning
+  // run, or the default.
+  size_t lds = kBatchLds;
+  int tuned = 0;
+  const TuneKey key = tune_key(count, hs, o->prec);
+  if (bo && bo->lds_bytes > 0) {
+    lds = std::min<size_t>((size_t)bo->lds_bytes, kBatchLdsMax);
+  } else if (bo && bo->autotune) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      lds = it->second;
+      tuned = 1;
+    }
   }
-  const int grid = std::min(count, std::max(1, ncu * std::max(per_cu, 1)));
-  hipEvent_t e0, e1;
-  FV_HIP(hipEventCreate(&e0));
-  FV_HIP(hipEventCreate(&e1));
-  FV_HIP(hipEventRecord(e0, s));
-  if (o->prec == FV_PREC_FP32_MIXED) {
-    enable_engine_lds<float, kWGBatch>(kBatchLds);
-    k_engine<float, kWGBatch><<<grid, kWGBatch, kBatchLds, s>>>(
-        d_tasks, count, queue, (int)(kBatchLds / sizeof(float)));
-  } else {
-    enable_engine_lds<double, kWGBatch>(kBatchLds);
-    k_engine<double, kWGBatch><<<grid, kWGBatch, kBatchLds, s>>>(
-        d_tasks, count, queue, (int)(kBatchLds / sizeof(double)));
+  const bool tune_now = bo && bo->autotune == 1 && bo->lds_bytes <= 0 && !tuned;
+  struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  FV_HIP(hipEventCreate(&ev.a));
+  FV_HIP(hipEventCreate(&ev.b));
+
+  // The captured graph of the previous call, if this call repeats it.
+  BatchGraph* bg = (bo && bo->graph) ? static_cast<BatchGraph*>(ctx->bgraph) : nullptr;
+  std::vector<unsigned char> gkey;
+  if (bo && bo->graph) {
+    // what determines the captured sequence: every task's inputs and
+    // outputs (by their hierarchy and output pointers), the options, the
+    // configuration
+    auto put = [&](const void* p, size_t n) {
+      const unsigned char* c = static_cast<const unsigned char*>(p);
+      gkey.insert(gkey.end(), c, c + n);
+    };
+    put(&count, sizeof(count));
+    put(&x_on_device, sizeof(x_on_device));
+    put(o, sizeof(*o));
+    put(&lds, sizeof(lds));
+    const int ws = stats ? 1 : 0;
+    put(&ws, sizeof(ws));
+    for (int k = 0; k < count; ++k) {
+      put(&hs[k]->serial, sizeof(hs[k]->serial));  // a rebuilt hierarchy never matches
+      // device outputs are written by the captured launch itself; host
+      // outputs are copied from the pinned mirror after it, wherever they are
+      if (x_on_device) put(&x_out[k], sizeof(x_out[k]));
+    }
   }
-  FV_HIP(hipGetLastError());
-  FV_HIP(hipEventRecord(e1, s));
-  std::vector<DevState> hst(count);
-  std::vector<int> hsched(stats ? count * (size_t)FV_SCHEDULE_CAP : 0);
-  std::vector<int> hslen(count);
-  std::vector<double> hout(xoff[count]);
-  FV_HIP(hipMemcpyAsync(hst.data(), d_st, sizeof(DevState) * count, hipMemcpyDeviceToHost, s));
-  FV_HIP(hipMemcpyAsync(hslen.data(), d_slen, sizeof(int) * count, hipMemcpyDeviceToHost, s));
-  if (stats)
-    FV_HIP(hipMemcpyAsync(hsched.data(), d_sched, sizeof(int) * FV_SCHEDULE_CAP * count,
-                          hipMemcpyDeviceToHost, s));
-  if (!hout.empty())
-    FV_HIP(hipMemcpyAsync(hout.data(), d_out, sizeof(double) * hout.size(), hipMemcpyDeviceToHost,
-                          s));
+  const bool replay = bg && !tune_now && bg->exec && bg->key == gkey;
+
+  BatchBufs local;
+  BatchBufs* buf = &local;
+  if (replay) {
+    buf = &bg->bufs;
+  } else {
+    local = B;
+    budget_reserve(ctx, dev_bytes);
+    try {
+      local.dev = block_get(ctx, dev_bytes);
+    } catch (...) {
+      budget_release(ctx, dev_bytes);
+      throw;
+    }
+    local.dev_bytes = dev_bytes;
+    if (hipHostMalloc(&local.pin, pin_bytes, hipHostMallocDefault) != hipSuccess) {
+      local.pin = nullptr;
+      local.release();
+      throw Error(FV_E_NOMEM, "pinned staging of the batch");
+    }
+    local.pin_bytes = pin_bytes;
+    std::vector<GraphTask> sorted;
+    make_tasks(static_cast<char*>(local.dev), sorted);
+    std::memcpy(local.pin, sorted.data(), sizeof(GraphTask) * count);
+  }
+  struct Guard {
+    BatchBufs* b;
+    hipStream_t s;
+    bool own;
+    ~Guard() {
+      if (!own) return;
+      (void)hipStreamSynchronize(s);
+      b->release();
+    }
+  } guard{&local, s, !replay};
+
+  if (tune_now) {
+    // Autotuning: each candidate configuration runs a size-stratified sample
+    // of the batch (every k-th graph in the largest-first order, at most 256)
+    // on this batch's own buffers; the fastest is cached for the size class.
+    // The sample's results are overwritten by the full launch below.
+    const int stride = std::max(1, count / 256);
+    const int ns = (count + stride - 1) / stride;
+    std::vector<GraphTask> all(count), samp;
+    std::memcpy(all.data(), local.pin, sizeof(GraphTask) * count);
+    for (int j = 0; j < count; j += stride) samp.push_back(all[j]);
+    std::memcpy(local.pin, samp.data(), sizeof(GraphTask) * ns);
+    hipEvent_t a = ev.a, b = ev.b;
+    float best_ms = 0.0f;
+    size_t best = lds;
+    bool first = true;
+    for (size_t cand : kBatchLdsCand) {
+      const int grid = batch_grid<VT>(ns, cand);
+      enqueue_batch<VT>(local, ns, cand, grid, false, 0, s);  // warm (first use of each)
+      FV_HIP(hipEventRecord(a, s));
+      enqueue_batch<VT>(local, ns, cand, grid, false, 0, s);
+      FV_HIP(hipEventRecord(b, s));
+      FV_HIP(hipEventSynchronize(b));
+      float ms = 0.0f;
+      FV_HIP(hipEventElapsedTime(&ms, a, b));
+      if (first || ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+        first = false;
+      }
+    }
+    lds = best;
+    tuned = 1;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tune[key] = lds;
+    }
+    std::memcpy(local.pin, all.data(), sizeof(GraphTask) * count);
+  }
+  const int grid = batch_grid<VT>(count, lds);
+
+  hipEvent_t e0 = ev.a, e1 = ev.b;
+  if (replay) {
+    FV_HIP(hipEventRecord(e0, s));
+    FV_HIP(hipGraphLaunch(bg->exec, s));
+    FV_HIP(hipEventRecord(e1, s));
+  } else if (bo && bo->graph && !gkey.empty()) {
+    // Capture the sequence, keep it (with its buffers) for a repeat of this
+    // call, and run it.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    FV_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_batch<VT>(local, count, lds, grid, stats != nullptr, nout, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    FV_HIP(hipStreamEndCapture(s, &graph));
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      throw Error(FV_E_DEVICE, "hipGraphInstantiate");
+    }
+    if (!ctx->bgraph) ctx->bgraph = new BatchGraph();
+    bg = static_cast<BatchGraph*>(ctx->bgraph);
+    FV_HIP(hipStreamSynchronize(s));  // the old graph's buffers are idle
+    bg->release();
+    bg->graph = graph;
+    bg->exec = exec;
+    bg->key = gkey;
+    bg->bufs = local;
+    guard.own = false;
+    buf = &bg->bufs;
+    FV_HIP(hipEventRecord(e0, s));
+    FV_HIP(hipGraphLaunch(exec, s));
+    FV_HIP(hipEventRecord(e1, s));
+  } else {
+    FV_HIP(hipEventRecord(e0, s));
+    enqueue_batch<VT>(local, count, lds, grid, stats != nullptr, nout, s);
+    FV_HIP(hipEventRecord(e1, s));
+  }
   FV_HIP(hipStreamSynchronize(s));
-  if (!x_on_device)
-    for (int k = 0; k < count; ++k)
-      std::memcpy(x_out[k], hout.data() + xoff[k], sizeof(double) * (xoff[k + 1] - xoff[k]));
   float ms = 0.0f;
   FV_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  const char* pin = static_cast<const char*>(buf->pin);
+  const DevState* hst = reinterpret_cast<const DevState*>(pin + buf->p_st);
+  const int* hslen = reinterpret_cast<const int*>(pin + buf->p_slen);
+  const int* hsched = reinterpret_cast<const int*>(pin + buf->p_sched);
+  const double* hout = reinterpret_cast<const double*>(pin + buf->p_out);
+  if (!x_on_device)
+    for (int k = 0; k < count; ++k)
+      std::memcpy(x_out[k], hout + xoff[k], sizeof(double) * (xoff[k + 1] - xoff[k]));
   for (int k = 0; k < count; ++k) {
     if (lambda_out) lambda_out[k] = hst[k].lambda;
     if (item_status) item_status[k] = hst[k].err ? FV_E_NOT_CONVERGED : FV_OK;
@@ -1194,7 +1448,26 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
       S.alg_bytes = schedule_bytes(h, S.schedule, S.schedule_len, o->prec);
     }
   }
+  if (bo) {
+    bo->lds_bytes_used = (int64_t)lds;
+    bo->grid = grid;
+    bo->tuned = tuned;
+    bo->replayed = replay ? 1 : 0;
+    bo->launch_ms = ms;
+  }
   return FV_OK;
+}
+
+fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* hs,
+                      const fv_solve_opts* o, fv_batch_opts* bo, double* const* x_out,
+                      int x_on_device, double* lambda_out, fv_solve_stats* stats,
+                      fv_status* item_status, hipStream_t s) {
+  if (count <= 0) return FV_OK;
+  if (o->prec == FV_PREC_FP32_MIXED)
+    return solve_batch_t<float>(ctx, count, hs, o, bo, x_out, x_on_device, lambda_out, stats,
+                                item_status, s);
+  return solve_batch_t<double>(ctx, count, hs, o, bo, x_out, x_on_device, lambda_out, stats,
+                               item_status, s);
 }
 
 }  // namespace fv
