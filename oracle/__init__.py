@@ -114,6 +114,10 @@ def lib():
         L.or_colour.argtypes = [C.c_int32, i32p, i32p, C.c_uint32, i32p]
         L.or_recolour.restype = C.c_int32
         L.or_recolour.argtypes = [C.c_int32, i32p, i32p, C.c_int32, i32p]
+        L.or_hec_random.restype = C.c_int32
+        L.or_hec_random.argtypes = [C.c_int32, i32p, i32p, f64p, i32p, i32p]
+        L.or_randperm.restype = None
+        L.or_randperm.argtypes = [C.c_int32, C.c_uint64, i32p]
         L.or_colour_two.restype = C.c_int32
         L.or_colour_two.argtypes = [C.c_int32, i32p, i32p, i32p]
         L.or_level_colouring.restype = C.c_int32
@@ -144,6 +148,9 @@ def lib():
         L.or_hier_build.restype = C.c_void_p
         L.or_hier_build.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_int32, C.c_int32, C.c_uint64,
                                     C.POINTER(C.c_int32)]
+        L.or_hier_build_hec.restype = C.c_void_p
+        L.or_hier_build_hec.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_int32, C.c_int32,
+                                        C.c_uint64, C.c_uint64, C.POINTER(C.c_int32)]
         L.or_hier_free.restype = None
         L.or_hier_free.argtypes = [C.c_void_p]
         L.or_hier_nlevels.restype = C.c_int32
@@ -235,6 +242,21 @@ def recolour(n, rowptr, col, colour_in, ncol):
     k = lib().or_recolour(n, _i32(rowptr), _i32(col), ncol, c)
     assert k >= 0
     return c, k
+
+
+def hec_random(n, rowptr, col, w, perm):
+    """Algorithm 1 (randomised heavy edge coarsening) in the visiting order
+    perm; returns (q, number of aggregates)."""
+    q = np.zeros(n, np.int32)
+    c = lib().or_hec_random(n, _i32(rowptr), _i32(col), _f64(w), _i32(perm), q)
+    assert c >= 0
+    return q, c
+
+
+def randperm(n, seed):
+    p = np.zeros(n, np.int32)
+    lib().or_randperm(n, seed, p)
+    return p
 
 
 def colour_two(n, rowptr, col):
@@ -351,11 +373,15 @@ class SolveResult:
 class Hierarchy:
     """Hierarchy built by the oracle (Algorithm 3, Step 1)."""
 
-    def __init__(self, n, rowptr, col, w, n_coarse=25, max_levels=64, colour_seed=0):
+    def __init__(self, n, rowptr, col, w, n_coarse=25, max_levels=64, colour_seed=0,
+                 hec_seed=0):
+        """hec_seed != 0: the paper's randomised heavy edge coarsening
+        (Algorithm 1 in random visiting orders) instead of the deterministic
+        matching; an oracle-only mode."""
         st = C.c_int32(0)
         self._rp, self._col, self._w = _i32(rowptr), _i32(col), _f64(w)
-        self._h = lib().or_hier_build(n, self._rp, self._col, self._w, n_coarse, max_levels,
-                                      colour_seed, C.byref(st))
+        self._h = lib().or_hier_build_hec(n, self._rp, self._col, self._w, n_coarse, max_levels,
+                                          colour_seed, hec_seed, C.byref(st))
         if not self._h:
             raise RuntimeError(f"oracle hierarchy build failed: {st.value}")
         self.nlevels = lib().or_hier_nlevels(self._h)

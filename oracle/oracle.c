@@ -262,6 +262,60 @@ int32_t or_aggregate(int32_t n, const int32_t* rp, const int32_t* col, const dou
   return nc;
 }
 
+/*
+ * Heavy edge coarsening as Algorithm 1 prints it (oracle-only mode, for
+ * comparison with the deterministic matching): vertices are visited in the
+ * order perm[0], perm[1], ...; a vertex not yet in an aggregate looks up its
+ * heaviest neighbour (the most negative entry of its column of L; ties to
+ * the smallest index, as MATLAB's min returns the first minimum) and either
+ * opens a new aggregate with it, when that neighbour is free too, or joins the
+ * neighbour's aggregate.  Aggregates are numbered in the order they are
+ * opened.  Every aggregate has at least two vertices (each vertex is opened
+ * with a neighbour or joins an existing aggregate).  Returns the number of
+ * aggregates, or OR_E_ISOLATED for a vertex without neighbours.
+ */
+int32_t or_hec_random(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                      const int32_t* perm, int32_t* q) {
+  for (int32_t v = 0; v < n; ++v) q[v] = -1;
+  int32_t c = 0;
+  for (int32_t t = 0; t < n; ++t) {
+    const int32_t v = perm[t];
+    if (q[v] >= 0) continue;
+    if (rp[v + 1] == rp[v]) return OR_E_ISOLATED;
+    int32_t m = -1;
+    double best = 0.0;
+    for (int64_t p = rp[v]; p < rp[v + 1]; ++p)
+      if (m < 0 || w[p] > best || (w[p] == best && col[p] < m)) {
+        m = col[p];
+        best = w[p];
+      }
+    if (q[m] < 0) {
+      q[m] = c;
+      q[v] = c;
+      ++c;
+    } else {
+      q[v] = q[m];
+    }
+  }
+  return c;
+}
+
+/* A uniformly random permutation of 0..n-1 by the Fisher-Yates shuffle
+ * (Knuth, TAOCP vol. 2, Algorithm P), drawing j uniform in [0, i] as
+ * floor(u (i + 1)) from the 53-bit uniforms of SplitMix64(seed). */
+void or_randperm(int32_t n, uint64_t seed, int32_t* perm) {
+  uint64_t s = seed;
+  for (int32_t i = 0; i < n; ++i) perm[i] = i;
+  for (int32_t i = n - 1; i > 0; --i) {
+    const double u = (double)(or_splitmix64(&s) >> 11) * (1.0 / 9007199254740992.0);
+    int32_t j = (int32_t)(u * (double)(i + 1));
+    if (j > i) j = i;
+    const int32_t t = perm[i];
+    perm[i] = perm[j];
+    perm[j] = t;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Galerkin coarse Laplacian L_c = I L I^T (Algorithm 3, Step 1).            */
 /* ------------------------------------------------------------------------ */
@@ -711,9 +765,22 @@ void or_hier_free(void* hp) {
  * also stops when the next level would have fewer than 2 vertices or would not
  * be smaller, and at max_levels levels.
  */
+void* or_hier_build_hec(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                        int32_t n_coarse, int32_t max_levels, uint64_t colour_seed,
+                        uint64_t hec_seed, int32_t* status);
+
 void* or_hier_build(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
                     int32_t n_coarse, int32_t max_levels, uint64_t colour_seed,
                     int32_t* status) {
+  return or_hier_build_hec(n, rp, col, w, n_coarse, max_levels, colour_seed, 0, status);
+}
+
+/* hec_seed != 0: every level is aggregated by or_hec_random in the order of
+ * or_randperm(n_l, hec_seed + l) (the paper's randomised coarsening, an
+ * oracle-only mode); 0: the deterministic matching and attachment. */
+void* or_hier_build_hec(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                        int32_t n_coarse, int32_t max_levels, uint64_t colour_seed,
+                        uint64_t hec_seed, int32_t* status) {
   or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
   if (!h) { *status = OR_E_NOMEM; return NULL; }
   if (max_levels < 1) max_levels = 1;
@@ -736,8 +803,14 @@ void* or_hier_build(int32_t n, const int32_t* rp, const int32_t* col, const doub
     if (F->n <= n_coarse || l + 1 >= max_levels) break;
     int32_t* mate = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
     int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)F->n);
-    int32_t st = or_match(F->n, F->rp, F->col, F->w, mate);
-    int32_t nc = st == OR_OK ? or_aggregate(F->n, F->rp, F->col, F->w, mate, q) : st;
+    int32_t nc;
+    if (hec_seed) {
+      or_randperm(F->n, hec_seed + (uint64_t)l, mate);  /* mate holds the order here */
+      nc = or_hec_random(F->n, F->rp, F->col, F->w, mate, q);
+    } else {
+      int32_t st = or_match(F->n, F->rp, F->col, F->w, mate);
+      nc = st == OR_OK ? or_aggregate(F->n, F->rp, F->col, F->w, mate, q) : st;
+    }
     free(mate);
     if (nc < 0) { free(q); or_hier_free(h); *status = nc; return NULL; }
     if (nc < 2 || nc >= F->n) { free(q); break; }

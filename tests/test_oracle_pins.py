@@ -474,6 +474,43 @@ def test_gs_sweep_is_matrix_splitting(orc, omega, rho):
     assert np.allclose(got, expect, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("rho", [0.0, 0.05, 3.0])
+def test_lexicographic_sweep_is_matrix_splitting(orc, rho):
+    """Algorithm 2's literal order (rows 1..n, the oracle-only mode): one sweep
+    solves (D - W_l) x' = (W_u + rho I) x with W_l / W_u the strict lower /
+    upper triangles in the natural index order (no permutation)."""
+    g = gen.random_connected(40, 29)
+    x = np.cos(np.arange(g.n) * 0.31) + 0.1
+    W = dense_W(g.n, g.rowptr, g.col, g.w)
+    D = np.diag(W.sum(1))
+    Wl, Wu = np.tril(W, -1), np.triu(W, 1)
+    expect = np.linalg.solve(D - Wl, (Wu + rho * np.eye(g.n)) @ x)
+    got = orc.gs_sweep_lex(g.n, g.rowptr, g.col, g.w, x.copy(), rho=rho)
+    assert np.allclose(got, expect, rtol=1e-13, atol=1e-13)
+    # one sweep differs from the multicolour order's on the same graph: the
+    # order matters, so a wrong row range would show
+    c, k = orc.colour(g.n, g.rowptr, g.col, orc.level_seed(0, 0))
+    assert not np.allclose(oracle_sweep(orc, g, c, k, x, rho, 1.0), expect, atol=1e-6)
+
+
+@pytest.mark.parametrize("k", [24, 40])
+def test_lexicographic_mode_solves_path(orc, k):
+    """The whole solve in the lexicographic order on a path of k vertices: the
+    closed form lambda_2 = 2 - 2 cos(pi/k), phi_2 = cos(pi (i + 1/2)/k)."""
+    g = gen.path(k)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=4)
+    r = h.solve(seed=1, lexicographic=True, tol_cos=1e-14, tol_res=1e-11, max_gs=2000,
+                max_pi=20, max_outer=20000)
+    lam = 2 - 2 * math.cos(math.pi / k)
+    assert r.status == 0 and abs(r.lam - lam) <= 1e-10 * lam
+    phi = np.cos(math.pi * (np.arange(k) + 0.5) / k)
+    phi /= np.linalg.norm(phi)
+    assert 1 - abs(float(r.x @ phi)) <= 1e-9
+    # the lexicographic schedule is not the multicolour one
+    rm = h.solve(seed=1, tol_cos=1e-14, tol_res=1e-11, max_gs=2000, max_pi=20, max_outer=20000)
+    assert r.counts != rm.counts or r.x.tobytes() != rm.x.tobytes()
+
+
 def oracle_sweep(orc, g, c, k, x, rho, omega):
     import ctypes as C
     xx = np.ascontiguousarray(x, dtype=np.float64).copy()
@@ -682,3 +719,52 @@ def test_replay_reproduces_schedule_bitwise(orc):
     r2 = h.solve(seed=3, replay=r1.counts)
     assert r2.counts == r1.counts
     assert np.array_equal(r1.x, r2.x) and r1.lam == r2.lam
+
+
+# ------------------------------------------- randomised heavy edge coarsening --
+
+def hec_reference(n, rp, col, w, perm):
+    """Algorithm 1 written out in Python on a dense copy: in the visiting order,
+    an unassigned vertex takes the smallest entry of its column of L
+    (argmin over the whole column, the diagonal included: the most negative
+    entry is the heaviest edge; the first index on ties) and pairs with it or
+    joins its aggregate."""
+    Ld = -dense_W(n, rp, col, w)
+    np.fill_diagonal(Ld, -Ld.sum(axis=1))
+    q = np.full(n, -1)
+    c = 0
+    for v in perm:
+        if q[v] >= 0:
+            continue
+        m = int(np.argmin(Ld[:, v]))
+        if q[m] < 0:
+            q[m] = q[v] = c
+            c += 1
+        else:
+            q[v] = q[m]
+    return q, c
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_randomised_hec_equals_algorithm_1(orc, seed):
+    g = gen.random_connected(70 + 9 * seed, 500 + seed, dyadic=seed % 2 == 0)
+    perm = orc.randperm(g.n, 99 + seed)
+    assert sorted(perm) == list(range(g.n))
+    q, c = orc.hec_random(g.n, g.rowptr, g.col, g.w, perm)
+    qr, cr = hec_reference(g.n, g.rowptr, g.col, g.w, perm)
+    assert c == cr and np.array_equal(q, qr)
+    sizes = np.bincount(q, minlength=c)
+    assert sizes.min() >= 2 and c <= g.n // 2  # every aggregate has two or more vertices
+
+
+def test_randomised_hec_hierarchy_solves_grid(orc):
+    """The whole method on hierarchies from the paper's randomised coarsening:
+    the 20 x 9 grid's lambda_2 = 2 - 2 cos(pi/20), and each level at most half
+    the previous one."""
+    g = gen.grid(20, 9)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=8, hec_seed=7)
+    ns = [h.level(l).n for l in range(h.nlevels)]
+    assert all(b <= a // 2 for a, b in zip(ns, ns[1:]))
+    r = h.solve(seed=1, tol_cos=1e-12, tol_res=1e-10, max_gs=2000, max_pi=20, max_outer=5000)
+    lam = 2 - 2 * math.cos(math.pi / 20)
+    assert r.status == 0 and abs(r.lam - lam) <= 1e-9 * lam
