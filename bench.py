@@ -59,6 +59,11 @@ SQUARE_SOLVE = dict(SOLVE, omega=1.95)
 # power steps per phase, finest rounds until residual <= 1e-6 (the oracle:
 # 8 rounds, 2,200 sweeps on the 1024 x 1000 grid).
 GS_SOLVE = dict(SOLVE, omega=1.0, tol_cos=0.0, max_gs=100, max_pi=2)
+# Many mid-size graphs (the batch mix, the serving pool): at SOR factor 1.9
+# the cosine tolerance stops the finest rounds of many mid-size 4:3 grids
+# with the residual just above 1e-6 (454 of 526 sampled grids reach it in 200
+# rounds); at 1.95 all of them do, in 7 to 15 rounds.
+BATCH_SOLVE = dict(SOLVE, omega=1.95, max_outer=200)
 N_COARSE = 25
 
 
@@ -372,7 +377,7 @@ def run_batch(args):
     graphs = gen.batch_mix(args.batch_count)
     log(f"generated {len(graphs)} graphs, sum n={sum(g.n for g in graphs)} in "
         f"{time.perf_counter() - t:.1f} s")
-    solve = dict(SOLVE, max_outer=200)
+    solve = BATCH_SOLVE
     ctx = fv.Context(0)
     dev = [(DeviceArray(g.rowptr), DeviceArray(g.col), DeviceArray(g.w)) for g in graphs]
     xs = [DeviceArray(dtype=np.float64, count=g.n) for g in graphs]
@@ -537,7 +542,7 @@ def run_serve(args):
     pool = gen.serve_pool(args.pool)
     log(f"generated pool of {len(pool)} graphs, sum n={sum(g.n for g in pool)} in "
         f"{time.perf_counter() - t:.1f} s")
-    solve = dict(SOLVE, max_outer=10)
+    solve = dict(BATCH_SOLVE, max_outer=10)
     ctx = fv.Context(0)
     srv = fv.Server(ctx, max_inflight=64, queue_capacity=1 << 16, cache_hierarchies=True,
                     n_coarse=N_COARSE, prec="fp32", **solve)
