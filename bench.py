@@ -19,6 +19,8 @@ Other workloads (one JSON line each):
 * ``serve``: open-loop Poisson requests against the serving loop (pool of
   request graphs, n log-uniform in [1e3, 2e6], 70% random geometric / 30%
   grids), latency from the scheduled arrival, p50/p99.
+* ``partition``: an 8-way recursive spectral bisection (median cuts) of the
+  1024 x 1000 grid, with cut ratio and part sizes.
 * ``scaling``: the paper's grid-scaling experiment (Section 4, the second
   table): the 20 N x N unit grids from 326^2 to 978^2, setup + solve time
   against n with a least-squares line, beside the paper's MATLAB times.
@@ -795,6 +797,59 @@ def run_scaling(args):
     return out
 
 
+def run_partition(args):
+    """Spectral partitioning, the use of the Fiedler vector the paper names:
+    an args.parts-way recursive bisection (median cuts) of the 1024 x 1000
+    grid, each cut solved to residual 1e-6 in FP32-mixed; cut weight over total
+    weight and part sizes, beside the oracle's own recursion (FP64)."""
+    import numpy as np
+
+    import gen
+    import paper_1602_04386_amd as fv
+
+    g = gen.grid_1024x1000()
+    ctx = fv.Context(0)
+    kw = dict(SOLVE, prec=args.prec)
+    for _ in range(args.warmup):
+        fv.spectral_partition(ctx, g, parts=args.parts, **kw)
+    times, st = [], None
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        labels, st = fv.spectral_partition(ctx, g, parts=args.parts, **kw)
+        times.append(time.perf_counter() - t)
+    ctx.close()
+    el = statistics.median(times)
+    log(f"partition: {el * 1e3:.1f} ms, cut ratio {st['cut_weight'] / st['total_weight']:.5f}")
+    out = {
+        "metric": f"{args.parts}-way spectral partitions/s (recursive median bisection of phi_2, "
+                  f"grid 1024x1000)",
+        "value": round(1.0 / el, 3), "unit": "partitions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32-mixed" if args.prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "grid 1024x1000, weights iid U[0.5,1.5] (SplitMix64 seed 2)",
+                   "parts": args.parts, "cut": "median", "solve": SOLVE},
+        "cut_ratio": st["cut_weight"] / st["total_weight"],
+        "part_sizes": [st["part_size_min"], st["part_size_max"]],
+        "solves": st["solves"], "not_converged": st["not_converged"],
+    }
+    if not args.no_cpu:
+        oracle, host = oracle_native()
+        t = time.perf_counter()
+        ref, _ = oracle.spectral_partition(g, args.parts, "median", **SOLVE)
+        t_cpu = time.perf_counter() - t
+        rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+        m = (ref[rows] != ref[g.col]) & (g.col > rows)
+        out["agreement_with_oracle"] = float(np.mean(ref == labels))
+        out["oracle_cut_ratio"] = float(g.w[m].sum()) / st["total_weight"]
+        out["cpu_baseline"] = {
+            "value": round(1.0 / t_cpu, 4), "unit": "partitions/s", "cores": 1, "kind": "oracle",
+            "sample": f"one {args.parts}-way recursion of the same grid, FP64, same parameters "
+                      f"({t_cpu:.1f} s)", "build": "gcc -O3 -march=native -ffp-contract=off",
+            "cpu_model": host["model"], "nproc": host["nproc"]}
+    return out
+
+
 def run_counters_probe(args):
     """Short run for hardware-counter passes: one 256 MiB device-to-device
     copy (the calibration kernel, known bytes), then the level-0 sweeps of the
@@ -839,7 +894,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--workload", default="grid",
-                    choices=["grid", "rgg", "batch", "serve", "scaling"])
+                    choices=["grid", "rgg", "batch", "serve", "scaling", "partition"])
+    ap.add_argument("--parts", type=int, default=8, help="partition: number of parts")
     ap.add_argument("--scaling-steps", type=int, default=3, help="timed runs per scaling grid")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-runs", type=int, default=5, help="oracle runs for the median")
@@ -865,7 +921,7 @@ def main():
         print(json.dumps(run_counters_probe(args)))
         return
     run = {"grid": run_grid, "rgg": run_rgg, "batch": run_batch, "serve": run_serve,
-           "scaling": run_scaling}[args.workload]
+           "scaling": run_scaling, "partition": run_partition}[args.workload]
     print(json.dumps(run(args)))
 
 

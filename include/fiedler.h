@@ -269,6 +269,40 @@ fv_status fv_fiedler_solve_batch_ex(fv_context* ctx, int32_t count,
                                     int32_t x_on_device, double* lambda_out,
                                     fv_solve_stats* stats, fv_status* item_status);
 
+/* ---- Spectral partitioning (the use of phi_2 the paper names: graph
+ * partitioning and spectral clustering, Introduction and Conclusion) ---- */
+
+typedef struct {
+  int32_t parts; /* a power of two, >= 2: log2(parts) rounds of bisection */
+  int32_t cut;   /* 0: median cut -- the smaller half by (phi_2 value, vertex
+                    index) goes to the lower part; 1: sign cut -- phi_2 < 0 */
+} fv_partition_opts;
+
+typedef struct {
+  int32_t parts;
+  int32_t part_size_min, part_size_max;
+  int32_t solves;        /* Fiedler solves run (one per part cut) */
+  int32_t not_converged; /* of those, how many ended FV_E_NOT_CONVERGED (their
+                            vector is still used) */
+  double cut_weight;     /* total weight of the edges between parts */
+  double total_weight;   /* total edge weight */
+  double t_ms;           /* wall time of the call */
+} fv_partition_stats;
+
+/* Recursive spectral bisection: every part of the current round is cut in two
+ * by its own Fiedler vector (its induced subgraph is extracted on the device,
+ * a hierarchy built with hopts and solved with sopts), until `parts` parts.
+ * Part p of a round becomes parts 2p and 2p + 1.  A vertex left without an
+ * edge inside its part takes no part in that solve and joins the smaller half.
+ * graph is the adjacency form (is_adjacency = 1); part_out receives n labels
+ * in [0, parts) (device pointer when part_on_device).  Errors: input errors as
+ * fv_build_hierarchy, FV_E_INVALID (parts not a power of two >= 2, the
+ * Laplacian form), FV_E_NOMEM, FV_E_BUDGET, FV_E_DEVICE. */
+fv_status fv_spectral_partition(fv_context* ctx, const fv_csr* graph,
+                                const fv_hier_opts* hopts, const fv_solve_opts* sopts,
+                                const fv_partition_opts* popts, int32_t* part_out,
+                                int32_t part_on_device, fv_partition_stats* stats);
+
 /* ---- Serving: continuous batching of Fiedler requests over one GPU ---- */
 
 typedef struct {

@@ -433,3 +433,63 @@ def solve_graph(g, n_coarse=25, colour_seed=0, **kw):
     """Builds the hierarchy of adjacency CSR ``g`` and solves."""
     h = Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=n_coarse, colour_seed=colour_seed)
     return h, h.solve(**kw)
+
+
+def spectral_partition(g, parts, cut="median", vector=None, n_coarse=25, **solve_kw):
+    """Recursive spectral bisection, the oracle's counterpart of the library's
+    partitioning: log2(parts) rounds; in each, part p's induced subgraph
+    (vertices of p with an edge inside p, in index order) is solved and cut in
+    two -- median: the nsub // 2 smallest (value, index) pairs go to 2p;
+    sign: phi_2 < 0 goes to 2p -- and the vertices of p without an edge inside
+    p join the smaller half (2p on a tie).  vector(sub) returns the Fiedler
+    vector of a subgraph (sub has n, rowptr, col, w); by default the oracle's
+    own solve.  Returns (labels, number of vertices that were isolated in
+    their part at some round)."""
+    class Sub:
+        pass
+
+    if vector is None:
+        def vector(sub):
+            return Hierarchy(sub.n, sub.rowptr, sub.col, sub.w, n_coarse=n_coarse).solve(
+                **solve_kw).x
+
+    n = g.n
+    rp = np.asarray(g.rowptr, np.int64)
+    col = np.asarray(g.col, np.int64)
+    w = np.asarray(g.w, np.float64)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    levels = int(np.log2(parts))
+    part = np.zeros(n, np.int64)
+    n_iso = 0
+    for d in range(levels):
+        nxt = part.copy()
+        for p in range(2 ** d):
+            mask = part == p
+            inside = mask[rows] & mask[col]
+            deg = np.bincount(rows[inside], minlength=n)
+            inn = mask & (deg > 0)
+            iso = mask & (deg == 0)
+            n_iso += int(iso.sum())
+            orig = np.nonzero(inn)[0]
+            nsub = len(orig)
+            c0 = c1 = 0
+            if nsub >= 2:
+                newid = np.cumsum(inn) - inn
+                sub = Sub()
+                sub.n = nsub
+                sub.rowptr = np.concatenate([[0], np.cumsum(deg[orig])]).astype(np.int32)
+                sub.col = newid[col[inside]].astype(np.int32)
+                sub.w = w[inside].copy()
+                x = np.asarray(vector(sub), np.float64) + 0.0
+                child = np.ones(nsub, np.int64)
+                if cut == "median":
+                    order = np.lexsort((np.arange(nsub), x))
+                    child[order[:nsub // 2]] = 0
+                else:
+                    child[x < 0.0] = 0
+                c0 = int((child == 0).sum())
+                c1 = nsub - c0
+                nxt[orig] = 2 * p + child
+            nxt[iso] = 2 * p + (1 if c1 < c0 else 0)
+        part = nxt
+    return part.astype(np.int32), n_iso

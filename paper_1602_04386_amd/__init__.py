@@ -70,6 +70,16 @@ class fv_batch_opts(C.Structure):
                 ("replayed", C.c_int32), ("launch_ms", C.c_double)]
 
 
+class fv_partition_opts(C.Structure):
+    _fields_ = [("parts", C.c_int32), ("cut", C.c_int32)]
+
+
+class fv_partition_stats(C.Structure):
+    _fields_ = [("parts", C.c_int32), ("part_size_min", C.c_int32), ("part_size_max", C.c_int32),
+                ("solves", C.c_int32), ("not_converged", C.c_int32), ("cut_weight", C.c_double),
+                ("total_weight", C.c_double), ("t_ms", C.c_double)]
+
+
 class fv_server_opts(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("queue_capacity", C.c_int32),
                 ("hbm_budget_bytes", C.c_size_t), ("cache_hierarchies", C.c_int32),
@@ -90,7 +100,7 @@ EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
            "fv_context_destroy", "fv_build_hierarchy", "fv_hierarchy_info", "fv_hierarchy_bytes",
            "fv_hierarchy_export_level", "fv_free_hierarchy", "fv_fiedler_solve",
            "fv_fiedler_solve_noalloc", "fv_fiedler_solve_batch", "fv_fiedler_solve_batch_ex",
-           "fv_batch_opts_default", "fv_server_create", "fv_submit", "fv_poll",
+           "fv_batch_opts_default", "fv_spectral_partition", "fv_server_create", "fv_submit", "fv_poll",
            "fv_server_destroy", "fv_status_str"]
 
 _lib = None
@@ -136,6 +146,11 @@ def lib() -> C.CDLL:
                                                 C.POINTER(fv_batch_opts), vp, C.c_int32, vp, vp,
                                                 vp]
         L.fv_fiedler_solve_batch_ex.restype = C.c_int
+        L.fv_spectral_partition.argtypes = [vp, C.POINTER(fv_csr), C.POINTER(fv_hier_opts),
+                                            C.POINTER(fv_solve_opts),
+                                            C.POINTER(fv_partition_opts), vp, C.c_int32,
+                                            C.POINTER(fv_partition_stats)]
+        L.fv_spectral_partition.restype = C.c_int
         L.fv_batch_opts_default.argtypes = [C.POINTER(fv_batch_opts)]
         L.fv_batch_opts_default.restype = None
         L.fv_server_create.argtypes = [vp, C.POINTER(fv_server_opts), C.POINTER(vp)]
@@ -432,6 +447,25 @@ def fiedler_solve_batch(ctx: Context, hs: list, x_out=None, batch=None, **kw) ->
     del keep
     _check(st, "fv_fiedler_solve_batch")
     return [_stats_to_result(ist[k], xs[k], lam[k], stats[k]) for k in range(count)]
+
+
+# --- partitioning ---------------------------------------------------------------
+
+def spectral_partition(ctx: Context, g, parts: int = 2, cut: str = "median", n_coarse: int = 25,
+                       **solve_kw):
+    """fv_spectral_partition on graph g (adjacency CSR with n, rowptr, col, w);
+    returns (labels, stats dict)."""
+    csr, keep = _make_csr(g.n, g.rowptr, g.col, g.w, True)
+    ho = fv_hier_opts(n_coarse, FV_MAX_LEVELS, 0)
+    o, keep2 = solve_opts(**solve_kw)
+    po = fv_partition_opts(int(parts), {"median": 0, "sign": 1}[cut])
+    out = np.zeros(g.n, np.int32)
+    S = fv_partition_stats()
+    _check(lib().fv_spectral_partition(ctx.handle, C.byref(csr), C.byref(ho), C.byref(o),
+                                       C.byref(po), out.ctypes.data, 0, C.byref(S)),
+           "fv_spectral_partition")
+    del keep, keep2
+    return out, {k: getattr(S, k) for k, _ in S._fields_}
 
 
 # --- serving ----------------------------------------------------------------------

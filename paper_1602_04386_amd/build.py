@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfiedler.so")
-SOURCES = ["abi.cpp", "setup.hip", "solve.hip", "server.cpp"]
+SOURCES = ["abi.cpp", "setup.hip", "solve.hip", "server.cpp", "partition.hip"]
 
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

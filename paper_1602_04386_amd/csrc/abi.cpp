@@ -351,4 +351,27 @@ fv_status fv_fiedler_solve_batch_ex(fv_context* ctx, int32_t count,
   })
 }
 
+fv_status fv_spectral_partition(fv_context* ctx, const fv_csr* graph,
+                                const fv_hier_opts* hopts, const fv_solve_opts* sopts,
+                                const fv_partition_opts* popts, int32_t* part_out,
+                                int32_t part_on_device, fv_partition_stats* stats) {
+  if (!ctx || !graph || !popts || !part_out) return FV_E_INVALID;
+  if (popts->parts < 2 || (popts->parts & (popts->parts - 1)) || popts->cut < 0 ||
+      popts->cut > 1 || graph->n < 2)
+    return FV_E_INVALID;
+  fv_hier_opts ho;
+  fv_hier_opts_default(&ho);
+  if (hopts) ho = *hopts;
+  fv_solve_opts o;
+  fv_solve_opts_default(&o);
+  if (sopts) o = *sopts;
+  fv_status st = check_solve_opts(&o);
+  if (st != FV_OK) return st;
+  if (o.replay) return FV_E_INVALID;
+  FV_GUARD({
+    FV_HIP(hipSetDevice(ctx->device));
+    return fv::spectral_partition(ctx, graph, &ho, &o, popts, part_out, part_on_device, stats);
+  })
+}
+
 }  // extern "C"

@@ -232,6 +232,10 @@ fv_status solve_batch(fv_context* ctx, int count, const fv_hierarchy* const* h,
                       int x_on_device, double* lambda_out, fv_solve_stats* stats,
                       fv_status* item_status, hipStream_t s);
 void release_batch_graph(fv_context* ctx);
+// Recursive spectral bisection (partition.hip).
+fv_status spectral_partition(fv_context* ctx, const fv_csr* g, const fv_hier_opts* ho,
+                             const fv_solve_opts* so, const fv_partition_opts* po,
+                             int32_t* part_out, int part_on_device, fv_partition_stats* st);
 size_t solve_workspace_bytes(size_t nmax, int maxcol);
 
 // Algorithmic bytes of one refinement pass over a level.

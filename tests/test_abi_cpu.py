@@ -39,7 +39,9 @@ def test_ctypes_layouts_match_header(fv, tmp_path):
     structs = {"fv_csr": fv.fv_csr, "fv_hier_opts": fv.fv_hier_opts,
                "fv_solve_opts": fv.fv_solve_opts, "fv_solve_stats": fv.fv_solve_stats,
                "fv_server_opts": fv.fv_server_opts, "fv_request": fv.fv_request,
-               "fv_result": fv.fv_result, "fv_batch_opts": fv.fv_batch_opts}
+               "fv_result": fv.fv_result, "fv_batch_opts": fv.fv_batch_opts,
+               "fv_partition_opts": fv.fv_partition_opts,
+               "fv_partition_stats": fv.fv_partition_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fiedler.h"',
              "int main(void) {"]
     for name, cls in structs.items():
