@@ -173,7 +173,8 @@ class SolveParams(C.Structure):
                 ("max_coarsest", C.c_int32), ("gs_lexicographic", C.c_int32),
                 ("gs_unshifted", C.c_int32), ("omega", C.c_double),
                 ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32),
-                ("tol_coarse", C.c_double)]
+                ("tol_coarse", C.c_double), ("coarse_mass", C.c_int32), ("gs_rhs_y", C.c_int32),
+                ("lanczos_k", C.c_int32)]
 
 
 def _i32(a):
@@ -409,7 +410,13 @@ class Hierarchy:
 
     def solve(self, seed=1, tol_cos=1e-6, tol_res=0.0, max_gs=100, max_pi=100, max_outer=50,
               max_coarsest=100000, lexicographic=False, unshifted=False, omega=1.0,
-              replay=None, tol_coarse=1e-13) -> SolveResult:
+              replay=None, tol_coarse=1e-13, coarse_mass=False, rhs_y=False,
+              lanczos_k=0) -> SolveResult:
+        """Algorithm 3, Steps 2-3, then the finest Rayleigh quotient.  Variants
+        (oracle-only, for comparison): lexicographic (Algorithm 2's row
+        order), unshifted (the sweep on L x = 0), rhs_y (the sweep on L x = y),
+        coarse_mass (coarse problems L_c y = lambda M_c y), lanczos_k (k
+        Lanczos steps in place of each smoothing phase)."""
         n0 = self.level(0).n if self.nlevels else 0
         x = np.zeros(n0)
         scal = np.zeros(3)
@@ -418,7 +425,7 @@ class Hierarchy:
         clen = C.c_int32(0)
         P = SolveParams(seed, tol_cos, tol_res, max_gs, max_pi, max_outer, max_coarsest,
                         1 if lexicographic else 0, 1 if unshifted else 0, omega, None, 0,
-                        tol_coarse)
+                        tol_coarse, int(coarse_mass), int(rhs_y), int(lanczos_k))
         keep = None
         if replay is not None:
             keep = (C.c_int32 * len(replay))(*[int(v) for v in replay])

@@ -736,6 +736,7 @@ typedef struct {
   int32_t* colour; /* NULL on the coarsest */
   int32_t ncolours;
   double sigma;
+  double* mass;    /* aggregate sizes in finest vertices, M = I I^T; NULL on level 0 */
 } or_level;
 
 typedef struct {
@@ -752,6 +753,7 @@ void or_hier_free(void* hp) {
     free(h->lv[l].w);
     free(h->lv[l].q);
     free(h->lv[l].colour);
+    free(h->lv[l].mass);
   }
   free(h);
 }
@@ -824,6 +826,9 @@ void* or_hier_build_hec(int32_t n, const int32_t* rp, const int32_t* col, const 
     C->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(F->m > 0 ? F->m : 1));
     C->w = (double*)malloc(sizeof(double) * (size_t)(F->m > 0 ? F->m : 1));
     or_galerkin(F->n, F->rp, F->col, F->w, q, nc, C->rp, C->col, C->w, &C->m);
+    /* mass of an aggregate: the finest vertices it holds (M_{l+1} = I M_l I^T) */
+    C->mass = (double*)calloc((size_t)nc, sizeof(double));
+    for (int32_t i = 0; i < F->n; ++i) C->mass[q[i]] += F->mass ? F->mass[i] : 1.0;
     h->nlevels = l + 2;
     ++l;
   }
@@ -870,6 +875,11 @@ typedef struct {
   const int32_t* replay;    /* NULL, or the phase counts to execute exactly */
   int32_t replay_len;
   double tol_coarse;        /* coarsest stop: residual <= tol_coarse * sigma */
+  /* Variants of the smoother and of the coarse problems (oracle-only modes
+   * for comparison with the reading the library implements): */
+  int32_t coarse_mass;      /* 1: coarse levels solve L_c y = lambda M_c y, M_c = I I^T */
+  int32_t gs_rhs_y;         /* 1: the sweep solves L x = y with y the iterate before it */
+  int32_t lanczos_k;        /* > 0: each smoothing phase is k Lanczos steps on sigma I - L */
 } or_solve_params;
 
 /* Rayleigh quotient x^T L x / x^T x in the edge form of or_rq_residual. */
@@ -893,24 +903,180 @@ double or_rq_export(int32_t n, const int32_t* rp, const int32_t* col, const doub
   return or_rq(n, rp, col, w, x);
 }
 
+/* ---- mass-weighted coarse problems (variant): L_c y = lambda M_c y ---------
+ * M_c = I I^T is diagonal (aggregate sizes).  With it the coarse problem is the
+ * Ritz projection of the fine one onto the aggregates' indicator vectors.
+ * Inner products, means and norms are then M-weighted; m == NULL means M = I. */
+static double or_mw(const double* m, int32_t i) { return m ? m[i] : 1.0; }
+
+static double or_dot_m(int32_t n, const double* m, const double* a, const double* b) {
+  double s = 0.0;
+  for (int32_t i = 0; i < n; ++i) s += or_mw(m, i) * a[i] * b[i];
+  return s;
+}
+
+/* x <- (x - mu 1) / ||x - mu 1||_M with mu the M-weighted mean: the projection
+ * M-orthogonal to the null vector 1, then M-unit length. */
+static void or_project_normalise_m(int32_t n, const double* m, double* x) {
+  if (!m) { or_project_normalise(n, x); return; }
+  double s = 0.0, sm = 0.0;
+  for (int32_t i = 0; i < n; ++i) { s += m[i] * x[i]; sm += m[i]; }
+  const double mu = s / sm;
+  double nn = 0.0;
+  for (int32_t i = 0; i < n; ++i) { x[i] -= mu; nn += m[i] * x[i] * x[i]; }
+  const double inv = 1.0 / sqrt(nn);
+  for (int32_t i = 0; i < n; ++i) x[i] *= inv;
+}
+
+/* sigma_M = 2 max_i d_i / m_i bounds the spectrum of M^{-1} L (Gershgorin). */
+static double or_sigma_m(const or_level* L, const double* m) {
+  if (!m) return L->sigma;
+  double mx = 0.0;
+  for (int32_t i = 0; i < L->n; ++i) {
+    double d = 0.0;
+    for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) d += L->w[p];
+    if (d / m[i] > mx) mx = d / m[i];
+  }
+  return 2.0 * mx;
+}
+
+/* ---- Lanczos smoother (variant; the paper's conclusion names it) ----------
+ * k steps of Lanczos on B = sigma I - L restricted to the complement of 1,
+ * started from x, with full reorthogonalisation; x becomes the Ritz vector of
+ * the largest Ritz value (the approximation of phi_2).  The k x k tridiagonal
+ * eigenproblem is solved by cyclic Jacobi rotations (Golub & Van Loan, 8.5). */
+static void or_jacobi_eig(int32_t k, double* A, double* V) {
+  for (int32_t i = 0; i < k; ++i)
+    for (int32_t j = 0; j < k; ++j) V[i * k + j] = i == j ? 1.0 : 0.0;
+  for (int32_t sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int32_t i = 0; i < k; ++i)
+      for (int32_t j = i + 1; j < k; ++j) off += A[i * k + j] * A[i * k + j];
+    if (off < 1e-30) break;
+    for (int32_t p = 0; p < k; ++p)
+      for (int32_t q = p + 1; q < k; ++q) {
+        const double apq = A[p * k + q];
+        if (fabs(apq) < 1e-300) continue;
+        const double theta = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int32_t r = 0; r < k; ++r) {  /* A <- J^T A J, columns p and q */
+          const double arp = A[r * k + p], arq = A[r * k + q];
+          A[r * k + p] = c * arp - s * arq;
+          A[r * k + q] = s * arp + c * arq;
+        }
+        for (int32_t r = 0; r < k; ++r) {  /* rows p and q */
+          const double apr = A[p * k + r], aqr = A[q * k + r];
+          A[p * k + r] = c * apr - s * aqr;
+          A[q * k + r] = s * apr + c * aqr;
+        }
+        for (int32_t r = 0; r < k; ++r) {  /* V <- V J */
+          const double vrp = V[r * k + p], vrq = V[r * k + q];
+          V[r * k + p] = c * vrp - s * vrq;
+          V[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+}
+
+static int32_t or_lanczos_phase(const or_level* L, int32_t k, double* x) {
+  const int32_t n = L->n;
+  if (k > n - 1) k = n - 1;
+  if (k < 1) return 0;
+  double* Q = (double*)malloc(sizeof(double) * (size_t)n * (size_t)(k + 1));
+  double* T = (double*)calloc((size_t)k * (size_t)k, sizeof(double));
+  double* V = (double*)malloc(sizeof(double) * (size_t)k * (size_t)k);
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  or_project_normalise(n, x);
+  memcpy(Q, x, sizeof(double) * (size_t)n);
+  int32_t steps = 0;
+  for (int32_t j = 0; j < k; ++j) {
+    const double* qj = Q + (size_t)j * n;
+    or_pi_apply(n, L->rp, L->col, L->w, L->sigma, qj, z);
+    /* full reorthogonalisation against 1 and q_0 .. q_j, twice (Gram-Schmidt
+     * twice is enough, Giraud et al. 2005); alpha_j = q_j^T B q_j collects
+     * both passes' coefficients on q_j, beta_{j-1} is set with q_j */
+    for (int32_t pass = 0; pass < 2; ++pass) {
+      double mu = 0.0;
+      for (int32_t i = 0; i < n; ++i) mu += z[i];
+      mu /= (double)n;
+      for (int32_t i = 0; i < n; ++i) z[i] -= mu;
+      for (int32_t r = 0; r <= j; ++r) {
+        const double* qr = Q + (size_t)r * n;
+        const double h = or_dot(n, qr, z);
+        for (int32_t i = 0; i < n; ++i) z[i] -= h * qr[i];
+        if (r == j) T[j * k + j] += h;
+      }
+    }
+    steps = j + 1;
+    const double beta = sqrt(or_dot(n, z, z));
+    if (j + 1 == k || beta <= 1e-14 * L->sigma) break;
+    T[j * k + j + 1] = T[(j + 1) * k + j] = beta;
+    double* qn = Q + (size_t)(j + 1) * n;
+    for (int32_t i = 0; i < n; ++i) qn[i] = z[i] / beta;
+  }
+  /* top Ritz pair of the leading steps x steps block */
+  double* A = (double*)malloc(sizeof(double) * (size_t)steps * (size_t)steps);
+  for (int32_t i = 0; i < steps; ++i)
+    for (int32_t j = 0; j < steps; ++j) A[i * steps + j] = T[i * k + j];
+  or_jacobi_eig(steps, A, V);
+  int32_t best = 0;
+  for (int32_t i = 1; i < steps; ++i) if (A[i * steps + i] > A[best * steps + best]) best = i;
+  for (int32_t i = 0; i < n; ++i) {
+    double v = 0.0;
+    for (int32_t r = 0; r < steps; ++r) v += Q[(size_t)r * n + i] * V[r * steps + best];
+    x[i] = v;
+  }
+  or_project_normalise(n, x);
+  free(A);
+  free(Q);
+  free(T);
+  free(V);
+  free(z);
+  return steps;
+}
+
 /* One smoothing phase: each sweep takes the Rayleigh quotient of the current
  * (unit, mean-free) iterate as its shift; sweeps continue until the cosine
  * test passes or the cap. */
 static int32_t or_gs_phase(const or_level* L, const or_solve_params* P, int32_t forced,
                            double* x, double* xp, double* cos_out) {
+  const double* m = P->coarse_mass ? L->mass : NULL;
+  if (P->lanczos_k > 0) {
+    /* variant: one Lanczos phase in place of the sweeps */
+    memcpy(xp, x, sizeof(double) * (size_t)L->n);
+    const int32_t k = or_lanczos_phase(L, forced >= 0 ? forced : P->lanczos_k, x);
+    *cos_out = or_dot(L->n, x, xp);
+    return k;
+  }
   int32_t k = 0;
   double c = 0.0;
   for (;;) {
     if (k >= (forced >= 0 ? forced : P->max_gs)) break;
     memcpy(xp, x, sizeof(double) * (size_t)L->n);
     double rho = P->gs_unshifted ? 0.0 : or_rq(L->n, L->rp, L->col, L->w, x);
-    if (P->gs_lexicographic)
+    if (m) rho *= or_dot(L->n, x, x) / or_dot_m(L->n, m, x, x);  /* x^T L x / x^T M x */
+    if (P->gs_lexicographic) {
       or_gs_sweep_lex(L->n, L->rp, L->col, L->w, rho, x);
-    else
+    } else if (m || P->gs_rhs_y) {
+      /* the sweep on (L - rho M) x = 0 (mass-weighted) or on L x = y */
+      for (int32_t cc = 0; cc < L->ncolours; ++cc)
+        for (int32_t i = 0; i < L->n; ++i) {
+          if (L->colour[i] != cc) continue;
+          double num = 0.0, den = 0.0;
+          for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) { num += L->w[p] * x[L->col[p]]; den += L->w[p]; }
+          if (den > 0.0) {
+            const double b = P->gs_rhs_y ? xp[i] : rho * or_mw(m, i) * x[i];
+            const double g = (num + b) / den;
+            x[i] = P->omega == 1.0 ? g : (1.0 - P->omega) * x[i] + P->omega * g;
+          }
+        }
+    } else {
       or_gs_sweep(L->n, L->rp, L->col, L->w, L->colour, L->ncolours, rho, P->omega, x);
-    or_project_normalise(L->n, x);
+    }
+    or_project_normalise_m(L->n, m, x);
     ++k;
-    c = or_dot(L->n, x, xp);
+    c = or_dot_m(L->n, m, x, xp);
     if (forced < 0 && c > 1.0 - P->tol_cos) break;
   }
   *cos_out = c;
@@ -920,14 +1086,19 @@ static int32_t or_gs_phase(const or_level* L, const or_solve_params* P, int32_t 
 /* One power-iteration phase on B = sigma I - L (projected). */
 static int32_t or_pi_phase(const or_level* L, const or_solve_params* P, int32_t forced,
                            double* x, double* y, double* cos_out) {
+  const double* m = P->coarse_mass ? L->mass : NULL;
+  const double sig = or_sigma_m(L, m);
   int32_t k = 0;
   double c = 0.0;
   for (;;) {
     if (k >= (forced >= 0 ? forced : P->max_pi)) break;
-    or_pi_apply(L->n, L->rp, L->col, L->w, L->sigma, x, y);
-    or_project_normalise(L->n, y);
+    if (m) /* y = sigma x - M^{-1} L x */
+      for (int32_t i = 0; i < L->n; ++i) y[i] = sig * x[i] - or_lap_row(L->rp, L->col, L->w, x, i) / m[i];
+    else
+      or_pi_apply(L->n, L->rp, L->col, L->w, L->sigma, x, y);
+    or_project_normalise_m(L->n, m, y);
     ++k;
-    c = or_dot(L->n, x, y);
+    c = or_dot_m(L->n, m, x, y);
     memcpy(x, y, sizeof(double) * (size_t)L->n);
     if (forced < 0 && c > 1.0 - P->tol_cos) break;
   }
@@ -970,8 +1141,33 @@ int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double
 #define OR_PUSH(v) do { if (nc_out < counts_cap) counts[nc_out] = (v); ++nc_out; } while (0)
   const or_level* C = &h->lv[J];
   int32_t conv = 0;
-  int32_t cit = or_coarsest(C->n, C->rp, C->col, C->w, C->sigma, P->seed, P->max_coarsest,
-                            OR_NEXT_FORCED(), P->tol_coarse, x, &conv);
+  int32_t cit;
+  if (P->coarse_mass && C->mass) {
+    /* variant: power iteration on sigma I - M^{-1} L, M-projected, until the
+     * M^{-1}-norm residual ||M^{-1} L x - rho x||_M <= tol_coarse sigma */
+    const double sig = or_sigma_m(C, C->mass);
+    const int32_t forced = OR_NEXT_FORCED();
+    or_random_start(C->n, P->seed, x);
+    or_project_normalise_m(C->n, C->mass, x);
+    for (cit = 0;; ++cit) {
+      for (int32_t i = 0; i < C->n; ++i) t[i] = or_lap_row(C->rp, C->col, C->w, x, i) / C->mass[i];
+      if (forced >= 0) {
+        if (cit >= forced) { conv = 1; break; }
+      } else {
+        const double rho = or_dot_m(C->n, C->mass, x, t);
+        double r2 = 0.0;
+        for (int32_t i = 0; i < C->n; ++i) { const double r = t[i] - rho * x[i]; r2 += C->mass[i] * r * r; }
+        if (sqrt(r2) <= P->tol_coarse * sig) { conv = 1; break; }
+        if (cit >= P->max_coarsest) break;
+      }
+      for (int32_t i = 0; i < C->n; ++i) y[i] = sig * x[i] - t[i];
+      or_project_normalise_m(C->n, C->mass, y);
+      memcpy(x, y, sizeof(double) * (size_t)C->n);
+    }
+  } else {
+    cit = or_coarsest(C->n, C->rp, C->col, C->w, C->sigma, P->seed, P->max_coarsest,
+                      OR_NEXT_FORCED(), P->tol_coarse, x, &conv);
+  }
   if (!conv) status = OR_E_NOT_CONVERGED;
   OR_PUSH(cit);
   double cosv = 1.0;
@@ -980,7 +1176,7 @@ int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double
     /* prolongation y^l = I^T y^{l+1}: x_f[i] = x_c[q(i)] */
     for (int32_t i = 0; i < F->n; ++i) y[i] = x[F->q[i]];
     memcpy(x, y, sizeof(double) * (size_t)F->n);
-    or_project_normalise(F->n, x);
+    or_project_normalise_m(F->n, P->coarse_mass ? F->mass : NULL, x);
     int32_t g = or_gs_phase(F, P, OR_NEXT_FORCED(), x, t, &cosv);
     int32_t p = or_pi_phase(F, P, OR_NEXT_FORCED(), x, y, &cosv);
     OR_PUSH(g);

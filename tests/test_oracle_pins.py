@@ -768,3 +768,80 @@ def test_randomised_hec_hierarchy_solves_grid(orc):
     r = h.solve(seed=1, tol_cos=1e-12, tol_res=1e-10, max_gs=2000, max_pi=20, max_outer=5000)
     lam = 2 - 2 * math.cos(math.pi / 20)
     assert r.status == 0 and abs(r.lam - lam) <= 1e-9 * lam
+
+
+# ------------------------------------------- smoother and coarse-problem variants --
+
+def _eig2(g):
+    W = dense_W(g.n, g.rowptr, g.col, g.w)
+    L = np.diag(W.sum(1)) - W
+    vals, vecs = np.linalg.eigh(L)
+    return vals, vecs
+
+
+@pytest.mark.parametrize("variant", [dict(coarse_mass=True), dict(lanczos_k=8),
+                                     dict(max_gs=0, max_pi=400)])
+@pytest.mark.parametrize("seed", [3, 4])
+def test_variants_reach_lambda_2(orc, variant, seed):
+    """Every oracle variant of the smoother or the coarse problems, run to a
+    tight residual, ends at lambda_2 of a random 64-vertex graph (numpy eigh),
+    its vector within the Kato-Temple-style angle bound."""
+    g = gen.random_connected(64, 800 + seed)
+    vals, vecs = _eig2(g)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=6)
+    kw = dict(seed=1, tol_cos=1e-14, tol_res=1e-10, max_gs=400, max_pi=5, max_outer=20000)
+    kw.update(variant)
+    r = h.solve(**kw)
+    assert r.status == 0 and r.residual <= 1e-10
+    gap = vals[2] - vals[1]
+    assert abs(r.lam - vals[1]) <= r.residual ** 2 / gap * 1.01 + 1e-14
+    assert 1 - abs(float(r.x @ vecs[:, 1])) <= (r.residual / gap) ** 2 + 1e-12
+
+
+def test_lanczos_phase_exact_in_full_krylov_space(orc):
+    """n - 1 Lanczos steps span the whole complement of 1, so the top Ritz
+    vector of sigma I - L is phi_2 exactly (random 30-vertex graph)."""
+    g = gen.random_connected(30, 812)
+    vals, vecs = _eig2(g)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=2)
+    # one level above the coarsest: replay a single Lanczos phase of n-1 steps
+    # on level 0 after the cascade, then compare
+    J = h.nlevels - 1
+    r = h.solve(seed=1, lanczos_k=29, replay=[0] + [0, 0] * (J - 1) + [29, 0])
+    assert 1 - abs(float(r.x @ vecs[:, 1])) <= 1e-10
+    assert abs(r.lam - vals[1]) <= 1e-10 * vals[1]
+
+
+def test_mass_weighted_coarse_problem_is_ritz_projection(orc):
+    """On one coarsening, the mass-weighted coarse problem's smallest nonzero
+    eigenvalue equals the Ritz value of L on the aggregates' indicator vectors
+    (min over y of (I^T y)^T L (I^T y) / (I^T y)^T (I^T y)), and its masses are
+    the aggregate sizes."""
+    import scipy.linalg as sl
+
+    g = gen.random_connected(40, 813)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=30)
+    L0, L1 = h.level(0), h.level(1)
+    P = np.zeros((L0.n, L1.n))
+    P[np.arange(L0.n), L0.q] = 1.0
+    W = dense_W(g.n, g.rowptr, g.col, g.w)
+    L = np.diag(W.sum(1)) - W
+    ritz = sl.eigh(P.T @ L @ P, P.T @ P, eigvals_only=True)
+    Wc = dense_W(L1.n, L1.rowptr, L1.col, L1.w)
+    Lc = np.diag(Wc.sum(1)) - Wc
+    M = np.diag(np.bincount(L0.q, minlength=L1.n).astype(float))
+    gen_vals = sl.eigh(Lc, M, eigvals_only=True)
+    assert np.allclose(gen_vals, ritz, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_rhs_y_reading_does_not_converge(orc, seed):
+    """The reading of Algorithm 3's GS(L, y) with right-hand side b = y (the
+    iterate before the sweep) has the fixed points of (L - I) x = 0, not
+    phi_2: on the same graphs as above it stalls with a residual above 1e-2,
+    which is why the library's sweep takes the Rayleigh shift instead."""
+    g = gen.random_connected(64, 800 + seed)
+    h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=6)
+    r = h.solve(seed=1, tol_cos=1e-14, tol_res=1e-10, max_gs=400, max_pi=5, max_outer=2000,
+                rhs_y=True)
+    assert r.status == orc.E_NOT_CONVERGED and r.residual > 1e-2
