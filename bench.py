@@ -79,13 +79,13 @@ def pass_bytes(n, m, prec):
     return (8 * m + 4 * (n + 1) + 8 * n) if prec == "fp32" else (12 * m + 4 * (n + 1) + 16 * n)
 
 
-def measured_traffic(prec):
-    """HBM bytes per level-0 colour launch of the default workload, from the
+def measured_traffic(prec, name):
+    """HBM bytes per level-0 colour launch of workload `name`, from the
     calibrated FETCH_SIZE / WRITE_SIZE passes summarised in profiles/; None when
     the kernel sources changed since those counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_gs_tile_grid1024x1000_fp32_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_gs_tile_{name}_fp32_traffic.json")
     if prec != "fp32" or not os.path.exists(path):
         return None
     with open(path) as f:
@@ -97,7 +97,7 @@ def measured_traffic(prec):
     return rec["traffic_bytes"] if sha.hexdigest() == rec["source_sha256"] else None
 
 
-def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name):
+def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name, traffic_name=None):
     """Device time of one level-0 sweep from two replayed schedules that differ
     only in the number of level-0 sweeps (HIP events inside the library)."""
     import numpy as np
@@ -114,7 +114,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name):
 
     t_a, t_b = dev_ms(S0), dev_ms(S1)
     log(f"roofline replays: {S0} sweeps {t_a:.3f} ms, {S1} sweeps {t_b:.3f} ms")
-    traffic = measured_traffic(prec) if h.n[0] == 1024000 else None
+    traffic = measured_traffic(prec, traffic_name) if traffic_name else None
     t_sweep_ms = (t_b - t_a) / (S1 - S0)
     n0, m0 = h.n[0], h.nnz[0]
     # Colour launches per sweep: the last colours, when they hold at most 512
@@ -172,7 +172,7 @@ def timed_steps(fv, ctx, g, dev_in, x, prec, solve, steps, warmup):
 
 
 def single_graph(args, g, solve, metric, workload, cpu_fn, require_converged=True,
-                 paper_leg=None):
+                 paper_leg=None, traffic_name=None):
     """Timed steps of setup + solve on one device-resident graph."""
     import numpy as np
 
@@ -201,7 +201,8 @@ def single_graph(args, g, solve, metric, workload, cpu_fn, require_converged=Tru
     fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, **solve)
     t_solve = (time.perf_counter() - ts) * 1e3
     J = h.levels - 1
-    roof = level0_roofline(fv, ctx, h, x, args.prec, args.roofline_sweeps, "k_gs_tile")
+    roof = level0_roofline(fv, ctx, h, x, args.prec, args.roofline_sweeps, "k_gs_tile",
+                           traffic_name)
     h.free()
 
     # The same steps in the other precision, timed exactly as the headline.
@@ -327,7 +328,7 @@ def run_grid(args):
     return single_graph(
         args, g, SOLVE, "Fiedler solves/s at residual<=1e-6 (grid 1024x1000, setup+solve)",
         "grid 1024x1000, weights iid U[0.5,1.5] (SplitMix64 seed 2), n=1024000, nnz=4091952", cpu,
-        paper_leg=GS_SOLVE)
+        paper_leg=GS_SOLVE, traffic_name="grid1024x1000")
 
 
 def run_rgg(args):
@@ -365,7 +366,7 @@ def run_rgg(args):
         "Fiedler solves/s (RGG 4M, setup + cascade + <=20 finest rounds; residual reported)",
         f"random geometric graph, 4M points in the unit square, r=sqrt(8/(pi n)), weights "
         f"exp(-d^2/r^2), largest component n={g.n}, nnz={len(g.col)} (SplitMix64 seed 3)", cpu,
-        require_converged=False)
+        require_converged=False, traffic_name="rgg4m")
 
 
 def run_batch(args):
@@ -865,7 +866,7 @@ def run_counters_probe(args):
     dst = DeviceArray(dtype=np.uint8, count=nbytes)
     hip().hipMemcpy(C_void(dst.data_ptr()), C_void(src.data_ptr()), nbytes, 3)  # D2D
     hip().hipDeviceSynchronize()
-    g = gen.grid_1024x1000()
+    g = gen.rgg_4m() if args.workload == "rgg" else gen.grid_1024x1000()
     ctx = fv.Context(0)
     rp, col, w = DeviceArray(g.rowptr), DeviceArray(g.col), DeviceArray(g.w)
     x = DeviceArray(dtype=np.float64, count=g.n)
@@ -873,7 +874,8 @@ def run_counters_probe(args):
     J = h.levels - 1
     r = fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, seed=1, omega=SOLVE["omega"],
                          replay=[0] + [0, 0] * (J - 1) + [args.probe_sweeps, 0])
-    out = {"probe": "counters", "copy_bytes": nbytes, "level0_sweeps": args.probe_sweeps,
+    out = {"probe": "counters", "workload": args.workload, "copy_bytes": nbytes,
+           "level0_sweeps": args.probe_sweeps,
            "level0_colours": h.colours[0], "bytes_per_sweep": pass_bytes(h.n[0], h.nnz[0], args.prec),
            "level0_rows": h.n[0], "level0_nnz": h.nnz[0], "t_solve_ms": r.t_solve_ms}
     h.free()
