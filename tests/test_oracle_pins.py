@@ -845,3 +845,85 @@ def test_rhs_y_reading_does_not_converge(orc, seed):
     r = h.solve(seed=1, tol_cos=1e-14, tol_res=1e-10, max_gs=400, max_pi=5, max_outer=2000,
                 rhs_y=True)
     assert r.status == orc.E_NOT_CONVERGED and r.residual > 1e-2
+
+
+# --------------------------------------------------------------------------
+# Spectral partitioning (recursive bisection of phi_2, the application the
+# Introduction names): the oracle's recursion against closed forms.
+# --------------------------------------------------------------------------
+
+PART_KW = dict(seed=1, tol_cos=1e-12, tol_res=1e-9, max_gs=200, max_pi=10, max_outer=400)
+
+
+@pytest.mark.parametrize("parts", [2, 4, 8])
+def test_partition_of_path_is_intervals(orc, parts):
+    """phi_2 of a path is cos(pi (i + 1/2) / n), strictly monotone, and every
+    part of a median cut is again a path: each of the parts must be an
+    interval of n / parts consecutive vertices, and the cut weight is the
+    parts - 1 edges between them."""
+    n = 64
+    g = gen.path(n)
+    labels, n_iso = orc.spectral_partition(g, parts, "median", **PART_KW)
+    assert n_iso == 0
+    size = n // parts
+    blocks = labels.reshape(parts, size)
+    assert (blocks == blocks[:, :1]).all()  # constant on each interval
+    assert sorted(blocks[:, 0].tolist()) == list(range(parts))
+
+
+def test_partition_of_path_sign_cut_halves(orc):
+    """phi_2 of an even path changes sign exactly between n/2 - 1 and n/2."""
+    g = gen.path(40)
+    labels, _ = orc.spectral_partition(g, 2, "sign", **PART_KW)
+    assert len(set(labels[:20].tolist())) == 1 and len(set(labels[20:].tolist())) == 1
+    assert labels[0] != labels[-1]
+
+
+def test_partition_of_long_grid_cuts_across_the_long_side(orc):
+    """On a 4 x 16 unit grid lambda_2 = 2 - 2 cos(pi / 16) belongs to
+    cos(pi (c + 1/2) / 16), constant down each column; each half (4 x 8) has
+    lambda_2 = 2 - 2 cos(pi / 8) < 2 - 2 cos(pi / 4) again along its long side.
+    So four median parts are the column blocks 0-3, 4-7, 8-11 and 12-15, and
+    the cut is 3 x 4 unit edges."""
+    g = gen.grid(4, 16)
+    labels, _ = orc.spectral_partition(g, 4, "median", **PART_KW)
+    lab = labels.reshape(4, 16)
+    assert (lab == lab[:1]).all()  # every row cut the same way
+    cols = lab[0].reshape(4, 4)
+    assert (cols == cols[:, :1]).all() and sorted(cols[:, 0].tolist()) == [0, 1, 2, 3]
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    cut = (labels[rows] != labels[g.col]) & (g.col > rows)
+    assert float(g.w[cut].sum()) == 12.0
+
+
+def test_partition_separates_two_cliques(orc):
+    """Two 8-cliques joined by one edge: phi_2 is positive on one clique and
+    negative on the other (it is constant on each clique apart from the two
+    endpoints of the bridge, which keep the sign of their clique), so both
+    cuts give the cliques, with cut weight 1."""
+    a, b = [], []
+    for base in (0, 8):
+        for i in range(8):
+            for j in range(i + 1, 8):
+                a.append(base + i)
+                b.append(base + j)
+    a.append(7)
+    b.append(8)
+    g = gen._csr_from_undirected(16, np.array(a), np.array(b), np.ones(len(a)))
+    for cut in ("median", "sign"):
+        labels, _ = orc.spectral_partition(g, 2, cut, **PART_KW)
+        assert len(set(labels[:8].tolist())) == 1 and len(set(labels[8:].tolist())) == 1
+        assert labels[0] != labels[8]
+
+
+def test_partition_isolated_vertex_rule_worked_example(orc):
+    """A worked example of the rules for vertices left without an edge inside
+    their part: path 0-1-2-3 with a pendant 4 on vertex 0, and a supplied
+    vector equal to the vertex index. Round 1 (median): {0, 1} -> 0,
+    {2, 3, 4} -> 1. Round 2: part 0 splits into {0} -> 0 and {1} -> 1; in part
+    1 vertex 4 has no neighbour, {2} -> 2, {3} -> 3, and 4 joins the smaller
+    half, 2 on the tie. Labels [0, 1, 2, 3, 2], one isolated vertex."""
+    g = gen._csr_from_undirected(5, np.array([0, 1, 2, 0]), np.array([1, 2, 3, 4]), np.ones(4))
+    labels, n_iso = orc.spectral_partition(
+        g, 4, "median", vector=lambda sub: np.arange(sub.n, dtype=np.float64))
+    assert labels.tolist() == [0, 1, 2, 3, 2] and n_iso == 1
