@@ -66,6 +66,11 @@ GS_SOLVE = dict(SOLVE, omega=1.0, tol_cos=0.0, max_gs=100, max_pi=2)
 # with the residual just above 1e-6 (454 of 526 sampled grids reach it in 200
 # rounds); at 1.95 all of them do, in 7 to 15 rounds.
 BATCH_SOLVE = dict(SOLVE, omega=1.95, max_outer=200)
+# Recursive bisection of the 1024 x 1000 grid: its quarters (512 x 500) are
+# nearly square; at SOR factor 1.9 the FP64 oracle needs 82 to 336 finest
+# rounds on three of them and stalls at 1.005e-6 on the fourth, at 1.95 every
+# cut of the 8-way recursion converges within 23 rounds.
+PARTITION_SOLVE = dict(SOLVE, omega=1.95)
 N_COARSE = 25
 
 
@@ -810,7 +815,7 @@ def run_partition(args):
 
     g = gen.grid_1024x1000()
     ctx = fv.Context(0)
-    kw = dict(SOLVE, prec=args.prec)
+    kw = dict(PARTITION_SOLVE, prec=args.prec)
     for _ in range(args.warmup):
         fv.spectral_partition(ctx, g, parts=args.parts, **kw)
     times, st = [], None
@@ -829,7 +834,7 @@ def run_partition(args):
         "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32-mixed" if args.prec == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": "grid 1024x1000, weights iid U[0.5,1.5] (SplitMix64 seed 2)",
-                   "parts": args.parts, "cut": "median", "solve": SOLVE},
+                   "parts": args.parts, "cut": "median", "solve": PARTITION_SOLVE},
         "cut_ratio": st["cut_weight"] / st["total_weight"],
         "part_sizes": [st["part_size_min"], st["part_size_max"]],
         "solves": st["solves"], "not_converged": st["not_converged"],
@@ -837,7 +842,7 @@ def run_partition(args):
     if not args.no_cpu:
         oracle, host = oracle_native()
         t = time.perf_counter()
-        ref, _ = oracle.spectral_partition(g, args.parts, "median", **SOLVE)
+        ref, _ = oracle.spectral_partition(g, args.parts, "median", **PARTITION_SOLVE)
         t_cpu = time.perf_counter() - t
         rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
         m = (ref[rows] != ref[g.col]) & (g.col > rows)
