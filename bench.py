@@ -390,15 +390,34 @@ def run_batch(args):
     dev = [(DeviceArray(g.rowptr), DeviceArray(g.col), DeviceArray(g.w)) for g in graphs]
     xs = [DeviceArray(dtype=np.float64, count=g.n) for g in graphs]
     hip().hipDeviceSynchronize()
+
+    class DevGraph:
+        def __init__(self, n, d):
+            self.n, (self.rowptr, self.col, self.w) = n, d
+
+    dgs = [DevGraph(g.n, d) for g, d in zip(graphs, dev)]
+    # one build after another (fv_build_hierarchy) on the first 256 graphs,
+    # for comparison with the concurrent builds below
+    n_seq = min(256, len(dgs))
+    t = time.perf_counter()
+    for dg in dgs[:n_seq]:
+        fv.build_hierarchy(ctx, dg.n, dg.rowptr, dg.col, dg.w, is_adjacency=True,
+                           n_coarse=N_COARSE).free()
+    t_seq = time.perf_counter() - t
+    log(f"sequential builds: {n_seq} in {t_seq:.2f} s")
+    # every hierarchy: fv_build_hierarchies, concurrent host threads and streams
     t = time.perf_counter()
     hs = []
-    for g, d in zip(graphs, dev):
-        hs.append(fv.build_hierarchy(ctx, g.n, *d, is_adjacency=True, n_coarse=N_COARSE))
-        if len(hs) % 512 == 0:
-            log(f"  built {len(hs)} hierarchies in {time.perf_counter() - t:.1f} s")
+    for k in range(0, len(dgs), 512):
+        part, st = fv.build_hierarchies(ctx, dgs[k:k + 512], threads=args.build_threads,
+                                        n_coarse=N_COARSE)
+        if any(v != 0 for v in st):
+            raise RuntimeError(f"build failed: {sorted(set(st))}")
+        hs += part
+        log(f"  built {len(hs)} hierarchies in {time.perf_counter() - t:.1f} s")
     hip().hipDeviceSynchronize()
     t_setup = time.perf_counter() - t
-    log(f"setup of {len(hs)} hierarchies: {t_setup:.2f} s")
+    log(f"setup of {len(hs)} hierarchies: {t_setup:.2f} s ({args.build_threads} threads)")
 
     # Warm-up: the autotuner picks the launch configuration for this batch's
     # size class (timing each candidate on a sample of the batch).
@@ -481,6 +500,8 @@ def run_batch(args):
                         f"grids U[0.5,1.5], half Erdos-Renyi G(n, 6/(n-1)) largest components "
                         f"U[0.5,1.5]; sum n={sum(g.n for g in graphs)}",
             "solve": solve, "setup_s": round(t_setup, 3),
+            "setup_threads": args.build_threads,
+            "setup_sequential_s_per_graph": round(t_seq / max(n_seq, 1), 5),
         },
         "per_graph_fp64": {"value": round(rate64, 2), "unit": "solves/s",
                            "sample": f"every {args.loop_stride}th graph ({len(sub)} graphs)",
@@ -913,6 +934,8 @@ def main():
     ap.add_argument("--roofline-sweeps", type=int, default=200)
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--loop-stride", type=int, default=8)
+    ap.add_argument("--build-threads", type=int, default=8,
+                    help="batch: host threads of the concurrent hierarchy builds")
     ap.add_argument("--pool", type=int, default=32)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=10.0)

@@ -160,6 +160,19 @@ void fv_context_destroy(fv_context* ctx);
 fv_status fv_build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opts* opts,
                              fv_hierarchy** out);
 
+/* The setup phase of fv_build_hierarchy for many graphs at once (the batched
+ * solve's inputs): `threads` host threads (<= 0: up to 8), each with its own
+ * HIP stream, build graphs[0 .. count) concurrently, so the latency-bound
+ * setup rounds of different graphs overlap on the device.  out[i] receives
+ * graph i's hierarchy, exactly the one fv_build_hierarchy builds, or NULL
+ * when its build failed; item_status[i] (may be NULL) its status.  Every
+ * hierarchy is complete on the device when the call returns.  Returns FV_OK
+ * when every graph was built, else the status of the first failed graph (in
+ * index order); FV_E_INVALID for a NULL ctx, graphs or out, or count < 0. */
+fv_status fv_build_hierarchies(fv_context* ctx, int32_t count, const fv_csr* const* graphs,
+                               const fv_hier_opts* opts, int32_t threads, fv_hierarchy** out,
+                               fv_status* item_status);
+
 /* Level count and per-level sizes (arrays of FV_MAX_LEVELS entries, any may be
  * NULL): vertices, stored off-diagonal entries, colours, shift sigma. */
 fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz,

@@ -97,7 +97,7 @@ class fv_result(C.Structure):
 
 
 EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
-           "fv_context_destroy", "fv_build_hierarchy", "fv_hierarchy_info", "fv_hierarchy_bytes",
+           "fv_context_destroy", "fv_build_hierarchy", "fv_build_hierarchies", "fv_hierarchy_info", "fv_hierarchy_bytes",
            "fv_hierarchy_export_level", "fv_free_hierarchy", "fv_fiedler_solve",
            "fv_fiedler_solve_noalloc", "fv_fiedler_solve_batch", "fv_fiedler_solve_batch_ex",
            "fv_batch_opts_default", "fv_spectral_partition", "fv_server_create", "fv_submit", "fv_poll",
@@ -126,6 +126,10 @@ def lib() -> C.CDLL:
         L.fv_build_hierarchy.argtypes = [vp, C.POINTER(fv_csr), C.POINTER(fv_hier_opts),
                                          C.POINTER(vp)]
         L.fv_build_hierarchy.restype = C.c_int
+        L.fv_build_hierarchies.argtypes = [vp, C.c_int32, C.POINTER(C.POINTER(fv_csr)),
+                                           C.POINTER(fv_hier_opts), C.c_int32, C.POINTER(vp),
+                                           C.POINTER(C.c_int)]
+        L.fv_build_hierarchies.restype = C.c_int
         L.fv_hierarchy_info.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fv_hierarchy_info.restype = C.c_int
         L.fv_hierarchy_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -330,6 +334,27 @@ def build_hierarchy(ctx: Context, n: int, rowptr, col, val, is_adjacency: bool =
 
 def build_hierarchy_graph(ctx: Context, g, **kw) -> Hierarchy:
     return build_hierarchy(ctx, g.n, g.rowptr, g.col, g.w, True, **kw)
+
+
+def build_hierarchies(ctx: Context, graphs, threads: int = 0, n_coarse: int = 25,
+                      max_levels: int = FV_MAX_LEVELS, colour_seed: int = 0):
+    """fv_build_hierarchies: the setup phase for many adjacency graphs (objects
+    with n, rowptr, col, w) on concurrent host threads and streams.  Returns
+    (hierarchies, statuses): a Hierarchy or None per graph, and its status."""
+    count = len(graphs)
+    csrs, keep = [], []
+    for g in graphs:
+        c, k = _make_csr(g.n, g.rowptr, g.col, g.w, True)
+        csrs.append(c)
+        keep.append(k)
+    ptrs = (C.POINTER(fv_csr) * max(count, 1))(*[C.pointer(c) for c in csrs])
+    out = (C.c_void_p * max(count, 1))()
+    st = (C.c_int * max(count, 1))()
+    opts = fv_hier_opts(n_coarse, max_levels, colour_seed)
+    lib().fv_build_hierarchies(ctx.handle, count, ptrs, C.byref(opts), int(threads), out, st)
+    del keep
+    hs = [Hierarchy(ctx, C.c_void_p(out[i])) if out[i] else None for i in range(count)]
+    return hs, [int(st[i]) for i in range(count)]
 
 
 # --- solve ----------------------------------------------------------------------

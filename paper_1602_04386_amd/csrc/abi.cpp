@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "fv_internal.h"
 
@@ -84,6 +86,39 @@ void block_trim(fv_context* ctx) {
     ctx->cached = 0;
   }
   for (auto& kv : drop) (void)hipFree(kv.second);
+}
+
+void* pin_get(fv_context* ctx) {
+  {
+    std::lock_guard<std::mutex> g(ctx->pin_mu);
+    if (!ctx->pins.empty()) {
+      void* p = ctx->pins.back();
+      ctx->pins.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(FV_E_NOMEM, "pinned host allocation failed");
+  }
+  return p;
+}
+
+void pin_put(fv_context* ctx, void* p, hipStream_t s) {
+  if (!p) return;
+  (void)hipStreamSynchronize(s);
+  std::lock_guard<std::mutex> g(ctx->pin_mu);
+  ctx->pins.push_back(p);
+}
+
+void pin_trim(fv_context* ctx) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(ctx->pin_mu);
+    drop.swap(ctx->pins);
+  }
+  for (void* p : drop) (void)hipHostFree(p);
 }
 
 void* dev_alloc(fv_context* ctx, size_t bytes, size_t* counter) {
@@ -205,6 +240,7 @@ void fv_context_destroy(fv_context* c) {
   fv::release_batch_graph(c);
   fv::release_scratch(c, c->scratch);
   fv::block_trim(c);
+  fv::pin_trim(c);
   (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -221,6 +257,67 @@ fv_status fv_build_hierarchy(fv_context* ctx, const fv_csr* L, const fv_hier_opt
     *out = fv::build_hierarchy(ctx, L, &o, ctx->stream);
     return FV_OK;
   })
+}
+
+fv_status fv_build_hierarchies(fv_context* ctx, int32_t count, const fv_csr* const* graphs,
+                               const fv_hier_opts* opts, int32_t threads, fv_hierarchy** out,
+                               fv_status* item_status) {
+  if (!ctx || count < 0 || (count > 0 && (!graphs || !out))) return FV_E_INVALID;
+  fv_hier_opts o;
+  fv_hier_opts_default(&o);
+  if (opts) o = *opts;
+  std::vector<fv_status> st(count, FV_OK);
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  int nt = threads > 0 ? threads : 8;
+  nt = std::max(1, std::min(nt, count));
+  std::atomic<int> next{0};
+  auto work = [&] {
+    fv_status ts = FV_OK;
+    hipStream_t s = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      ts = FV_E_DEVICE;
+    }
+    for (int i = next++; i < count; i = next++) {
+      if (ts != FV_OK) {
+        st[i] = ts;
+        continue;
+      }
+      try {
+        out[i] = fv::build_hierarchy(ctx, graphs[i], &o, s);
+        FV_HIP(hipStreamSynchronize(s));
+      } catch (const fv::Error& e) {
+        st[i] = e.st;
+      } catch (const std::bad_alloc&) {
+        st[i] = FV_E_NOMEM;
+      } catch (...) {
+        st[i] = FV_E_DEVICE;
+      }
+      if (st[i] != FV_OK && out[i]) {
+        fv::free_hierarchy(out[i]);
+        out[i] = nullptr;
+      }
+    }
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  } catch (...) {
+    // fewer threads: the calling thread and those already started do the work
+  }
+  work();
+  for (auto& t : pool) t.join();
+  fv_status first = FV_OK;
+  for (int i = 0; i < count; ++i) {
+    if (item_status) item_status[i] = st[i];
+    if (first == FV_OK && st[i] != FV_OK) first = st[i];
+  }
+  return first;
 }
 
 fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, int64_t* nnz,

@@ -175,6 +175,11 @@ struct fv_context {
   std::unordered_map<void*, size_t> live;  // block handed out -> block size
   size_t cached = 0;
   std::mutex cache_mu;
+  // Small pinned host buffers for read-backs (kPinBytes each), reused so that
+  // builds on concurrent streams do not pay hipHostMalloc / hipHostFree (which
+  // synchronises) every time; freed with the context.
+  std::vector<void*> pins;
+  std::mutex pin_mu;
 };
 
 struct fv_hierarchy {
@@ -194,6 +199,14 @@ namespace fv {
 void* block_get(fv_context* ctx, size_t bytes);
 void block_put(fv_context* ctx, void* p);
 void block_trim(fv_context* ctx);  // hipFree every cached block
+
+// A pinned host buffer of kPinBytes from the context's pool.  pin_put
+// requires that no copy into or out of it is still queued: it synchronises
+// stream s (the stream that used it) before returning the buffer.
+constexpr size_t kPinBytes = 4096;
+void* pin_get(fv_context* ctx);
+void pin_put(fv_context* ctx, void* p, hipStream_t s);
+void pin_trim(fv_context* ctx);
 
 // Device allocation accounted against the context budget (blocks from the
 // cache; dev_free has block_put's precondition).

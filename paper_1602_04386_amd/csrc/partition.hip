@@ -264,12 +264,13 @@ fv_status spectral_partition(fv_context* ctx, const fv_csr* g, const fv_hier_opt
       sw(ctx, sizeof(double) * std::max<long long>(m, 1)), x(ctx, sizeof(double) * n),
       bsum(ctx, sizeof(long long) * (nb_of(n + 1, kTile) + 2)),
       misc(ctx, sizeof(unsigned) * (512 + 16 + (size_t)po->parts));
-  int* pin = nullptr;
-  FV_HIP(hipHostMalloc(reinterpret_cast<void**>(&pin), 4096, hipHostMallocDefault));
+  int* pin = static_cast<int*>(pin_get(ctx));  // kPinBytes
   struct PinGuard {
-    int* p;
-    ~PinGuard() { (void)hipHostFree(p); }
-  } pg{pin};
+    fv_context* c;
+    void* p;
+    hipStream_t s;
+    ~PinGuard() { pin_put(c, p, s); }
+  } pg{ctx, pin, s};
   FV_HIP(hipMemsetAsync(part.p, 0, sizeof(int) * n, s));
 
   // Exclusive scan of a[0, cnt) into out (out[cnt] = total); returns the total.

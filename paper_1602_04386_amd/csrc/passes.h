@@ -24,13 +24,14 @@ template <class WT, class XT>
 constexpr int tile_cap() { return 2048; }
 constexpr int kStageU = 8;  // staging slots per thread: kStageU * kBlock = the tile capacity
 
-// Waves per SIMD that a tile kernel's LDS leaves room for: six FP32 tiles
-// (25 KB each) or three FP64 tiles fit a CU.  The kernels ask the compiler for
-// that many so that registers never cut the occupancy below what LDS allows
-// (at 86 registers the FP32 sweep ran five blocks per CU, and the 1,488-block
+// Waves per SIMD that a tile kernel's LDS leaves room for: six FP32 tiles of
+// one row per thread (26 KB each), five of two rows per thread (27 KB), or
+// three FP64 tiles fit a CU.  The kernels ask the compiler for that many so
+// that registers never cut the occupancy below what LDS allows (at 86
+// registers the one-row FP32 sweep ran five blocks per CU, and the 1,488-block
 // colours of the 1024 x 1000 grid then needed a second round of blocks).
-template <class VT>
-constexpr int tile_waves() { return sizeof(VT) == 4 ? 6 : 3; }
+template <class VT, int RPT = 1>
+constexpr int tile_waves() { return sizeof(VT) == 4 ? (RPT == 1 ? 6 : 5) : 3; }
 
 // A tile is RPT * kBlock consecutive rows, RPT per thread (rows t, t + kBlock,
 // ...).  Two rows per thread let a colour of up to twice as many rows run in
@@ -223,7 +224,7 @@ __device__ inline void close_gs_sweep(DevState* st, const double (&S)[kNP], int 
 // ---- smoothing sweep, one colour -------------------------------------------
 
 template <class VT, int RPT>
-__global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride,
                                                   int slot_base, double omega) {
   __shared__ TileLds<VT, VT, RPT> T;
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_gs_tile(LevelDesc 
 // ---- power step ------------------------------------------------------------
 
 template <class VT, int RPT>
-__global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
                                                   const DevState* st, double* part, int stride) {
   __shared__ TileLds<VT, VT, RPT> T;
   __shared__ double lds[block_sum_lds(kBlock)];
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_pi_tile(LevelDesc 
 // ---- prolongation ----------------------------------------------------------
 
 template <class SRC, class VT, int RPT>
-__global__ __launch_bounds__(kBlock, tile_waves<VT>()) void k_prolong_tile(LevelDesc L, const SRC* xc_a,
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_prolong_tile(LevelDesc L, const SRC* xc_a,
                                                        const SRC* xc_b, VT* xf_a, VT* xf_b,
                                                        const DevState* st, double* part,
                                                        int stride) {

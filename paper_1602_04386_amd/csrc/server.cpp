@@ -1,14 +1,15 @@
 // Serving: continuous batching of Fiedler requests on one GPU.
 //
-// Worker threads, each with its own HIP stream, take up to their share of the
-// in-flight slots from the request queue, build (or reuse from the cache) the
-// requests' hierarchies, and run the small ones (finest level up to
-// kServeBatchMaxN vertices) as one persistent batched launch, one workgroup
-// per graph, and the large ones one after another through the
-// multi-workgroup single-graph path with the worker's own workspace.  A
-// request that arrives while others run on the device is admitted by the next
-// worker whose launch finishes, so launches from different workers overlap on
-// the device.  Device memory for hierarchies and launch workspaces comes out
+// Worker threads, each with its own HIP stream, take requests from the queue
+// as in-flight slots free up, build (or reuse from the cache) their
+// hierarchies, and run small ones (finest level up to kServeBatchMaxN
+// vertices) together as one persistent batched launch, one workgroup per
+// graph, and a large one alone through the multi-workgroup single-graph path
+// with the worker's own workspace.  With two or more workers the first one
+// takes only small requests, so they never queue behind a multi-million-vertex
+// solve.  A request that arrives while others run on the device is admitted by
+// the next worker that is free, launches from different workers overlap on
+// the device, and each result is published as soon as its own work ends.  Device memory for hierarchies and launch workspaces comes out
 // of the context's HBM budget; cached hierarchies not in use are evicted
 // least-recently-used first when a reservation does not fit.
 #include <hip/hip_runtime.h>
@@ -123,7 +124,53 @@ auto with_budget(fv_server* s, F f) -> decltype(f()) {
 // workgroup per graph stops paying off once a level no longer fits its LDS.
 constexpr int kServeBatchMaxN = 16384;
 
-void worker_main(fv_server* s, int share) {
+// Finest-level size of a queued request: its graph's, or its cached
+// hierarchy's; 0 when unknown (treated as small).  Caller holds s->mu.
+size_t request_n(const fv_server* s, const Request& r) {
+  if (r.has_graph) return (size_t)r.graph.n;
+  auto it = s->cache.find(r.req.graph_id);
+  if (it != s->cache.end() && it->second.h) return fv::hierarchy_nmax(it->second.h);
+  return 0;
+}
+
+bool is_large(const fv_server* s, uint64_t t) {
+  return request_n(s, s->reqs.at(t)) > (size_t)kServeBatchMaxN;
+}
+
+// Admission.  A worker of the small lane takes only small requests; the
+// others take the oldest request, alone when it is large, else together with
+// the next small ones (up to `room`, skipping large ones, which stay queued
+// in order).  So a small request never waits behind a large one in the same
+// worker, and the oldest request is always the next one a general worker
+// admits.  Returns false when this worker has nothing it may take.  Caller
+// holds s->mu.
+bool admit(fv_server* s, bool small_lane, int room, std::vector<uint64_t>& batch) {
+  auto& q = s->queue;
+  if (q.empty() || room < 1) return false;
+  if (!small_lane && is_large(s, q.front())) {
+    batch.push_back(q.front());
+    q.pop_front();
+    return true;
+  }
+  for (auto it = q.begin(); it != q.end() && (int)batch.size() < room;) {
+    if (is_large(s, *it)) {
+      ++it;
+      continue;
+    }
+    batch.push_back(*it);
+    it = q.erase(it);
+  }
+  return !batch.empty();
+}
+
+bool has_eligible(const fv_server* s, bool small_lane) {
+  if (!small_lane) return !s->queue.empty();
+  for (uint64_t t : s->queue)
+    if (!is_large(s, t)) return true;
+  return false;
+}
+
+void worker_main(fv_server* s, int share, bool small_lane) {
   (void)hipSetDevice(s->ctx->device);
   hipStream_t stream = nullptr;
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
@@ -134,18 +181,16 @@ void worker_main(fv_server* s, int share) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv.wait(lk, [&] {
-        return (!s->queue.empty() && s->inflight < s->opts.max_inflight) ||
-               (s->stop && s->queue.empty());
+        return (s->inflight < s->opts.max_inflight && has_eligible(s, small_lane)) ||
+               (s->stop && !has_eligible(s, small_lane));
       });
-      if (s->queue.empty()) break;
       const int room = std::min(share, s->opts.max_inflight - s->inflight);
-      while ((int)batch.size() < room && !s->queue.empty()) {
-        uint64_t t = s->queue.front();
-        s->queue.pop_front();
+      if (!admit(s, small_lane, room, batch)) break;  // stopping, nothing left for this lane
+      const auto now = Clock::now();
+      for (uint64_t t : batch) {
         Request& r = s->reqs[t];
         r.state = 1;
-        r.t_start = Clock::now();
-        batch.push_back(t);
+        r.t_start = now;
       }
       s->inflight += (int)batch.size();
       ++s->holders;
@@ -214,8 +259,35 @@ void worker_main(fv_server* s, int share) {
         owned[k] = hs[k] ? 1 : 0;
       }
     }
-    // One batched launch for the small admitted requests that have a
-    // hierarchy; the large ones run one by one below.
+    // Completes item k of the batch as soon as its own device work has ended
+    // (its stream has finished it): the result becomes visible to fv_poll,
+    // its slot and its hierarchy reference are given back.
+    auto complete = [&](size_t k, double lam, double res, long long bytes) {
+      const auto t_done = Clock::now();
+      std::lock_guard<std::mutex> g(s->mu);
+      Request& r = s->reqs[batch[k]];
+      r.res.status = st[k];
+      r.res.lambda = lam;
+      r.res.residual = res;
+      r.res.alg_bytes = bytes;
+      r.res.queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
+      r.res.latency_ms = std::chrono::duration<double, std::milli>(t_done - r.t_submit).count();
+      r.state = 2;
+      if (s->opts.cache_hierarchies) {
+        auto it = s->cache.find(r.req.graph_id);
+        if (it != s->cache.end() && hs[k] == it->second.h) it->second.refs--;
+      } else if (owned[k]) {
+        fv::free_hierarchy(hs[k], /*sync_device=*/false);
+      }
+      --s->inflight;
+      ++s->released;
+      s->cv.notify_all();
+    };
+    // Requests without a hierarchy (build failed) complete at once.
+    for (size_t k = 0; k < batch.size(); ++k)
+      if (!hs[k] || st[k] != FV_OK) complete(k, 0.0, 0.0, 0);
+    // One batched launch for the small admitted requests; the large ones run
+    // one by one below (a general worker admits a large request alone).
     std::vector<const fv_hierarchy*> run_h;
     std::vector<double*> run_x;
     std::vector<size_t> run_k, solo_k;
@@ -230,10 +302,10 @@ void worker_main(fv_server* s, int share) {
         run_x.push_back(s->reqs[batch[k]].req.x_out);
         run_k.push_back(k);
       }
-    std::vector<double> lam(run_h.size(), 0.0);
-    std::vector<fv_solve_stats> stats(run_h.size());
-    std::vector<fv_status> ist(run_h.size(), FV_OK);
     if (!run_h.empty()) {
+      std::vector<double> lam(run_h.size(), 0.0);
+      std::vector<fv_solve_stats> stats(run_h.size());
+      std::vector<fv_status> ist(run_h.size(), FV_OK);
       try {
         // the autotuner's cached configuration for this size class, if any
         // (a request never waits for a tuning run)
@@ -249,59 +321,33 @@ void worker_main(fv_server* s, int share) {
       } catch (...) {
         for (auto& v : ist) v = FV_E_DEVICE;
       }
+      for (size_t j = 0; j < run_k.size(); ++j) {
+        st[run_k[j]] = ist[j];
+        complete(run_k[j], lam[j], stats[j].residual, stats[j].alg_bytes);
+      }
     }
-    for (size_t j = 0; j < run_k.size(); ++j) st[run_k[j]] = ist[j];
-    std::vector<double> solo_lam(solo_k.size(), 0.0), solo_res(solo_k.size(), 0.0);
-    std::vector<long long> solo_bytes(solo_k.size(), 0);
-    for (size_t j = 0; j < solo_k.size(); ++j) {
-      const size_t k = solo_k[j];
+    for (size_t k : solo_k) {
       double* xo;
       {
         std::lock_guard<std::mutex> g(s->mu);
         xo = s->reqs[batch[k]].req.x_out;
       }
-      fv_solve_stats S;
+      fv_solve_stats S{};
+      double lam = 0.0;
       try {
         st[k] = with_budget(s, [&] {
-          return fv::solve_one_with(s->ctx, scratch, hs[k], &s->opts.solve, xo, 0, &solo_lam[j],
-                                    &S, stream);
+          return fv::solve_one_with(s->ctx, scratch, hs[k], &s->opts.solve, xo, 0, &lam, &S,
+                                    stream);
         });
-        solo_res[j] = S.residual;  // FV_E_NOT_CONVERGED still fills x and lambda
-        solo_bytes[j] = S.alg_bytes;
       } catch (const fv::Error& e) {
         st[k] = e.st;
       } catch (...) {
         st[k] = FV_E_DEVICE;
       }
+      // FV_E_NOT_CONVERGED still fills x and lambda
+      complete(k, lam, S.residual, S.alg_bytes);
     }
-    const auto t_done = Clock::now();
     std::lock_guard<std::mutex> g(s->mu);
-    for (size_t j = 0; j < run_k.size(); ++j) {
-      Request& r = s->reqs[batch[run_k[j]]];
-      r.res.lambda = lam[j];
-      r.res.residual = stats[j].residual;
-      r.res.alg_bytes = stats[j].alg_bytes;
-    }
-    for (size_t j = 0; j < solo_k.size(); ++j) {
-      Request& r = s->reqs[batch[solo_k[j]]];
-      r.res.lambda = solo_lam[j];
-      r.res.residual = solo_res[j];
-      r.res.alg_bytes = solo_bytes[j];
-    }
-    for (size_t k = 0; k < batch.size(); ++k) {
-      Request& r = s->reqs[batch[k]];
-      r.res.status = st[k];
-      r.res.queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
-      r.res.latency_ms = std::chrono::duration<double, std::milli>(t_done - r.t_submit).count();
-      r.state = 2;
-      if (s->opts.cache_hierarchies) {
-        auto it = s->cache.find(r.req.graph_id);
-        if (it != s->cache.end() && hs[k] == it->second.h) it->second.refs--;
-      } else if (owned[k]) {
-        fv::free_hierarchy(hs[k], /*sync_device=*/false);  // this batch's stream has finished
-      }
-    }
-    s->inflight -= (int)batch.size();
     --s->holders;
     ++s->released;
     s->cv.notify_all();
@@ -327,7 +373,9 @@ fv_status fv_server_create(fv_context* ctx, const fv_server_opts* opts, fv_serve
     if (opts->hbm_budget_bytes) ctx->budget = opts->hbm_budget_bytes;
     const int nworkers = std::max(1, std::min(4, opts->max_inflight));
     const int share = std::max(1, opts->max_inflight / nworkers);
-    for (int w = 0; w < nworkers; ++w) s->workers.emplace_back(worker_main, s, share);
+    // with two or more workers the first one is the small-request lane
+    for (int w = 0; w < nworkers; ++w)
+      s->workers.emplace_back(worker_main, s, share, nworkers > 1 && w == 0);
     *out = s;
     return FV_OK;
   } catch (...) {

@@ -419,6 +419,44 @@ __device__ inline int pick_best(int v, int a, int b, const int* col, const doubl
   return best;
 }
 
+// pick_best by one wavefront for a long row: each lane keeps the best of
+// every 64th entry, then the lanes' choices are reduced by the same strict
+// order (a total order, so the result does not depend on how the entries
+// were split).  Every lane of the wave calls it with the same v and returns
+// the same vertex.
+__device__ inline int pick_best_wave(int v, int a, int b, const int* col, const double* w,
+                                     const int* mate) {
+  int best = -1;
+  double bw = 0.0;
+  for (int p = a + (int)(threadIdx.x & 63); p < b; p += 64) {
+    const int u = col[p];
+    const double wu = w[p];
+    if (mate[u] == -1 && (best < 0 || edge_before(wu, v, u, bw, v, best))) {
+      best = u;
+      bw = wu;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const int ob = __shfl_xor(best, off, 64);
+    const double ow = __shfl_xor(bw, off, 64);
+    if (ob >= 0 && (best < 0 || edge_before(ow, v, ob, bw, v, best))) {
+      best = ob;
+      bw = ow;
+    }
+  }
+  return best;
+}
+
+// A level is dense for the one-workgroup kernels when its rows average at
+// least this many entries: each row is then scanned by a whole wavefront
+// instead of one thread (coarse levels of random graphs grow dense: on an
+// 11k-vertex Erdos-Renyi graph a 517-vertex level has 81 neighbours per
+// vertex and 27 colours, and one thread per row took milliseconds).
+constexpr int kDenseRow = 24;
+__host__ __device__ inline bool dense_level(int n, long long m) {
+  return m >= (long long)kDenseRow * n;
+}
+
 // ---------------------------------------------------------------------------
 // Heavy-edge matching by locally dominant rounds: every free vertex points at
 // its best free neighbour in the strict edge order; mutual pointers match.
@@ -463,12 +501,22 @@ __global__ __launch_bounds__(kLocalBlock) void k_match_local(int n, const int* r
                                                            const double* w, int* mate, int* ptr,
                                                            int* err) {
   __shared__ int pending;
+  const bool dense = dense_level(n, rp[n]);
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   for (int v = threadIdx.x; v < n; v += blockDim.x) mate[v] = -1;
   __syncthreads();
   for (int round = 0;; ++round) {
-    for (int v = threadIdx.x; v < n; v += blockDim.x) {
-      if (mate[v] != -1) continue;
-      ptr[v] = pick_best(v, rp[v], rp[v + 1], col, w, mate);
+    if (dense) {
+      for (int v = wave; v < n; v += nwave) {
+        if (mate[v] != -1) continue;  // uniform over the wave
+        const int b = pick_best_wave(v, rp[v], rp[v + 1], col, w, mate);
+        if ((threadIdx.x & 63) == 0) ptr[v] = b;
+      }
+    } else {
+      for (int v = threadIdx.x; v < n; v += blockDim.x) {
+        if (mate[v] != -1) continue;
+        ptr[v] = pick_best(v, rp[v], rp[v + 1], col, w, mate);
+      }
     }
     if (threadIdx.x == 0) pending = 0;
     __syncthreads();
@@ -556,6 +604,50 @@ __device__ inline bool jp_try(int v, int a, int b, IP col, CP colour, uint32_t s
   }
   if (wait) return true;
   *fit = mask != ~0ULL ? __builtin_ctzll(~mask) : first_fit(a, b, col, colour);
+  return false;
+}
+
+__device__ inline unsigned long long wave_or(unsigned long long m) {
+  for (int off = 32; off > 0; off >>= 1) m |= __shfl_xor(m, off, 64);
+  return m;
+}
+
+// first_fit by one wavefront (every lane of the wave calls it with the same
+// row and gets the same colour): the lanes take every 64th entry, windows of
+// 64 colours from `base` on.
+template <class IP, class CP>
+__device__ inline int first_fit_wave(int a, int b, IP col, CP c, int base) {
+  for (;; base += 64) {
+    unsigned long long mask = 0;
+    for (int p = a + (int)(threadIdx.x & 63); p < b; p += 64) {
+      const int k = c[col[p]];
+      if (k >= base && k < base + 64) mask |= 1ULL << (k - base);
+    }
+    mask = wave_or(mask);
+    if (mask != ~0ULL) return base + __builtin_ctzll(~mask);
+  }
+}
+
+// jp_try by one wavefront (same v in every lane; same answer in every lane).
+template <class IP, class CP>
+__device__ inline bool jp_try_wave(int v, int a, int b, IP col, CP colour, uint32_t seed,
+                                   int* fit) {
+  const uint32_t pv = colour_priority(v, seed);
+  bool wait = false;
+  unsigned long long mask = 0;
+  for (int p = a + (int)(threadIdx.x & 63); p < b; p += 64) {
+    const int u = col[p];
+    const int cu = colour[u];
+    if (cu < 0) {
+      const uint32_t pu = colour_priority(u, seed);
+      wait = wait || pu > pv || (pu == pv && u < v);
+    } else if (cu < 64) {
+      mask |= 1ULL << cu;
+    }
+  }
+  if (__ballot(wait) != 0ULL) return true;
+  mask = wave_or(mask);
+  *fit = mask != ~0ULL ? __builtin_ctzll(~mask) : first_fit_wave(a, b, col, colour, 64);
   return false;
 }
 
@@ -794,17 +886,32 @@ __device__ void colour_local_body(int n, IP rp, IP col, uint32_t seed, int two, 
   __syncthreads();
   for (int v = threadIdx.x; v < n; v += blockDim.x) colour[v] = -1;
   __syncthreads();
+  // dense levels: one wavefront per row (lane 0 stores the wave's result)
+  const bool dense = dense_level(n, rp[n]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   for (int round = 0;; ++round) {
     if (threadIdx.x == 0) waiting = 0;
     __syncthreads();
-    for (int v = threadIdx.x; v < n; v += blockDim.x) {
-      if (colour[v] >= 0) continue;
-      int fit;
-      if (jp_try(v, rp[v], rp[v + 1], col, colour, seed, &fit)) {
-        waiting = 1;
-        continue;
+    if (dense) {
+      for (int v = wave; v < n; v += nwave) {
+        if (colour[v] >= 0) continue;  // only this wave writes colour[v]
+        int fit;
+        if (jp_try_wave(v, rp[v], rp[v + 1], col, colour, seed, &fit)) {
+          if (lane == 0) waiting = 1;
+          continue;
+        }
+        if (lane == 0) colour[v] = fit;
       }
-      colour[v] = fit;
+    } else {
+      for (int v = threadIdx.x; v < n; v += blockDim.x) {
+        if (colour[v] >= 0) continue;
+        int fit;
+        if (jp_try(v, rp[v], rp[v + 1], col, colour, seed, &fit)) {
+          waiting = 1;
+          continue;
+        }
+        colour[v] = fit;
+      }
     }
     __syncthreads();
     if (!waiting) break;
@@ -821,8 +928,16 @@ __device__ void colour_local_body(int n, IP rp, IP col, uint32_t seed, int two, 
   for (int v = threadIdx.x; v < n; v += blockDim.x) cnew[v] = -1;
   __syncthreads();
   for (int c = m; c >= 0; --c) {
-    for (int v = threadIdx.x; v < n; v += blockDim.x)
-      if (colour[v] == c) cnew[v] = first_fit_batched(rp[v], rp[v + 1], col, cnew);
+    if (dense) {
+      for (int v = wave; v < n; v += nwave)
+        if (colour[v] == c) {
+          const int f = first_fit_wave(rp[v], rp[v + 1], col, cnew, 0);
+          if (lane == 0) cnew[v] = f;
+        }
+    } else {
+      for (int v = threadIdx.x; v < n; v += blockDim.x)
+        if (colour[v] == c) cnew[v] = first_fit_batched(rp[v], rp[v + 1], col, cnew);
+    }
     __syncthreads();
   }
   int m2 = -1;
@@ -1410,13 +1525,14 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
   if (max_levels < 1 || max_levels > FV_MAX_LEVELS) max_levels = FV_MAX_LEVELS;
 
   Tmp tmp{ctx, s, {}};
-  int* pin_i = nullptr;
+  int* pin_i = static_cast<int*>(pin_get(ctx));
   long long* pin_ll = nullptr;
-  FV_HIP(hipHostMalloc((void**)&pin_i, 64, hipHostMallocDefault));
   struct PinGuard {
-    int* p;
-    ~PinGuard() { (void)hipHostFree(p); }
-  } pg{pin_i};
+    fv_context* c;
+    void* p;
+    hipStream_t s;
+    ~PinGuard() { pin_put(c, p, s); }
+  } pg{ctx, pin_i, s};
   pin_ll = reinterpret_cast<long long*>(pin_i + 8);
 
   // Stage the input on the device.

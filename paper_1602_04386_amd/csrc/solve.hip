@@ -1336,14 +1336,23 @@ static fv_status solve_batch_t(fv_context* ctx, int count, const fv_hierarchy* c
 
   if (tune_now) {
     // Autotuning: each candidate configuration runs a size-stratified sample
-    // of the batch (every k-th graph in the largest-first order, at most 256)
-    // on this batch's own buffers; the fastest is cached for the size class.
-    // The sample's results are overwritten by the full launch below.
-    const int stride = std::max(1, count / 256);
-    const int ns = (count + stride - 1) / stride;
+    // of the batch (every 4th graph in the largest-first order, the whole
+    // batch below 1,024 graphs, at most 2,048), enough graphs per workgroup
+    // that the sample's time measures throughput and not the slowest graph
+    // alone, on this batch's own buffers; the fastest is cached for the size
+    // class.  One untimed launch of the sample's smallest graphs first pays
+    // the first use of the engine.  The sample's results are overwritten by
+    // the full launch below.
+    const int stride = count < 1024 ? 1 : 4;
     std::vector<GraphTask> all(count), samp;
     std::memcpy(all.data(), local.pin, sizeof(GraphTask) * count);
-    for (int j = 0; j < count; j += stride) samp.push_back(all[j]);
+    for (int j = 0; j < count && (int)samp.size() < 2048; j += stride) samp.push_back(all[j]);
+    const int ns = (int)samp.size();
+    const int nw = std::min(ns, 8);
+    std::memcpy(local.pin, samp.data() + (ns - nw), sizeof(GraphTask) * nw);
+    enqueue_batch<VT>(local, nw, kBatchLdsCand[0], batch_grid<VT>(nw, kBatchLdsCand[0]), false, 0,
+                      s);
+    FV_HIP(hipStreamSynchronize(s));  // its task copy has left the pinned buffer
     std::memcpy(local.pin, samp.data(), sizeof(GraphTask) * ns);
     hipEvent_t a = ev.a, b = ev.b;
     float best_ms = 0.0f;
@@ -1351,7 +1360,6 @@ static fv_status solve_batch_t(fv_context* ctx, int count, const fv_hierarchy* c
     bool first = true;
     for (size_t cand : kBatchLdsCand) {
       const int grid = batch_grid<VT>(ns, cand);
-      enqueue_batch<VT>(local, ns, cand, grid, false, 0, s);  // warm (first use of each)
       FV_HIP(hipEventRecord(a, s));
       enqueue_batch<VT>(local, ns, cand, grid, false, 0, s);
       FV_HIP(hipEventRecord(b, s));

@@ -101,6 +101,48 @@ def test_server_cold_mode_and_budget_eviction(fv, ctx):
         assert np.array_equal(out[t][1], ref[k].x)
 
 
+def _drain(srv, tickets, limit=120):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < limit:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.0005)
+    return out
+
+
+def test_server_small_requests_do_not_wait_for_large_ones(fv, ctx):
+    """A large request (the 1024 x 1000 grid) submitted first and small ones
+    right after it: the small ones are admitted by the small-request lane
+    while the large solve runs, and each result is published when its own
+    work ends, so every small request completes before the large one; every
+    result is bitwise the same as in the warm-up round, where the requests
+    were admitted in other combinations."""
+    kw = dict(prec="fp32", tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1,
+              max_outer=50)
+    big = gen.grid_1024x1000()
+    small = [gen.grid(20 + k, 15, "uniform", seed=k) for k in range(6)]
+    srv = fv.Server(ctx, max_inflight=8, n_coarse=25, **kw)
+    # warm-up: every hierarchy cached, so the timed round has no builds
+    warm = [srv.submit(100, big)] + [srv.submit(k, g) for k, g in enumerate(small)]
+    first = _drain(srv, warm)
+    assert len(first) == len(warm)
+    print("case server lanes: timed round", flush=True)
+    tickets = [srv.submit(100, big)] + [srv.submit(k, g) for k, g in enumerate(small)]
+    out = _drain(srv, tickets)
+    srv.close()
+    assert len(out) == len(tickets)
+    lat_big = out[tickets[0]][0]["latency_ms"]
+    lat_small = [out[t][0]["latency_ms"] for t in tickets[1:]]
+    assert max(lat_small) < lat_big, (lat_small, lat_big)
+    for a, b in zip(warm, tickets):
+        assert np.array_equal(first[a][1], out[b][1])
+        assert first[a][0]["lambda"] == out[b][0]["lambda"]
+
+
 def test_server_busy_and_unknown_ticket(fv, ctx):
     big = gen.grid(200, 150, "uniform", seed=3)
     srv = fv.Server(ctx, max_inflight=1, queue_capacity=1, n_coarse=25, prec="fp32",

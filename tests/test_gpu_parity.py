@@ -74,6 +74,10 @@ CASES = {
     # row pointers but not its FP32 weights: the engine reads only those from
     # global memory
     "grid96x96u": (lambda: gen.grid(96, 96, "uniform", seed=9), 25),
+    # coarse levels of Erdos-Renyi graphs grow dense (levels of about 1,000
+    # vertices and below average 30 to 120 neighbours): the one-workgroup
+    # matching and colouring scan such rows with a whole wavefront
+    "er12000": (lambda: gen.erdos_renyi(12000, 6 / 11999, 21), 25),
 }
 _graphs = {}
 
@@ -105,6 +109,27 @@ def test_structure_bit_exact(fv, ctx, orc, name):
     h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
     oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
     compare_structure(h, oh)
+
+
+def test_concurrent_builds_bit_exact(fv, ctx, orc):
+    """fv_build_hierarchies: every case built on four concurrent host threads
+    and streams is the oracle's hierarchy bit for bit, and a graph with an
+    isolated vertex among them fails alone with the oracle's status."""
+    names = list(CASES)
+    graphs = [graph(nm)[0] for nm in names]
+    bad = gen._csr_from_undirected(5, np.array([0, 1, 2]), np.array([1, 2, 3]), np.ones(3))
+    print(f"case concurrent builds of {len(graphs)} graphs and one invalid", flush=True)
+    hs, st = fv.build_hierarchies(ctx, graphs[:3] + [bad] + graphs[3:], threads=4, n_coarse=25)
+    assert st[3] == fv.E_ISOLATED and hs[3] is None
+    del hs[3], st[3]
+    assert st == [0] * len(graphs)
+    for nm, g, h in zip(names, graphs, hs):
+        nc = graph(nm)[1]
+        if nc != 25:
+            h.free()
+            h = fv.build_hierarchies(ctx, [g], threads=1, n_coarse=nc)[0][0]
+        compare_structure(h, orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc))
+        h.free()
 
 
 @pytest.mark.parametrize("name", list(CASES))
