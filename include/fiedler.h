@@ -117,6 +117,9 @@ typedef struct {
                             once ||L x - (x^T L x) x|| <= tol_coarse * sigma for the
                             unit iterate x; the paper leaves this tolerance open.
                             Default 1e-13 */
+  int32_t time_finest;   /* 1: time every finest-level smoothing launch with a pair
+                            of HIP events (totals in fv_solve_stats; the first 2048
+                            launches of a solve); 0 (default): no timing */
 } fv_solve_opts;
 
 /* Per-solve statistics.  schedule = [coarsest steps, then (gs sweeps, pi steps)
@@ -133,6 +136,12 @@ typedef struct {
   double final_cos;
   double t_solve_ms; /* device time of the solve (HIP events) */
   int64_t alg_bytes; /* algorithmic HBM bytes of the refinement passes */
+  /* with fv_solve_opts.time_finest: the finest-level smoothing launches that
+     were timed, their summed event time and their algorithmic bytes (per
+     launch: its colour's rows and entries, as in alg_bytes) */
+  int32_t n_finest_gs;
+  double t_finest_gs_ms;
+  int64_t finest_gs_bytes;
 } fv_solve_stats;
 
 /* Fills opts with the defaults named above (FP64, seed 1, tol_cos 1e-6, no
@@ -237,7 +246,8 @@ fv_status fv_fiedler_solve_batch(fv_context* ctx, int32_t count, const fv_hierar
  * Every call on one GPU shares that GPU's scratch and the context's host
  * buffers: calls that overlap on one GPU (other threads, other contexts, other
  * streams) race and must be serialised by the caller.  The scratch keeps the
- * last call's contents; the solve clears what it needs.  Errors: as
+ * last call's contents; the solve clears what it needs.  opts->time_finest is
+ * ignored (its events would be created on first use).  Errors: as
  * fv_fiedler_solve, plus FV_E_SCRATCH when the hierarchy's workspace exceeds
  * FV_NOALLOC_SCRATCH_BYTES (nothing runs). */
 fv_status fv_fiedler_solve_noalloc(fv_context* ctx, const fv_hierarchy* h,

@@ -53,7 +53,7 @@ class fv_solve_opts(C.Structure):
                 ("tol_res", C.c_double), ("omega", C.c_double), ("max_gs", C.c_int32),
                 ("max_pi", C.c_int32), ("max_outer", C.c_int32), ("max_coarsest", C.c_int32),
                 ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32),
-                ("stream", C.c_void_p), ("tol_coarse", C.c_double)]
+                ("stream", C.c_void_p), ("tol_coarse", C.c_double), ("time_finest", C.c_int32)]
 
 
 class fv_solve_stats(C.Structure):
@@ -61,7 +61,9 @@ class fv_solve_stats(C.Structure):
                 ("nnz", C.c_int64 * FV_MAX_LEVELS), ("colours", C.c_int32 * FV_MAX_LEVELS),
                 ("schedule_len", C.c_int32), ("schedule", C.c_int32 * FV_SCHEDULE_CAP),
                 ("lambda_", C.c_double), ("residual", C.c_double), ("final_cos", C.c_double),
-                ("t_solve_ms", C.c_double), ("alg_bytes", C.c_int64)]
+                ("t_solve_ms", C.c_double), ("alg_bytes", C.c_int64),
+                ("n_finest_gs", C.c_int32), ("t_finest_gs_ms", C.c_double),
+                ("finest_gs_bytes", C.c_int64)]
 
 
 class fv_batch_opts(C.Structure):
@@ -373,17 +375,21 @@ class SolveResult:
     n: list = field(default_factory=list)
     nnz: list = field(default_factory=list)
     colours: list = field(default_factory=list)
+    n_finest_gs: int = 0
+    t_finest_gs_ms: float = 0.0
+    finest_gs_bytes: int = 0
 
 
 def solve_opts(prec="fp64", seed=1, tol_cos=1e-6, tol_res=0.0, omega=1.0, max_gs=100,
                max_pi=100, max_outer=50, max_coarsest=100000, replay=None, stream=None,
-               tol_coarse=1e-13):
+               tol_coarse=1e-13, time_finest=False):
     o = fv_solve_opts()
     lib().fv_solve_opts_default(C.byref(o))
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.seed, o.tol_cos, o.tol_res, o.omega = seed, tol_cos, tol_res, omega
     o.max_gs, o.max_pi, o.max_outer, o.max_coarsest = max_gs, max_pi, max_outer, max_coarsest
     o.tol_coarse = tol_coarse
+    o.time_finest = 1 if time_finest else 0
     keep = None
     if replay is not None:
         keep = (C.c_int32 * len(replay))(*[int(v) for v in replay])
@@ -398,7 +404,8 @@ def _stats_to_result(st, x, lam, S: fv_solve_stats) -> SolveResult:
     L = S.levels
     return SolveResult(st, x, lam, S.residual, S.final_cos, list(S.schedule[:S.schedule_len]),
                        S.t_solve_ms, S.alg_bytes, L, list(S.n[:L]), list(S.nnz[:L]),
-                       list(S.colours[:L]))
+                       list(S.colours[:L]), S.n_finest_gs, S.t_finest_gs_ms,
+                       S.finest_gs_bytes)
 
 
 def fiedler_solve(ctx: Context, h: Hierarchy, x_out=None, **kw) -> SolveResult:

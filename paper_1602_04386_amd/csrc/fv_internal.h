@@ -133,6 +133,7 @@ struct Level {
   float* w32 = nullptr;
   int* cptr = nullptr;
   std::vector<int> cptr_h;
+  std::vector<long long> cnnz_h;  // solve-order row pointer at each colour start (and m)
   int* perm = nullptr;
   int* iperm = nullptr;
   int* qs = nullptr;
@@ -158,6 +159,8 @@ struct SolveScratch {
   // events of the early stop, and the event after a residual pass.
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_chunk[2] = {nullptr, nullptr},
              ev_res = nullptr;
+  // Event pairs of the opt-in per-launch timing (created on first use).
+  std::vector<hipEvent_t> tev;
 };
 }  // namespace fv
 

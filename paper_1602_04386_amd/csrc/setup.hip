@@ -1448,14 +1448,21 @@ static int read_int(const int* d, hipStream_t s, int* pinned) {
 // reads them back with a single copy.
 struct LevelRanges {
   const int* cptr[FV_MAX_LEVELS];
+  const int* rp[FV_MAX_LEVELS];  // solve-order row pointers
   int len[FV_MAX_LEVELS];
   int off[FV_MAX_LEVELS];
 };
+// out[off + k]: colour k's first row; out[total + off + k]: the row pointer
+// there (the colour's first entry).
 __global__ void k_gather_ranges(LevelRanges R, int nlev, const unsigned long long* dmax,
-                                int ndm, unsigned long long* out_dm, int* out) {
+                                int ndm, unsigned long long* out_dm, int* out, int total) {
   for (int k = threadIdx.x; k < ndm; k += blockDim.x) out_dm[k] = dmax[k];
   for (int l = 0; l < nlev; ++l)
-    for (int k = threadIdx.x; k < R.len[l]; k += blockDim.x) out[R.off[l] + k] = R.cptr[l][k];
+    for (int k = threadIdx.x; k < R.len[l]; k += blockDim.x) {
+      const int r = R.cptr[l][k];
+      out[R.off[l] + k] = r;
+      out[total + R.off[l] + k] = R.rp[l][r];
+    }
 }
 
 // Copies up to 8 device ints into out[0..7] (one launch, so that one
@@ -1889,17 +1896,18 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     int total = 0;
     for (int k = 0; k < J; ++k) {
       R.cptr[k] = h->lv[k].cptr;
+      R.rp[k] = h->lv[k].rp;
       R.len[k] = h->lv[k].ncol + 1;
       R.off[k] = total;
       total += R.len[k];
     }
     const size_t dm_bytes = sizeof(unsigned long long) * (J + 1);
-    unsigned char* stage = tmp.get<unsigned char>(dm_bytes + sizeof(int) * total);
+    unsigned char* stage = tmp.get<unsigned char>(dm_bytes + sizeof(int) * 2 * total);
     k_gather_ranges<<<1, kBlock, 0, s>>>(R, J, dmax, J + 1,
                                          reinterpret_cast<unsigned long long*>(stage),
-                                         reinterpret_cast<int*>(stage + dm_bytes));
+                                         reinterpret_cast<int*>(stage + dm_bytes), total);
     FV_HIP(hipGetLastError());
-    std::vector<unsigned char> host(dm_bytes + sizeof(int) * total);
+    std::vector<unsigned char> host(dm_bytes + sizeof(int) * 2 * total);
     FV_HIP(hipMemcpyAsync(host.data(), stage, host.size(), hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
     std::vector<unsigned long long> dm(J + 1);
@@ -1909,11 +1917,16 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       F.cptr_h.assign(F.ncol + 1, 0);
       std::memcpy(F.cptr_h.data(), host.data() + dm_bytes + sizeof(int) * R.off[k],
                   sizeof(int) * R.len[k]);
+      std::vector<int> e(R.len[k]);
+      std::memcpy(e.data(), host.data() + dm_bytes + sizeof(int) * (total + R.off[k]),
+                  sizeof(int) * R.len[k]);
+      F.cnnz_h.assign(e.begin(), e.end());
     }
     for (int k = 0; k < J; ++k) {  // drop the empty last classes the recolouring left
       Level& F = h->lv[k];
       while (F.ncol > 1 && F.cptr_h[F.ncol - 1] == F.n) --F.ncol;
       F.cptr_h.resize(F.ncol + 1);
+      F.cnnz_h.resize(F.ncol + 1);
     }
     for (int k = 0; k <= J; ++k) {
       double d;

@@ -589,6 +589,28 @@ struct HostSync {
 
 constexpr int kChunk = 2;
 
+// Opt-in timing of the finest level's smoothing launches: a pair of HIP
+// events around each launch, read after the solve has finished.  Events come
+// from the scratch's pool, created on first use, at most kTimedLaunches pairs
+// per solve (later launches run untimed).
+constexpr int kTimedLaunches = 2048;
+struct LaunchTimer {
+  std::vector<hipEvent_t>* pool = nullptr;
+  int used = 0;
+  std::vector<long long> bytes;
+  bool on() const { return pool != nullptr; }
+  // the event before launch `used`, or nullptr when the pool is exhausted
+  hipEvent_t* pair() {
+    if (!pool || used >= kTimedLaunches) return nullptr;
+    while ((int)pool->size() < 2 * (used + 1)) {
+      hipEvent_t e = nullptr;
+      FV_HIP(hipEventCreate(&e));
+      pool->push_back(e);
+    }
+    return pool->data() + 2 * used;
+  }
+};
+
 // Enqueues one smoothing (gs) or power phase: `forced` steps exactly when it
 // is not negative, else up to `cap` steps with the cosine test.  The step
 // count lands in *rec on the device.  before_wait, when given, runs once
@@ -598,7 +620,8 @@ constexpr int kChunk = 2;
 template <class VT, class BeforeWait>
 static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const Workspace& W,
                             int forced, int cap, double tol, double omega, hipStream_t s,
-                            HostSync& hs, int* rec, bool use_halt, BeforeWait before_wait) {
+                            HostSync& hs, int* rec, bool use_halt, BeforeWait before_wait,
+                            LaunchTimer* timer = nullptr) {
   const int lim = forced >= 0 ? forced : cap;
   k_phase_begin<<<1, 1, 0, s>>>(W.st, lim, forced >= 0 ? 1 : 0, tol, use_halt ? 1 : 0, rec,
                                 hs.hdone_dev);
@@ -625,12 +648,21 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
         int base = 0;
         for (int c = 0; c < ct; ++c) {
           const int r0 = Lh.cptr_h[c], r1 = Lh.cptr_h[c + 1];
+          hipEvent_t* ev = timer ? timer->pair() : nullptr;
+          if (ev) FV_HIP(hipEventRecord(ev[0], s));
           if (rpt[c] == 2)
             k_gs_tile<VT, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
                                                        base, omega);
           else
             k_gs_tile<VT, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
                                                        base, omega);
+          if (ev) {
+            FV_HIP(hipEventRecord(ev[1], s));
+            timer->bytes.push_back(pass_bytes(r1 - r0, Lh.cnnz_h[c + 1] - Lh.cnnz_h[c],
+                                              sizeof(VT) == 4 ? FV_PREC_FP32_MIXED
+                                                              : FV_PREC_FP64));
+            ++timer->used;
+          }
           base += nbs[c];
         }
         if (ct < L.ncol)
@@ -757,6 +789,8 @@ void release_scratch(fv_context* ctx, SolveScratch& sc) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
+  for (hipEvent_t e : sc.tev) (void)hipEventDestroy(e);
+  sc.tev.clear();
 }
 
 void scratch_host_init(SolveScratch& sc) {
@@ -806,6 +840,9 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
   // Output staging for a host x_out: lx, free once the residual is done.
   double* out_dev = x_on_device ? x_out : W.lx;
   hipEvent_t e0 = sc.ev_t0, e1 = sc.ev_t1;
+  LaunchTimer timer;
+  if (o->time_finest) timer.pool = &sc.tev;
+  LaunchTimer* tptr = timer.on() ? &timer : nullptr;
   FV_HIP(hipEventRecord(e0, s));
 
   GraphTask T;
@@ -882,7 +919,7 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
                                     nullptr);
       FV_HIP(hipGetLastError());
       run_phase_multi<VT>(true, F, L, W, next_forced(), o->max_gs, o->tol_cos, o->omega, s, hsync,
-                          rec_slot(), false, no_wait);
+                          rec_slot(), false, no_wait, l == 0 ? tptr : nullptr);
       run_phase_multi<VT>(false, F, L, W, next_forced(), o->max_pi, o->tol_cos, o->omega, s,
                           hsync, rec_slot(), false, no_wait);
     }
@@ -924,7 +961,7 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
         return *hsync.hres <= o->tol_res;
       };
       if (run_phase_multi<VT>(true, F0, L0, W, fg, o->max_gs, o->tol_cos, o->omega, s, hsync,
-                              rec_slot(), spec, residual_met)) {
+                              rec_slot(), spec, residual_met, tptr)) {
         --nrec;  // the void round is not part of the schedule
         break;
       }
@@ -973,6 +1010,17 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
     stats->final_cos = fcos;
     stats->t_solve_ms = ms;
     stats->alg_bytes = schedule_bytes(h, sched.data(), (int)sched.size(), o->prec);
+    double tsum = 0.0;
+    long long bsum = 0;
+    for (int k = 0; k < timer.used; ++k) {
+      float t = 0.0f;
+      FV_HIP(hipEventElapsedTime(&t, timer.pool->at(2 * k), timer.pool->at(2 * k + 1)));
+      tsum += t;
+      bsum += timer.bytes[k];
+    }
+    stats->n_finest_gs = timer.used;
+    stats->t_finest_gs_ms = tsum;
+    stats->finest_gs_bytes = bsum;
   }
   return status;
 }
@@ -1039,9 +1087,11 @@ fv_status solve_noalloc(fv_context* ctx, const fv_hierarchy* h, const fv_solve_o
   if (!ws || !sc.pinned || !sc.hflags || !sc.ev_t0 || !sc.ev_res)
     throw Error(FV_E_DEVICE, "context set-up incomplete");
   hipStream_t s = o->stream ? static_cast<hipStream_t>(o->stream) : ctx->stream;
+  fv_solve_opts oo = *o;
+  oo.time_finest = 0;  // the timing's events are created on first use: not here
   if (o->prec == FV_PREC_FP32_MIXED)
-    return solve_one_t<float>(ctx, sc, ws, h, o, x_out, x_on_device, lambda_out, stats, s);
-  return solve_one_t<double>(ctx, sc, ws, h, o, x_out, x_on_device, lambda_out, stats, s);
+    return solve_one_t<float>(ctx, sc, ws, h, &oo, x_out, x_on_device, lambda_out, stats, s);
+  return solve_one_t<double>(ctx, sc, ws, h, &oo, x_out, x_on_device, lambda_out, stats, s);
 }
 
 fv_status solve_one(fv_context* ctx, const fv_hierarchy* h, const fv_solve_opts* o,
