@@ -6,9 +6,11 @@
   its eigenvalue is within 1e-5 of the FP64 oracle on the same schedule, and the
   FP64 GPU solve on that schedule within 1e-10.
 * 4M-vertex random geometric graph: the whole hierarchy bit-exact; the FP64
-  oracle's free-running solve with the benchmark's parameters (a stored
-  golden record) replayed in FP64 and FP32-mixed: eigenvalue, residual and
-  sampled vector entries.
+  oracle's free-running solves with the grid's parameters (which stall) and
+  with the graph's own long-phase parameters (which converge), two stored
+  golden records, replayed in FP64 and FP32-mixed: eigenvalue, residual and
+  sampled vector entries; the FP32-mixed solve with the graph's parameters
+  reaches residual 1e-6.
 * Batch of graphs drawn from the 4096-graph benchmark mix (grids and
   Erdos-Renyi graphs with pendant vertices): one FP32-mixed batched launch
   with the batch workload's parameters; every item against the FP64 oracle on
@@ -33,6 +35,7 @@ pytestmark = pytest.mark.gpu
 from bench import SOLVE as BENCH_SOLVE  # the benchmark's solve parameters
 from bench import SQUARE_SOLVE  # the square-grid scaling workload's
 from bench import BATCH_SOLVE  # the batch and serving workloads
+from bench import RGG_SOLVE  # the random geometric graph's own parameters
 from test_gpu_parity import check_fp32_result
 
 
@@ -103,6 +106,28 @@ def test_rgg_4m_structure_and_benchmark_schedule(fv, ctx, orc):
     assert np.max(np.abs(s * r32.x[idx] - xs)) <= 1.4e-4  # 1 - |cos| <= 1e-8
     # the reported residual is that of the returned vector (FP64 on the CPU)
     assert abs(cpu_residual(g, r32.x, r32.lam) - r32.residual) <= 1e-6 * r32.residual
+
+    # The graph's own parameters (long phases, no cosine stop): the oracle's
+    # converged free-running solve (tests/golden/rgg4m_oracle_long.json)
+    # replayed in both precisions, then the FP32-mixed solve run exactly as the
+    # benchmark runs it reaches residual 1e-6, checked again on the CPU.
+    with open(os.path.join(os.path.dirname(__file__), "golden", "rgg4m_oracle_long.json")) as f:
+        gold = json.load(f)
+    assert gold["status"] == 0 and gold["residual"] <= 1e-6
+    sched, lam = gold["schedule"], gold["lambda"]
+    idx = np.array(gold["sample_index"])
+    xs = np.array(gold["sample_x"])
+    print(f"case rgg4m long: fp64 replay ({len(sched)} phases)", flush=True)
+    r64 = fv.fiedler_solve(ctx, h, prec="fp64", seed=1, omega=1.9, replay=sched)
+    assert abs(r64.lam - lam) <= 1e-10 * lam
+    assert abs(r64.residual - gold["residual"]) <= 1e-9 * gold["residual"]
+    s = 1.0 if float(r64.x[idx] @ xs) >= 0 else -1.0
+    assert np.max(np.abs(s * r64.x[idx] - xs)) <= 1.4e-5
+    print("case rgg4m long: fp32 as benchmarked", flush=True)
+    r32 = fv.fiedler_solve(ctx, h, prec="fp32", **RGG_SOLVE)
+    assert r32.status == 0 and r32.residual <= 1e-6
+    assert cpu_residual(g, r32.x, r32.lam) <= 1e-6 * (1 + 1e-6)
+    assert abs(r32.lam - lam) <= 1e-5 * lam
     h.free()
 
 
