@@ -392,12 +392,26 @@ def run_rgg(args):
                 "build": "gcc -O3 -march=native -ffp-contract=off",
                 "cpu_model": host["model"], "nproc": host["nproc"]}
 
-    return single_graph(
+    out = single_graph(
         args, g, solve,
         "Fiedler solves/s at residual<=1e-6 (RGG 4M, setup+solve)",
         f"random geometric graph, 4M points in the unit square, r=sqrt(8/(pi n)), weights "
         f"exp(-d^2/r^2), largest component n={g.n}, nnz={len(g.col)} (SplitMix64 seed 3)", cpu,
         traffic_name="rgg4m")
+    # The FP64 oracle's own free-running solve of this graph with these
+    # parameters takes minutes on one core: its stored record (written by
+    # tests/golden/make_rgg4m_oracle.py, which calls only the oracle) is the
+    # reference for the eigenvalue.
+    with open(os.path.join(ROOT, "tests", "golden", "rgg4m_oracle_long.json")) as f:
+        gold = json.load(f)
+    if gold["solve"] == solve and gold["n"] == g.n:
+        lam = out["config"]["lambda"]
+        out["vs_oracle"] = {"lambda_oracle": gold["lambda"],
+                            "lambda_rel_err": abs(lam - gold["lambda"]) / gold["lambda"],
+                            "residual_oracle": gold["residual"],
+                            "residual_gpu": out["config"]["residual_max"],
+                            "source": "stored oracle record (tests/golden/rgg4m_oracle_long.json)"}
+    return out
 
 
 def run_batch(args):
