@@ -5,12 +5,12 @@ its vector at 4096 positions drawn with SplitMix64 seed 12.
 * rgg4m_oracle.json: SOR factor 1.9, cosine tolerance 3e-12, at most 30 sweeps
   and one power step per phase, at most 20 finest rounds (the 1024 x 1000
   grid's parameters; this graph stalls above residual 1e-6 under them).
-* rgg4m_oracle_long.json: the random geometric graph's own parameters: no
-  cosine stop, 100 sweeps and one power step per phase, finest rounds until
+* rgg4m_oracle_own.json: the random geometric graph's own parameters: no
+  cosine stop, 30 sweeps and 30 power steps per phase, finest rounds until
   residual 1e-6 (at most 100).
 
 Calls only the oracle; each takes a few minutes on one core.
-Run: python tests/golden/make_rgg4m_oracle.py [short|long]
+Run: python tests/golden/make_rgg4m_oracle.py [short|own]
 """
 import json
 import os
@@ -25,8 +25,8 @@ import oracle  # noqa: E402
 
 SOLVE = dict(seed=1, tol_cos=3e-12, tol_res=1e-6, omega=1.9, max_gs=30, max_pi=1, max_outer=20,
              max_coarsest=100000, tol_coarse=1e-6)
-LONG = dict(SOLVE, tol_cos=0.0, max_gs=100, max_outer=100)
-RECORDS = {"short": ("rgg4m_oracle.json", SOLVE), "long": ("rgg4m_oracle_long.json", LONG)}
+OWN = dict(SOLVE, tol_cos=0.0, max_gs=30, max_pi=30, max_outer=100)
+RECORDS = {"short": ("rgg4m_oracle.json", SOLVE), "own": ("rgg4m_oracle_own.json", OWN)}
 
 
 def main(which):
