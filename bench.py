@@ -624,6 +624,7 @@ def run_serve(args):
     solve = SERVE_SOLVE
     ctx = fv.Context(0)
     srv = fv.Server(ctx, max_inflight=64, queue_capacity=1 << 16, cache_hierarchies=True,
+                    workers=args.serve_workers,
                     n_coarse=N_COARSE, prec="fp32", **solve)
 
     def wait_all(tickets, limit_s):
@@ -726,7 +727,7 @@ def run_serve(args):
         "config": {
             "workload": f"pool of {len(pool)} graphs, n log-uniform [1e3, 2e6] (SplitMix64 seed 5), "
                         f"70% random geometric / 30% 4:3 grids; sum n={sum(g.n for g in pool)}",
-            "solve": solve,
+            "solve": solve, "workers": args.serve_workers or 8,
             "requested_rate": args.rate, "offered_rate": round(rate, 2),
             "closed_loop_capacity": round(cap_rate, 2),
             "saturated_at_requested_rate": args.rate > 0.8 * cap_rate,
@@ -987,6 +988,8 @@ def main():
     ap.add_argument("--build-threads", type=int, default=8,
                     help="batch: host threads of the concurrent hierarchy builds")
     ap.add_argument("--pool", type=int, default=32)
+    ap.add_argument("--serve-workers", type=int, default=0,
+                    help="serve: server worker threads (0: the library's default, 8)")
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--capacity-s", type=float, default=5.0)

@@ -335,6 +335,9 @@ typedef struct {
   int32_t cache_hierarchies; /* 1: keep hierarchies resident by graph_id (LRU) */
   fv_hier_opts hier;
   fv_solve_opts solve;       /* replay and stream must be NULL */
+  int32_t workers;           /* worker threads, each with its own stream (0: 8; at most
+                                max_inflight); with two or more, the first takes only
+                                requests of up to 16384 vertices */
 } fv_server_opts;
 
 typedef struct {

@@ -85,7 +85,7 @@ class fv_partition_stats(C.Structure):
 class fv_server_opts(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("queue_capacity", C.c_int32),
                 ("hbm_budget_bytes", C.c_size_t), ("cache_hierarchies", C.c_int32),
-                ("hier", fv_hier_opts), ("solve", fv_solve_opts)]
+                ("hier", fv_hier_opts), ("solve", fv_solve_opts), ("workers", C.c_int32)]
 
 
 class fv_request(C.Structure):
@@ -506,9 +506,10 @@ class Server:
     """fv_server_create / fv_submit / fv_poll / fv_server_destroy."""
 
     def __init__(self, ctx: Context, max_inflight=64, queue_capacity=4096, hbm_budget_bytes=0,
-                 cache_hierarchies=True, n_coarse=25, **solve_kw):
+                 cache_hierarchies=True, n_coarse=25, workers=0, **solve_kw):
         so = fv_server_opts()
         so.max_inflight, so.queue_capacity = max_inflight, queue_capacity
+        so.workers = workers
         so.hbm_budget_bytes, so.cache_hierarchies = hbm_budget_bytes, int(cache_hierarchies)
         so.hier = fv_hier_opts(n_coarse, FV_MAX_LEVELS, 0)
         o, keep = solve_opts(**solve_kw)
