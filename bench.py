@@ -994,7 +994,7 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=0,
                     help="serve: server worker threads (0: the library's default, 8)")
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--duration", type=float, default=30.0)
     ap.add_argument("--capacity-s", type=float, default=5.0)
     ap.add_argument("--counters-probe", action="store_true",
                     help="short run for rocprofv3 --pmc passes (copy calibration + level-0 sweeps)")
