@@ -100,7 +100,8 @@ typedef struct {
   int32_t prec;          /* fv_precision */
   uint64_t seed;         /* SplitMix64 seed of the coarsest random start */
   double tol_cos;        /* a phase ends when (x_k, x_{k-1}) > 1 - tol_cos; Section 4
-                            uses 1e-6 */
+                            uses 1e-6; <= 0: no cosine stop, every phase runs to its cap
+                            (a test against exactly 1 would fire on rounding) */
   double tol_res;        /* > 0: repeat the finest-level phases until
                             ||L x - lambda x|| / ||x|| <= tol_res; 0 = off */
   double omega;          /* relaxation of the smoothing sweep; 1 = Gauss-Seidel */

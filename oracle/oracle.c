@@ -863,7 +863,8 @@ void or_hier_level_copy(const void* hp, int32_t l, int32_t* rp, int32_t* col, do
 
 typedef struct {
   uint64_t seed;
-  double tol_cos;      /* stop a phase when (x_k, x_{k-1}) > 1 - tol_cos */
+  double tol_cos;      /* stop a phase when (x_k, x_{k-1}) > 1 - tol_cos; <= 0: no
+                          cosine stop, every phase runs to its cap */
   double tol_res;      /* > 0: repeat level-0 phases until residual <= tol_res */
   int32_t max_gs;      /* sweeps per smoothing phase */
   int32_t max_pi;      /* steps per power-iteration phase */
@@ -1077,7 +1078,7 @@ static int32_t or_gs_phase(const or_level* L, const or_solve_params* P, int32_t 
     or_project_normalise_m(L->n, m, x);
     ++k;
     c = or_dot_m(L->n, m, x, xp);
-    if (forced < 0 && c > 1.0 - P->tol_cos) break;
+    if (forced < 0 && P->tol_cos > 0.0 && c > 1.0 - P->tol_cos) break;
   }
   *cos_out = c;
   return k;
@@ -1100,7 +1101,7 @@ static int32_t or_pi_phase(const or_level* L, const or_solve_params* P, int32_t 
     ++k;
     c = or_dot_m(L->n, m, x, y);
     memcpy(x, y, sizeof(double) * (size_t)L->n);
-    if (forced < 0 && c > 1.0 - P->tol_cos) break;
+    if (forced < 0 && P->tol_cos > 0.0 && c > 1.0 - P->tol_cos) break;
   }
   *cos_out = c;
   return k;

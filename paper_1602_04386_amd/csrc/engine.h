@@ -236,7 +236,7 @@ __device__ __forceinline__ int vgs_phase(const V& L, XP x, Scal& s, double omega
   while (k < lim) {
     s = vsweep<VT>(L, x, s, omega, E);
     ++k;
-    if (P.forced < 0 && s.cos > 1.0 - P.tol) break;
+    if (P.forced < 0 && P.tol > 0.0 && s.cos > 1.0 - P.tol) break;
   }
   return k;
 }
@@ -248,7 +248,7 @@ __device__ __forceinline__ int vpi_phase(const V& L, XP x, VT* y, Scal& s, Phase
   while (k < lim) {
     s = vpi_step<VT>(L, x, y, s, E);
     ++k;
-    if (P.forced < 0 && s.cos > 1.0 - P.tol) break;
+    if (P.forced < 0 && P.tol > 0.0 && s.cos > 1.0 - P.tol) break;
   }
   return k;
 }

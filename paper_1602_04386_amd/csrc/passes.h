@@ -214,7 +214,8 @@ __device__ inline void close_gs_sweep(DevState* st, const double (&S)[kNP], int 
   const int it = st->iters + 1;
   st->iters = it;
   *rec = it;
-  const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  const int done =
+      (it >= st->cap || (!st->forced && st->tol > 0.0 && r.cos > 1.0 - st->tol)) ? 1 : 0;
   st->done = done;
   // The host copy only ever goes from 0 (set when the phase opens) to 1: a
   // write across the bus on every step would hold up the kernel's end.
@@ -492,7 +493,8 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
   const int it = st->iters + 1;
   st->iters = it;
   *rec = it;
-  const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  const int done =
+      (it >= st->cap || (!st->forced && st->tol > 0.0 && r.cos > 1.0 - st->tol)) ? 1 : 0;
   st->done = done;
   if (done) *hdone = 1;
 }
@@ -547,7 +549,8 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
   const int it = st->iters + 1;
   st->iters = it;
   *rec = it;
-  const int done = (it >= st->cap || (!st->forced && r.cos > 1.0 - st->tol)) ? 1 : 0;
+  const int done =
+      (it >= st->cap || (!st->forced && st->tol > 0.0 && r.cos > 1.0 - st->tol)) ? 1 : 0;
   st->done = done;
   if (done) *hdone = 1;
 }

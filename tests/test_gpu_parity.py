@@ -408,3 +408,31 @@ def test_server_large_requests_take_the_single_graph_path(fv, ctx):
         info, x = out[t]
         assert info["status"] == ref.status
         assert np.array_equal(x, ref.x) and info["lambda"] == ref.lam
+
+
+# Long phases without the cosine stop and many power steps per phase (the
+# random geometric graph's and the serving pool's parameters): every phase
+# runs to its cap, so the schedule is fixed by the parameters alone and the
+# GPU's free-running schedule must be the oracle's.
+LONG_PHASES = dict(seed=1, tol_cos=0.0, max_gs=30, max_pi=30, omega=1.95, tol_res=1e-6,
+                   max_outer=6, tol_coarse=1e-6)
+
+
+@pytest.mark.parametrize("name", ["grid64x48u", "er3000", "rgg20k", "grid256x250u"])
+def test_long_phase_parameters(fv, ctx, orc, name):
+    g, nc = graph(name)
+    print(f"case {name} long phases", flush=True)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=nc)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+    ro = oh.solve(**LONG_PHASES)
+    # single-graph path (multi-workgroup passes on the large levels), FP64
+    r = fv.fiedler_solve(ctx, h, prec="fp64", **LONG_PHASES)
+    assert r.schedule == ro.counts
+    assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+    assert 1 - abs(float(r.x @ ro.x)) <= 1e-10
+    # the batched engine on the same graph, FP64 and FP32-mixed
+    rb = fv.fiedler_solve_batch(ctx, [h], prec="fp64", **LONG_PHASES)[0]
+    assert rb.schedule == ro.counts
+    assert abs(rb.lam - ro.lam) <= 1e-10 * ro.lam
+    r32 = fv.fiedler_solve(ctx, h, prec="fp32", **LONG_PHASES)
+    check_fp32_result(g, r32, oh.solve(**dict(LONG_PHASES, replay=r32.schedule)), h.sigma[0])

@@ -927,3 +927,16 @@ def test_partition_isolated_vertex_rule_worked_example(orc):
     labels, n_iso = orc.spectral_partition(
         g, 4, "median", vector=lambda sub: np.arange(sub.n, dtype=np.float64))
     assert labels.tolist() == [0, 1, 2, 3, 2] and n_iso == 1
+
+
+def test_zero_cosine_tolerance_runs_every_phase_to_its_cap(orc):
+    """tol_cos <= 0 switches the cosine stop off (Section 4's test compares
+    the cosine of successive unit iterates with 1 - tol_cos; against exactly 1
+    it could fire on rounding once the iterates agree to the last bit): every
+    phase then runs its full sweep and step caps, so the schedule is the caps
+    alone, also for many power steps on a graph where they converge fast."""
+    for g, nc in ((gen.grid(20, 9), 8), (gen.random_connected(64, 802), 6)):
+        h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=nc)
+        J = h.nlevels - 1
+        r = h.solve(seed=1, tol_cos=0.0, max_gs=7, max_pi=40, tol_res=1e-30, max_outer=3)
+        assert r.counts[1:] == [7, 40] * (J + 3)
