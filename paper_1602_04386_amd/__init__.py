@@ -45,7 +45,8 @@ class fv_csr(C.Structure):
 
 
 class fv_hier_opts(C.Structure):
-    _fields_ = [("n_coarse", C.c_int32), ("max_levels", C.c_int32), ("colour_seed", C.c_uint64)]
+    _fields_ = [("n_coarse", C.c_int32), ("max_levels", C.c_int32), ("colour_seed", C.c_uint64),
+                ("ell", C.c_int32)]
 
 
 class fv_solve_opts(C.Structure):
@@ -323,10 +324,11 @@ def _make_csr(n, rowptr, col, val, is_adjacency):
 
 def build_hierarchy(ctx: Context, n: int, rowptr, col, val, is_adjacency: bool = True,
                     n_coarse: int = 25, max_levels: int = FV_MAX_LEVELS,
-                    colour_seed: int = 0) -> Hierarchy:
-    """fv_build_hierarchy: setup phase (Algorithm 3, Step 1) on the device."""
+                    colour_seed: int = 0, ell: bool = True) -> Hierarchy:
+    """fv_build_hierarchy: setup phase (Algorithm 3, Step 1) on the device.
+    ell=False keeps every level in CSR only (fv_hier_opts.ell = -1)."""
     csr, keep = _make_csr(n, rowptr, col, val, is_adjacency)
-    opts = fv_hier_opts(n_coarse, max_levels, colour_seed)
+    opts = fv_hier_opts(n_coarse, max_levels, colour_seed, 0 if ell else -1)
     h = C.c_void_p()
     _check(lib().fv_build_hierarchy(ctx.handle, C.byref(csr), C.byref(opts), C.byref(h)),
            "fv_build_hierarchy")
@@ -339,7 +341,7 @@ def build_hierarchy_graph(ctx: Context, g, **kw) -> Hierarchy:
 
 
 def build_hierarchies(ctx: Context, graphs, threads: int = 0, n_coarse: int = 25,
-                      max_levels: int = FV_MAX_LEVELS, colour_seed: int = 0):
+                      max_levels: int = FV_MAX_LEVELS, colour_seed: int = 0, ell: bool = True):
     """fv_build_hierarchies: the setup phase for many adjacency graphs (objects
     with n, rowptr, col, w) on concurrent host threads and streams.  Returns
     (hierarchies, statuses): a Hierarchy or None per graph, and its status."""
@@ -352,7 +354,7 @@ def build_hierarchies(ctx: Context, graphs, threads: int = 0, n_coarse: int = 25
     ptrs = (C.POINTER(fv_csr) * max(count, 1))(*[C.pointer(c) for c in csrs])
     out = (C.c_void_p * max(count, 1))()
     st = (C.c_int * max(count, 1))()
-    opts = fv_hier_opts(n_coarse, max_levels, colour_seed)
+    opts = fv_hier_opts(n_coarse, max_levels, colour_seed, 0 if ell else -1)
     lib().fv_build_hierarchies(ctx.handle, count, ptrs, C.byref(opts), int(threads), out, st)
     del keep
     hs = [Hierarchy(ctx, C.c_void_p(out[i])) if out[i] else None for i in range(count)]

@@ -163,6 +163,7 @@ void fv_hier_opts_default(fv_hier_opts* o) {
   o->n_coarse = 25;
   o->max_levels = FV_MAX_LEVELS;
   o->colour_seed = 0;
+  o->ell = 0;
 }
 
 void fv_solve_opts_default(fv_solve_opts* o) {

@@ -86,6 +86,13 @@ struct LevelDesc {
   const int* perm;   // original index -> solve position
   const int* iperm;  // solve position -> original index
   double sigma;
+  // Slot-major (ELL) copy of the solve-order matrix, or ew == 0: entry k of
+  // row i at ecol[k * n + i] (CSR order; padding slots hold column -1 and
+  // weight 0), ew slots per row.
+  int ew;
+  const int* ecol;
+  const double* ew64;
+  const float* ew32;
 };
 
 // One graph's work for the one-workgroup engine.
@@ -137,7 +144,35 @@ struct Level {
   int* perm = nullptr;
   int* iperm = nullptr;
   int* qs = nullptr;
+  // slot-major copy for the smoothing sweeps (ew slots per row; 0: none)
+  int ew = 0;
+  int* ecol = nullptr;
+  double* ew64 = nullptr;
+  float* ew32 = nullptr;
 };
+
+// The device descriptor of a level.
+inline LevelDesc desc_of(const Level& F) {
+  LevelDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.n = F.n;
+  d.ncol = F.ncol;
+  d.m = F.m;
+  d.rp = F.rp;
+  d.col = F.col;
+  d.w64 = F.w64;
+  d.w32 = F.w32;
+  d.cptr = F.cptr;
+  d.qs = F.qs;
+  d.perm = F.perm;
+  d.iperm = F.iperm;
+  d.sigma = F.sigma;
+  d.ew = F.ew;
+  d.ecol = F.ecol;
+  d.ew64 = F.ew64;
+  d.ew32 = F.ew32;
+  return d;
+}
 
 }  // namespace fv
 

@@ -252,34 +252,106 @@ __global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_tile(Lev
         const int i = rs + t;
         const double xo = ((double)xown[kk] - mu) * inv_s;
         double num = 0.0, den = 0.0;
-        for (int k = a; k < e; ++k) {
-          const double wj = (double)T.w[k];
-          const double xj = (double)T.x[k];
-          num += wj * (T.col[k] < r0 ? xj : (xj - mu) * inv_s);
-          den += wj;
-        }
-        double u = xo;
-        if (den > 0.0) {
-          const double g = (num + rho * xo) / den;
-          u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
-        }
-        const VT us = (VT)u;
+        for (int k = a; k < e; ++k)
+          gs_entry(num, den, (double)T.w[k], (double)T.x[k], T.col[k] < r0, mu, inv_s);
+        const VT us = (VT)gs_relax(num, den, xo, rho, omega);
         x[i] = us;
         const double ud = (double)us;
         double en = 0.0;
         for (int k = a; k < e; ++k)
-          if (T.col[k] < r0) {
-            const double d = ud - (double)T.x[k];
-            en += (double)T.w[k] * d * d;
-          }
-        acc[0] += ud;
-        acc[1] += ud * ud;
-        acc[2] += ud * xo;
-        acc[3] += xo;
-        acc[4] += en;
+          if (T.col[k] < r0) gs_energy(en, (double)T.w[k], ud, (double)T.x[k]);
+        gs_sums(acc, ud, xo, en);
       },
       [&](int t) { row_gs<VT>(rs + t, L, x, r0, mu, inv_s, rho, omega, acc); });
   if (!ran) return;
+  store_block_sum(acc, lds, part, stride, slot_base + blockIdx.x);
+}
+
+// ---- smoothing sweep, one colour, from the level's ELL copy ----------------
+
+template <class VT>
+struct EllW;
+template <>
+struct EllW<float> {
+  __device__ static const float* w(const LevelDesc& L) { return L.ew32; }
+};
+template <>
+struct EllW<double> {
+  __device__ static const double* w(const LevelDesc& L) { return L.ew64; }
+};
+
+// The rows, block-to-slot mapping, arithmetic and summation order of
+// k_gs_tile<VT, RPT>, so the two give bitwise-equal sweeps; the row's entries
+// come from the slot-major copy (EW slots, column -1 past the row's end)
+// straight into registers.  Entry k of the rows of a wave are consecutive
+// words, so the loads are coalesced and need no row pointers.  Two load
+// phases: the column indices (with the phase state), then the weights, the
+// row's own values and the gathers of the neighbour values together.  No LDS
+// staging and no barrier before the block's sum.
+template <class VT, int EW, int RPT>
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_ell(
+    LevelDesc L, int r0, int r1, VT* xa, VT* xb, const DevState* st, double* part, int stride,
+    int slot_base, double omega) {
+  __shared__ double lds[block_sum_lds(kBlock)];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int rs = r0 + b * RPT * kBlock;
+  const int n = L.n;
+  const int* __restrict__ ecol = L.ecol;
+  const VT* __restrict__ ew = EllW<VT>::w(L);
+  int done = st->done, cur = st->cur;
+  double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
+  int row[RPT];
+  int cc[RPT][EW];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    // rows past the colour repeat its last row (loaded, never written)
+    row[k] = min(rs + (int)threadIdx.x + k * kBlock, r1 - 1);
+#pragma unroll
+    for (int j = 0; j < EW; ++j) cc[k][j] = ecol[j * n + row[k]];
+  }
+  // The index loads and the phase state complete together here, before the
+  // stop flag is tested: the compiler would otherwise test the flag first and
+  // issue the index loads after it, and load the state after the flag, each a
+  // memory round trip of its own.  A launch after the phase has ended reads
+  // the indices and returns.
+#pragma unroll
+  for (int k = 0; k < RPT; ++k)
+#pragma unroll
+    for (int j = 0; j < EW; ++j) asm volatile("" : "+v"(cc[k][j]));
+  asm volatile("" : "+s"(done), "+s"(cur), "+s"(mu), "+s"(inv_s), "+s"(rho));
+  if (done) return;
+  VT* x = cur ? xb : xa;
+  VT ww[RPT][EW];
+  VT xown[RPT];
+  VT xg[RPT][EW];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+    for (int j = 0; j < EW; ++j) ww[k][j] = ew[j * n + row[k]];
+    xown[k] = x[row[k]];
+#pragma unroll
+    for (int j = 0; j < EW; ++j) xg[k][j] = x[cc[k][j] >= 0 ? cc[k][j] : row[k]];
+  }
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = rs + (int)threadIdx.x + k * kBlock;
+    if (i >= r1) continue;
+    const double xo = ((double)xown[k] - mu) * inv_s;
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int j = 0; j < EW; ++j)
+      if (cc[k][j] >= 0)
+        gs_entry(num, den, (double)ww[k][j], (double)xg[k][j], cc[k][j] < r0, mu, inv_s);
+    const VT us = (VT)gs_relax(num, den, xo, rho, omega);
+    x[i] = us;
+    const double ud = (double)us;
+    double en = 0.0;
+#pragma unroll
+    for (int j = 0; j < EW; ++j)
+      if (cc[k][j] >= 0 && cc[k][j] < r0) gs_energy(en, (double)ww[k][j], ud, (double)xg[k][j]);
+    gs_sums(acc, ud, xo, en);
+  }
   store_block_sum(acc, lds, part, stride, slot_base + blockIdx.x);
 }
 

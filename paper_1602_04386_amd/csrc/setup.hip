@@ -369,20 +369,59 @@ __global__ void k_extract(int n, const int* __restrict__ rp, const int* __restri
 // ---------------------------------------------------------------------------
 // Rows are strided over at most kDegreeGrid blocks: one atomicMax per block,
 // and atomics on one address serialise (one block per 256 rows of a
-// 1M-vertex level took ~50 us, nearly all of it in the atomics).
+// 1M-vertex level took ~50 us, nearly all of it in the atomics).  The same
+// pass finds the longest row (*lmax), which decides the level's ELL copy.
 constexpr int kDegreeGrid = 512;
 
 __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, const double* w,
-                                                     unsigned long long* dmax) {
+                                                     unsigned long long* dmax,
+                                                     unsigned long long* lmax) {
   __shared__ double lds[kBlock / 64];
-  double m = 0.0;
+  double m = 0.0, len = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     double d = 0.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) d += w[p];
+    const int a = rp[i], e = rp[i + 1];
+    for (int p = a; p < e; ++p) d += w[p];
     m = fmax(m, d);
+    len = fmax(len, (double)(e - a));
   }
   m = block_max(m, lds);
-  if (threadIdx.x == 0) atomicMax(dmax, (unsigned long long)__double_as_longlong(m));
+  len = block_max(len, lds);
+  if (threadIdx.x == 0) {
+    atomicMax(dmax, (unsigned long long)__double_as_longlong(m));
+    atomicMax(lmax, (unsigned long long)len);
+  }
+}
+
+// ELL copies (the sweeps' storage for near-regular levels): at least kEllMinRows
+// rows, at most kEllMaxWidth entries per row, padded to 4 or 8 slots with at
+// most an eighth more slots than entries.
+constexpr int kEllMinRows = 65536;
+constexpr int kEllMaxWidth = 8;
+
+static int ell_width(int n, long long m, long long longest) {
+  if (n < kEllMinRows || longest < 1 || longest > kEllMaxWidth) return 0;
+  const int ew = longest <= 4 ? 4 : 8;
+  if ((long long)ew * n > m + m / 8 || (long long)ew * n >= INT_MAX) return 0;
+  return ew;
+}
+
+// Slot-major copy of a level's solve-order matrix: entry k of row i goes to
+// k * n + i; the slots past the row's end hold column -1 and weight 0.
+__global__ void k_ell_fill(int n, int ew, const int* __restrict__ rp, const int* __restrict__ col,
+                           const double* __restrict__ w64, const float* __restrict__ w32,
+                           int* __restrict__ ecol, double* __restrict__ ew64,
+                           float* __restrict__ ew32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = rp[i], e = rp[i + 1];
+  for (int k = 0; k < ew; ++k) {
+    const int o = k * n + i;
+    const bool in = a + k < e;
+    ecol[o] = in ? col[a + k] : -1;
+    ew64[o] = in ? w64[a + k] : 0.0;
+    ew32[o] = in ? w32[a + k] : 0.0f;
+  }
 }
 
 // Neighbours loaded per batch by the matching and colouring kernels: every
@@ -1493,6 +1532,10 @@ static void free_level(fv_hierarchy* h, Level& L) {
   f(L.perm, n * sizeof(int));
   f(L.iperm, n * sizeof(int));
   f(L.qs, n * sizeof(int));
+  const size_t slots = (size_t)L.ew * n;
+  f(L.ecol, slots * sizeof(int));
+  f(L.ew64, slots * sizeof(double));
+  f(L.ew32, slots * sizeof(float));
   L = Level();
 }
 
@@ -1528,6 +1571,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
   int n_coarse = o ? o->n_coarse : 25;
   int max_levels = o ? o->max_levels : FV_MAX_LEVELS;
   unsigned long long cseed = o ? o->colour_seed : 0ULL;
+  const int ell = o ? o->ell : 0;
   if (n_coarse < 1) throw Error(FV_E_INVALID, "n_coarse < 1");
   if (max_levels < 1 || max_levels > FV_MAX_LEVELS) max_levels = FV_MAX_LEVELS;
 
@@ -1638,8 +1682,10 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     double* cw = tmp.get<double>(mcap);
     int* sJ = tmp.get<int>(mcap);
     double* sw = tmp.get<double>(mcap);
-    unsigned long long* dmax = tmp.get<unsigned long long>(FV_MAX_LEVELS);
-    FV_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned long long) * FV_MAX_LEVELS, s));
+    // [l]: level l's largest degree (bits of the double); [FV_MAX_LEVELS + l]: its
+    // longest row
+    unsigned long long* dmax = tmp.get<unsigned long long>(2 * FV_MAX_LEVELS);
+    FV_HIP(hipMemsetAsync(dmax, 0, sizeof(unsigned long long) * 2 * FV_MAX_LEVELS, s));
     // Per-round progress flags of the matching and colouring rounds.
     constexpr int kRoundCap = 4096;
     int* mflag = tmp.get<int>(kRoundCap);
@@ -1653,7 +1699,8 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     int l = 0;
     for (;;) {
       Level& F = h->lv[l];
-      k_degree_max<<<std::min(nblk(F.n), kDegreeGrid), kBlock, 0, s>>>(F.n, F.rp_c, F.w_c, dmax + l);
+      k_degree_max<<<std::min(nblk(F.n), kDegreeGrid), kBlock, 0, s>>>(F.n, F.rp_c, F.w_c, dmax + l,
+                                                                         dmax + FV_MAX_LEVELS + l);
       FV_HIP(hipGetLastError());
       if (F.n <= n_coarse || l + 1 >= max_levels) break;
       const int fn = F.n;
@@ -1901,16 +1948,16 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       R.off[k] = total;
       total += R.len[k];
     }
-    const size_t dm_bytes = sizeof(unsigned long long) * (J + 1);
+    const size_t dm_bytes = sizeof(unsigned long long) * 2 * FV_MAX_LEVELS;
     unsigned char* stage = tmp.get<unsigned char>(dm_bytes + sizeof(int) * 2 * total);
-    k_gather_ranges<<<1, kBlock, 0, s>>>(R, J, dmax, J + 1,
+    k_gather_ranges<<<1, kBlock, 0, s>>>(R, J, dmax, 2 * FV_MAX_LEVELS,
                                          reinterpret_cast<unsigned long long*>(stage),
                                          reinterpret_cast<int*>(stage + dm_bytes), total);
     FV_HIP(hipGetLastError());
     std::vector<unsigned char> host(dm_bytes + sizeof(int) * 2 * total);
     FV_HIP(hipMemcpyAsync(host.data(), stage, host.size(), hipMemcpyDeviceToHost, s));
     FV_HIP(hipStreamSynchronize(s));
-    std::vector<unsigned long long> dm(J + 1);
+    std::vector<unsigned long long> dm(2 * FV_MAX_LEVELS);
     std::memcpy(dm.data(), host.data(), dm_bytes);
     for (int k = 0; k < J; ++k) {
       Level& F = h->lv[k];
@@ -1933,24 +1980,24 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       std::memcpy(&d, &dm[k], sizeof(double));
       h->lv[k].sigma = 2.0 * d;
     }
+    // ELL copies of the near-regular levels the multi-workgroup sweeps visit.
+    for (int k = 0; k < J && ell >= 0; ++k) {
+      Level& F = h->lv[k];
+      const int ew = ell_width(F.n, F.m, (long long)dm[FV_MAX_LEVELS + k]);
+      if (!ew) continue;
+      const size_t slots = (size_t)ew * F.n;
+      F.ecol = halloc<int>(h, slots);
+      F.ew64 = halloc<double>(h, slots);
+      F.ew32 = halloc<float>(h, slots);
+      F.ew = ew;
+      k_ell_fill<<<nblk(F.n), kBlock, 0, s>>>(F.n, ew, F.rp, F.col, F.w64, F.w32, F.ecol, F.ew64,
+                                              F.ew32);
+      FV_HIP(hipGetLastError());
+    }
     // Device descriptors.
     std::vector<LevelDesc> d(FV_MAX_LEVELS);
     std::memset(d.data(), 0, sizeof(LevelDesc) * FV_MAX_LEVELS);
-    for (int k = 0; k <= J; ++k) {
-      const Level& F = h->lv[k];
-      d[k].n = F.n;
-      d[k].ncol = F.ncol;
-      d[k].m = F.m;
-      d[k].rp = F.rp;
-      d[k].col = F.col;
-      d[k].w64 = F.w64;
-      d[k].w32 = F.w32;
-      d[k].cptr = F.cptr;
-      d[k].qs = F.qs;
-      d[k].perm = F.perm;
-      d[k].iperm = F.iperm;
-      d[k].sigma = F.sigma;
-    }
+    for (int k = 0; k <= J; ++k) d[k] = desc_of(h->lv[k]);
     h->d_desc = static_cast<LevelDesc*>(
         dev_alloc(ctx, sizeof(LevelDesc) * FV_MAX_LEVELS, &h->bytes));
     FV_HIP(hipMemcpyAsync(h->d_desc, d.data(), sizeof(LevelDesc) * FV_MAX_LEVELS,

@@ -43,6 +43,50 @@ struct WSel<double> {
 // Per-row arithmetic.
 // ---------------------------------------------------------------------------
 
+// Row arithmetic of the multi-workgroup sweeps (the tile and ELL kernels, the
+// direct path of long rows and the finishing block's rows): one fixed
+// sequence of roundings (contraction off, the fused multiply-adds written
+// out), so that the kernels give bitwise-equal sweeps whatever the compiler
+// makes of the surrounding code.  Entry (wj, xj) of a row: xj is already this sweep's
+// value when `updated` (an earlier colour), else it still needs the pending
+// shift and scale.
+__device__ inline void gs_entry(double& num, double& den, double wj, double xj, bool updated,
+                                double mu, double inv_s) {
+#pragma clang fp contract(off)
+  num = fma(wj, updated ? xj : (xj - mu) * inv_s, num);
+  den = den + wj;
+}
+
+// The relaxed update of a row from its sums (the row's value xo when it has
+// no entries).
+__device__ inline double gs_relax(double num, double den, double xo, double rho,
+                                  double omega) {
+#pragma clang fp contract(off)
+  double u = xo;
+  if (den > 0.0) {
+    const double g = fma(rho, xo, num) / den;
+    u = omega == 1.0 ? g : fma(omega, g, (1.0 - omega) * xo);
+  }
+  return u;
+}
+
+// Adds w (u - xj)^2 of an edge to an earlier colour to the sweep's energy term.
+__device__ inline void gs_energy(double& en, double wj, double ud, double xj) {
+#pragma clang fp contract(off)
+  const double d = ud - xj;
+  en = fma(wj * d, d, en);
+}
+
+// Adds a row's terms to the sweep's sums.
+__device__ inline void gs_sums(double (&acc)[kNP], double ud, double xo, double en) {
+#pragma clang fp contract(off)
+  acc[0] = acc[0] + ud;
+  acc[1] = fma(ud, ud, acc[1]);
+  acc[2] = fma(ud, xo, acc[2]);
+  acc[3] = acc[3] + xo;
+  acc[4] = acc[4] + en;
+}
+
 // Shifted Gauss-Seidel update of row i (Algorithm 2 on (L - rho I) x = 0 with
 // the splitting (D - W_l) x' = (W_u + rho I) x):
 // x_i <- (sum_j w_ij x_j + rho xhat_i) / d_i, relaxed by omega (an eigenvector
@@ -63,32 +107,17 @@ __device__ inline void row_gs(int i, const LevelDesc& L, VT* __restrict__ x, int
   double num = 0.0, den = 0.0;
   for (int p = p0; p < p1; ++p) {
     const int j = col[p];
-    const double wj = (double)w[p];
-    const double xj = (double)x[j];
-    num += wj * (j < lower_end ? xj : (xj - mu) * inv_s);
-    den += wj;
+    gs_entry(num, den, (double)w[p], (double)x[j], j < lower_end, mu, inv_s);
   }
-  double u = xo;
-  if (den > 0.0) {
-    const double g = (num + rho * xo) / den;
-    u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
-  }
-  const VT us = (VT)u;
+  const VT us = (VT)gs_relax(num, den, xo, rho, omega);
   x[i] = us;
   const double ud = (double)us;
   double e = 0.0;
   for (int p = p0; p < p1; ++p) {
     const int j = col[p];
-    if (j < lower_end) {
-      const double d = ud - (double)x[j];
-      e += (double)w[p] * d * d;
-    }
+    if (j < lower_end) gs_energy(e, (double)w[p], ud, (double)x[j]);
   }
-  acc[0] += ud;
-  acc[1] += ud * ud;
-  acc[2] += ud * xo;
-  acc[3] += xo;
-  acc[4] += e;
+  gs_sums(acc, ud, xo, e);
 }
 
 // row_gs with the row's pointers given and its neighbours fetched kRowB at a
@@ -125,10 +154,7 @@ __device__ inline void row_gs_batched(int i, int p0, int p1, const LevelDesc& L,
     batch(pb, jj, ww, xx);
 #pragma unroll
     for (int u = 0; u < kRowB; ++u)
-      if (pb + u < p1) {
-        num += ww[u] * (jj[u] < lower_end ? xx[u] : (xx[u] - mu) * inv_s);
-        den += ww[u];
-      }
+      if (pb + u < p1) gs_entry(num, den, ww[u], xx[u], jj[u] < lower_end, mu, inv_s);
     if (pb == p0)
 #pragma unroll
       for (int u = 0; u < kRowB; ++u) {
@@ -137,38 +163,23 @@ __device__ inline void row_gs_batched(int i, int p0, int p1, const LevelDesc& L,
         x0[u] = xx[u];
       }
   }
-  double u = xo;
-  if (den > 0.0) {
-    const double g = (num + rho * xo) / den;
-    u = omega == 1.0 ? g : (1.0 - omega) * xo + omega * g;
-  }
-  const VT us = (VT)u;
+  const VT us = (VT)gs_relax(num, den, xo, rho, omega);
   x[i] = us;
   const double ud = (double)us;
   double e = 0.0;
   if (p1 > p0)
 #pragma unroll
     for (int u = 0; u < kRowB; ++u)
-      if (p0 + u < p1 && j0[u] < lower_end) {
-        const double d = ud - x0[u];
-        e += w0[u] * d * d;
-      }
+      if (p0 + u < p1 && j0[u] < lower_end) gs_energy(e, w0[u], ud, x0[u]);
   for (int pb = p0 + kRowB; pb < p1; pb += kRowB) {
     int jj[kRowB];
     double ww[kRowB], xx[kRowB];
     batch(pb, jj, ww, xx);
 #pragma unroll
     for (int u = 0; u < kRowB; ++u)
-      if (pb + u < p1 && jj[u] < lower_end) {
-        const double d = ud - xx[u];
-        e += ww[u] * d * d;
-      }
+      if (pb + u < p1 && jj[u] < lower_end) gs_energy(e, ww[u], ud, xx[u]);
   }
-  acc[0] += ud;
-  acc[1] += ud * ud;
-  acc[2] += ud * xo;
-  acc[3] += xo;
-  acc[4] += e;
+  gs_sums(acc, ud, xo, e);
 }
 
 // Power-iteration step of row i: y_i = sigma xhat_i - (L xhat)_i with
@@ -650,7 +661,19 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
           const int r0 = Lh.cptr_h[c], r1 = Lh.cptr_h[c + 1];
           hipEvent_t* ev = timer ? timer->pair() : nullptr;
           if (ev) FV_HIP(hipEventRecord(ev[0], s));
-          if (rpt[c] == 2)
+          if (L.ew == 4 && rpt[c] == 2)
+            k_gs_ell<VT, 4, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
+                                                         W.stride, base, omega);
+          else if (L.ew == 4)
+            k_gs_ell<VT, 4, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
+                                                         W.stride, base, omega);
+          else if (L.ew == 8 && rpt[c] == 2)
+            k_gs_ell<VT, 8, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
+                                                         W.stride, base, omega);
+          else if (L.ew == 8)
+            k_gs_ell<VT, 8, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
+                                                         W.stride, base, omega);
+          else if (rpt[c] == 2)
             k_gs_tile<VT, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
                                                        base, omega);
           else
@@ -710,23 +733,7 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
   return false;
 }
 
-static LevelDesc host_desc(const Level& F) {
-  LevelDesc d;
-  std::memset(&d, 0, sizeof(d));
-  d.n = F.n;
-  d.ncol = F.ncol;
-  d.m = F.m;
-  d.rp = F.rp;
-  d.col = F.col;
-  d.w64 = F.w64;
-  d.w32 = F.w32;
-  d.cptr = F.cptr;
-  d.qs = F.qs;
-  d.perm = F.perm;
-  d.iperm = F.iperm;
-  d.sigma = F.sigma;
-  return d;
-}
+static LevelDesc host_desc(const Level& F) { return desc_of(F); }
 
 static void fill_task(GraphTask& T, const fv_hierarchy* h, const fv_solve_opts* o, int stop,
                       void* xa, void* xb, double* lx, double* x_out, DevState* st,
