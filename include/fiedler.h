@@ -89,12 +89,13 @@ typedef struct {
 /* Setup options (Algorithm 3, Step 1).  Coarsen while a level has more than
  * n_coarse vertices (the text asks for about 25), for at most max_levels
  * levels.  colour_seed seeds the smoother's colouring.  ell chooses the
- * storage the smoothing sweeps read: with 0, a level of at least 65,536 rows
- * whose longest row has at most 8 entries, and whose rows padded to 4 or 8
- * entries add at most an eighth to its entries, also keeps a slot-major (ELL)
- * copy of its solve-order matrix (16 bytes per slot, counted in
- * fv_hierarchy_bytes) that its sweeps read instead of the CSR arrays; -1
- * keeps CSR only.  The two give bitwise-equal solves. */
+ * storage the smoothing sweeps read: with 0, a level of more than 8,192 rows
+ * whose longest row has at most 16 entries also keeps a slot-major (ELL) copy
+ * of its solve-order matrix, rows padded to a multiple of 4 slots (16 bytes
+ * per slot, counted in fv_hierarchy_bytes), when the padding adds at most an
+ * eighth to its entries or at most 4 MiB of FP32 index and weight per colour;
+ * its sweeps then read that copy instead of the CSR arrays.  -1 keeps CSR
+ * only.  The two give bitwise-equal solves. */
 typedef struct {
   int32_t n_coarse;     /* default 25 */
   int32_t max_levels;   /* default and maximum FV_MAX_LEVELS */

@@ -288,8 +288,15 @@ struct EllW<double> {
 // phases: the column indices (with the phase state), then the weights, the
 // row's own values and the gathers of the neighbour values together.  No LDS
 // staging and no barrier before the block's sum.
+// Waves per SIMD the ELL sweep asks the compiler to leave room for: those of
+// the tile sweep of the same rows per thread (the same block counts then run
+// in one round), four for rows of 12 or 16 slots (their registers: 16 index,
+// weight and gathered values per row), which only the smaller levels have.
 template <class VT, int EW, int RPT>
-__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_ell(
+constexpr int ell_waves() { return EW <= 8 ? tile_waves<VT, RPT>() : 4; }
+
+template <class VT, int EW, int RPT>
+__global__ __launch_bounds__(kBlock, (ell_waves<VT, EW, RPT>())) void k_gs_ell(
     LevelDesc L, int r0, int r1, VT* xa, VT* xb, const DevState* st, double* part, int stride,
     int slot_base, double omega) {
   __shared__ double lds[block_sum_lds(kBlock)];

@@ -393,17 +393,25 @@ __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, con
   }
 }
 
-// ELL copies (the sweeps' storage for near-regular levels): at least kEllMinRows
-// rows, at most kEllMaxWidth entries per row, padded to 4 or 8 slots with at
-// most an eighth more slots than entries.
-constexpr int kEllMinRows = 65536;
-constexpr int kEllMaxWidth = 8;
+// ELL copies (the sweeps' storage for near-regular levels).  A level that
+// the multi-workgroup sweeps visit (more than kEllMinRows rows) whose longest
+// row has at most kEllMaxWidth entries gets rows of 4, 8, 12 or 16 slots when
+// the padding is cheap: at most an eighth more slots than entries, or at most
+// kEllPadBytes of padding read per colour launch (FP32 index and weight).  A
+// CSR tile launch pays a dependent load phase (the row pointers) that the
+// ELL launch does not, worth about that many bytes at the bandwidth such
+// launches reach.
+constexpr int kEllMinRows = 8192;
+constexpr int kEllMaxWidth = 16;
+constexpr long long kEllPadBytes = 4LL << 20;
 
-static int ell_width(int n, long long m, long long longest) {
-  if (n < kEllMinRows || longest < 1 || longest > kEllMaxWidth) return 0;
-  const int ew = longest <= 4 ? 4 : 8;
-  if ((long long)ew * n > m + m / 8 || (long long)ew * n >= INT_MAX) return 0;
-  return ew;
+static int ell_width(int n, long long m, int ncol, long long longest) {
+  if (n <= kEllMinRows || longest < 1 || longest > kEllMaxWidth) return 0;
+  const int ew = (int)((longest + 3) / 4) * 4;
+  const long long slots = (long long)ew * n;
+  if (slots >= INT_MAX) return 0;
+  if (slots <= m + m / 8 || (slots - m) * 8 <= kEllPadBytes * std::max(ncol, 1)) return ew;
+  return 0;
 }
 
 // Slot-major copy of a level's solve-order matrix: entry k of row i goes to
@@ -1983,7 +1991,7 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     // ELL copies of the near-regular levels the multi-workgroup sweeps visit.
     for (int k = 0; k < J && ell >= 0; ++k) {
       Level& F = h->lv[k];
-      const int ew = ell_width(F.n, F.m, (long long)dm[FV_MAX_LEVELS + k]);
+      const int ew = ell_width(F.n, F.m, F.ncol, (long long)dm[FV_MAX_LEVELS + k]);
       if (!ew) continue;
       const size_t slots = (size_t)ew * F.n;
       F.ecol = halloc<int>(h, slots);

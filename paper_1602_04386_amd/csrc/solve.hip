@@ -673,6 +673,12 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
           else if (L.ew == 8)
             k_gs_ell<VT, 8, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
                                                          W.stride, base, omega);
+          else if (L.ew == 12 && rpt[c] == 1)
+            k_gs_ell<VT, 12, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
+                                                          W.stride, base, omega);
+          else if (L.ew == 16 && rpt[c] == 1)
+            k_gs_ell<VT, 16, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
+                                                          W.stride, base, omega);
           else if (rpt[c] == 2)
             k_gs_tile<VT, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
                                                        base, omega);
