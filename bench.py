@@ -99,13 +99,13 @@ def pass_bytes(n, m, prec):
     return (8 * m + 4 * (n + 1) + 8 * n) if prec == "fp32" else (12 * m + 4 * (n + 1) + 16 * n)
 
 
-def measured_traffic(prec, name):
-    """HBM bytes per level-0 colour launch of workload `name`, from the
-    calibrated FETCH_SIZE / WRITE_SIZE passes summarised in profiles/; None when
-    the kernel sources changed since those counters were taken."""
+def measured_traffic(prec, name, kernel):
+    """HBM bytes per level-0 colour launch of `kernel` on workload `name`, from
+    the calibrated FETCH_SIZE / WRITE_SIZE passes summarised in profiles/; None
+    when the kernel sources changed since those counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"k_gs_tile_{name}_fp32_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_fp32_traffic.json")
     if prec != "fp32" or not os.path.exists(path):
         return None
     with open(path) as f:
@@ -117,10 +117,21 @@ def measured_traffic(prec, name):
     return rec["traffic_bytes"] if sha.hexdigest() == rec["source_sha256"] else None
 
 
-def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name, traffic_name=None):
+def level0_kernel(h):
+    """The smoothing kernel level 0's colour launches run: the ELL sweep when
+    the level has an ELL copy, else the CSR tile sweep."""
+    return "k_gs_ell" if h.ell_width(0) else "k_gs_tile"
+
+
+def level0_roofline(fv, ctx, h, x, prec, sweeps, traffic_name=None):
     """Device time of one level-0 sweep from two replayed schedules that differ
     only in the number of level-0 sweeps (HIP events inside the library)."""
     import numpy as np
+
+    kernel_name = level0_kernel(h)
+    vt = "float" if prec == "fp32" else "double"
+    label = (f"{kernel_name}<{vt}, {h.ell_width(0)}> (level 0, ELL)" if h.ell_width(0)
+             else f"{kernel_name}<{vt}> (level 0)")
 
     J = h.levels - 1
     S0, S1 = 2, 2 + sweeps
@@ -134,7 +145,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name, traffic_name=None)
 
     t_a, t_b = dev_ms(S0), dev_ms(S1)
     log(f"roofline replays: {S0} sweeps {t_a:.3f} ms, {S1} sweeps {t_b:.3f} ms")
-    traffic = measured_traffic(prec, traffic_name) if traffic_name else None
+    traffic = measured_traffic(prec, traffic_name, kernel_name) if traffic_name else None
     t_sweep_ms = (t_b - t_a) / (S1 - S0)
     n0, m0 = h.n[0], h.nnz[0]
     # Colour launches per sweep: the last colours, when they hold at most 512
@@ -148,7 +159,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, kernel_name, traffic_name=None)
     bytes_sweep = pass_bytes(n0, m0, prec)
     achieved = bytes_sweep / (t_sweep_ms * 1e-3) / 1e9
     return {
-        "kernel": f"{kernel_name}<{'float' if prec == 'fp32' else 'double'}> (level 0)",
+        "kernel": label,
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -232,8 +243,7 @@ def single_graph(args, g, solve, metric, workload, cpu_fn, require_converged=Tru
     fv.fiedler_solve(ctx, h, x_out=x, prec=args.prec, **solve)
     t_solve = (time.perf_counter() - ts) * 1e3
     J = h.levels - 1
-    roof = level0_roofline(fv, ctx, h, x, args.prec, args.roofline_sweeps, "k_gs_tile",
-                           traffic_name)
+    roof = level0_roofline(fv, ctx, h, x, args.prec, args.roofline_sweeps, traffic_name)
     # The same solve once more with a HIP event pair around every level-0
     # smoothing launch (untimed: the events cost ~7 % of a step): each launch's
     # time from its own events, which include its dispatch.
@@ -956,7 +966,8 @@ def run_counters_probe(args):
                          replay=[0] + [0, 0] * (J - 1) + [args.probe_sweeps, 0])
     out = {"probe": "counters", "workload": args.workload, "copy_bytes": nbytes,
            "level0_sweeps": args.probe_sweeps,
-           "level0_colours": h.colours[0], "bytes_per_sweep": pass_bytes(h.n[0], h.nnz[0], args.prec),
+           "level0_colours": h.colours[0], "level0_kernel": level0_kernel(h),
+           "bytes_per_sweep": pass_bytes(h.n[0], h.nnz[0], args.prec),
            "level0_rows": h.n[0], "level0_nnz": h.nnz[0], "t_solve_ms": r.t_solve_ms}
     h.free()
     ctx.close()

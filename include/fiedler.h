@@ -200,6 +200,10 @@ fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, 
  * budget while the hierarchy lives).  FV_E_INVALID for a NULL argument. */
 fv_status fv_hierarchy_bytes(const fv_hierarchy* h, int64_t* bytes);
 
+/* Slots per row of level `level`'s ELL copy (fv_hier_opts.ell), 0 when its
+ * sweeps read CSR.  FV_E_INVALID for a NULL argument or a level out of range. */
+fv_status fv_hierarchy_ell_width(const fv_hierarchy* h, int32_t level, int32_t* width);
+
 /* Copies level `level` to host buffers in the canonical numbering (vertices of
  * a coarse level numbered by their aggregate's smallest member): row_ptr[n+1],
  * col[nnz], w[nnz] (off-diagonal weights), q[n] (aggregate of each vertex in

@@ -101,6 +101,7 @@ class fv_result(C.Structure):
 
 EXPORTS = ["fv_hier_opts_default", "fv_solve_opts_default", "fv_context_create",
            "fv_context_destroy", "fv_build_hierarchy", "fv_build_hierarchies", "fv_hierarchy_info", "fv_hierarchy_bytes",
+           "fv_hierarchy_ell_width",
            "fv_hierarchy_export_level", "fv_free_hierarchy", "fv_fiedler_solve",
            "fv_fiedler_solve_noalloc", "fv_fiedler_solve_batch", "fv_fiedler_solve_batch_ex",
            "fv_batch_opts_default", "fv_spectral_partition", "fv_server_create", "fv_submit", "fv_poll",
@@ -279,6 +280,13 @@ class Hierarchy:
         b = C.c_int64()
         _check(lib().fv_hierarchy_bytes(self._h, C.byref(b)), "fv_hierarchy_bytes")
         return b.value
+
+    def ell_width(self, level: int) -> int:
+        """fv_hierarchy_ell_width: slots per row of the level's ELL copy (0: CSR)."""
+        w = C.c_int32()
+        _check(lib().fv_hierarchy_ell_width(self._h, int(level), C.byref(w)),
+               "fv_hierarchy_ell_width")
+        return w.value
 
     def export_level(self, level: int) -> LevelExport:
         n, m = self.n[level], self.nnz[level]

@@ -341,6 +341,12 @@ fv_status fv_hierarchy_bytes(const fv_hierarchy* h, int64_t* bytes) {
   return FV_OK;
 }
 
+fv_status fv_hierarchy_ell_width(const fv_hierarchy* h, int32_t level, int32_t* width) {
+  if (!h || !width || level < 0 || level >= h->levels) return FV_E_INVALID;
+  *width = h->lv[level].ew;
+  return FV_OK;
+}
+
 fv_status fv_hierarchy_export_level(const fv_hierarchy* h, int32_t level, int32_t* row_ptr,
                                     int32_t* col, double* w, int32_t* q, int32_t* colour) {
   if (!h || level < 0 || level >= h->levels) return FV_E_INVALID;

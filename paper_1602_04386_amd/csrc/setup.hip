@@ -403,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, con
 // launches reach.
 constexpr int kEllMinRows = 8192;
 constexpr int kEllMaxWidth = 16;
-constexpr long long kEllPadBytes = 4LL << 20;
+constexpr long long kEllPadBytes = 8LL << 20;
 
 static int ell_width(int n, long long m, int ncol, long long longest) {
   if (n <= kEllMinRows || longest < 1 || longest > kEllMaxWidth) return 0;
