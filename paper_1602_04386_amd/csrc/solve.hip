@@ -493,12 +493,18 @@ static inline int nblk(long long n, int b = kBlock) {
   return (int)std::max<long long>(1, (n + b - 1) / b);
 }
 
-// Rows per thread of a tile pass over `rows` rows: two when tiles of kBlock
-// rows would need more than one round of resident blocks (the CU count times
-// the blocks per CU that the tile's LDS allows), one otherwise (more, smaller
-// blocks spread a small level over more CUs).  FV_TILE_RPT=1 or 2 forces it.
+// Rows per thread of a tile pass over `rows` rows holding `entries` entries:
+// two when tiles of kBlock rows would need more than one round of resident
+// blocks (the CU count times the blocks per CU that the tile's LDS allows) and
+// a tile of two rows per thread still fits one staging chunk on average (at
+// most four entries a row), one otherwise: more, smaller blocks spread a small
+// level over more CUs, and on denser levels a two-row tile takes two or three
+// chunks, each two more dependent load phases (the 4M-point random geometric
+// graph's level-0 sweep: 281 us with two rows per thread, 256 us with one).
+// The ELL sweep takes the same count, so both give the same block sums.
+// FV_TILE_RPT=1 or 2 forces it.
 template <class VT>
-static int tile_rpt(long long rows) {
+static int tile_rpt(long long rows, long long entries) {
   static const long long one_round = [] {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
@@ -510,7 +516,7 @@ static int tile_rpt(long long rows) {
     return e ? std::atoi(e) : 0;
   }();
   if (forced == 1 || forced == 2) return forced;
-  return rows > one_round ? 2 : 1;
+  return rows > one_round && entries <= 4 * rows ? 2 : 1;
 }
 
 // Allows an engine instantiation the dynamic LDS it is launched with (more
@@ -646,11 +652,11 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
   int nslots = 0;
   for (int c = 0; c < ct; ++c) {
     const int rows = Lh.cptr_h[c + 1] - Lh.cptr_h[c];
-    rpt[c] = tile_rpt<VT>(rows);
+    rpt[c] = tile_rpt<VT>(rows, Lh.cnnz_h[c + 1] - Lh.cnnz_h[c]);
     nbs[c] = nblk(rows, kBlock * rpt[c]);
     nslots += nbs[c];
   }
-  const int pi_rpt = tile_rpt<VT>(L.n);
+  const int pi_rpt = tile_rpt<VT>(L.n, L.m);
   const int pi_nb = nblk(L.n, kBlock * pi_rpt);
   if (nslots > W.stride) throw Error(FV_E_DEVICE, "partial-sum slots exceeded");
   auto enqueue = [&](int k) {
@@ -913,7 +919,7 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
       const Level& F = h->lv[l];
       const LevelDesc L = host_desc(F);
       // (from the FP64 coarsest vector: one row per thread)
-      const int prpt = l == J - 1 ? 1 : tile_rpt<VT>(F.n);
+      const int prpt = l == J - 1 ? 1 : tile_rpt<VT>(F.n, F.m);
       const int nb = nblk(F.n, kBlock * prpt);
       if (l == J - 1) {
         k_prolong_tile<double, VT, 1><<<nb, kBlock, 0, s>>>(
