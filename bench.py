@@ -118,9 +118,9 @@ def measured_traffic(prec, name, kernel):
 
 
 def level0_kernel(h):
-    """The smoothing kernel level 0's colour launches run: the ELL sweep when
-    the level has an ELL copy, else the CSR tile sweep."""
-    return "k_gs_ell" if h.ell_width(0) else "k_gs_tile"
+    """The smoothing kernel of level 0's largest colour (colour 0): the ELL
+    sweep when the colour has an ELL block, else the CSR tile sweep."""
+    return "k_gs_ell" if h.ell_width(0, 0) else "k_gs_tile"
 
 
 def level0_roofline(fv, ctx, h, x, prec, sweeps, traffic_name=None):
@@ -130,7 +130,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, traffic_name=None):
 
     kernel_name = level0_kernel(h)
     vt = "float" if prec == "fp32" else "double"
-    label = (f"{kernel_name}<{vt}, {h.ell_width(0)}> (level 0, ELL)" if h.ell_width(0)
+    label = (f"{kernel_name}<{vt}, {h.ell_width(0, 0)}> (level 0, ELL)" if h.ell_width(0, 0)
              else f"{kernel_name}<{vt}> (level 0)")
 
     J = h.levels - 1
@@ -170,6 +170,7 @@ def level0_roofline(fv, ctx, h, x, prec, sweeps, traffic_name=None):
         "launches_per_sweep": c0,
         "avg_launch_us": round(t_sweep_ms * 1e3 / c0, 3),
         "sweep_us": round(t_sweep_ms * 1e3, 3),
+        "ell_launches_per_sweep": sum(1 for c in range(c0) if h.ell_width(0, c)),
     }
 
 

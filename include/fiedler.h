@@ -89,13 +89,14 @@ typedef struct {
 /* Setup options (Algorithm 3, Step 1).  Coarsen while a level has more than
  * n_coarse vertices (the text asks for about 25), for at most max_levels
  * levels.  colour_seed seeds the smoother's colouring.  ell chooses the
- * storage the smoothing sweeps read: with 0, a level of more than 8,192 rows
- * whose longest row has at most 16 entries also keeps a slot-major (ELL) copy
- * of its solve-order matrix, rows padded to a multiple of 4 slots (16 bytes
- * per slot, counted in fv_hierarchy_bytes), when the padding adds at most an
- * eighth to its entries or at most 4 MiB of FP32 index and weight per colour;
- * its sweeps then read that copy instead of the CSR arrays.  -1 keeps CSR
- * only.  The two give bitwise-equal solves. */
+ * storage the smoothing sweeps read: with 0, on a level of more than 8,192
+ * rows whose longest row has at most 32 entries, each of the first 32 colours
+ * also keeps a slot-major (ELL) block of its rows of the solve-order matrix,
+ * every row padded to the level's longest rounded up to a multiple of 4 slots
+ * (16 bytes per slot, counted in fv_hierarchy_bytes), when the padding adds at
+ * most an eighth to the colour's entries or at most 8 MiB of FP32 index and
+ * weight; the colour's sweep launches then read that block instead of the CSR
+ * arrays.  -1 keeps CSR only.  The two give bitwise-equal solves. */
 typedef struct {
   int32_t n_coarse;     /* default 25 */
   int32_t max_levels;   /* default and maximum FV_MAX_LEVELS */
@@ -200,9 +201,13 @@ fv_status fv_hierarchy_info(const fv_hierarchy* h, int32_t* levels, int32_t* n, 
  * budget while the hierarchy lives).  FV_E_INVALID for a NULL argument. */
 fv_status fv_hierarchy_bytes(const fv_hierarchy* h, int64_t* bytes);
 
-/* Slots per row of level `level`'s ELL copy (fv_hier_opts.ell), 0 when its
- * sweeps read CSR.  FV_E_INVALID for a NULL argument or a level out of range. */
-fv_status fv_hierarchy_ell_width(const fv_hierarchy* h, int32_t level, int32_t* width);
+/* Slots per row of the ELL block of colour `colour` of level `level` (its
+ * smoothing launches read it; fv_hier_opts.ell), 0 when that colour is swept
+ * from CSR (colours count in solve order, as fv_hierarchy_export_level's
+ * colour array numbers them).  FV_E_INVALID for a NULL argument or a level
+ * out of range. */
+fv_status fv_hierarchy_ell_width(const fv_hierarchy* h, int32_t level, int32_t colour,
+                                 int32_t* width);
 
 /* Copies level `level` to host buffers in the canonical numbering (vertices of
  * a coarse level numbered by their aggregate's smallest member): row_ptr[n+1],

@@ -281,10 +281,11 @@ class Hierarchy:
         _check(lib().fv_hierarchy_bytes(self._h, C.byref(b)), "fv_hierarchy_bytes")
         return b.value
 
-    def ell_width(self, level: int) -> int:
-        """fv_hierarchy_ell_width: slots per row of the level's ELL copy (0: CSR)."""
+    def ell_width(self, level: int, colour: int = 0) -> int:
+        """fv_hierarchy_ell_width: slots per row of the ELL block of a colour of
+        a level (0: swept from CSR)."""
         w = C.c_int32()
-        _check(lib().fv_hierarchy_ell_width(self._h, int(level), C.byref(w)),
+        _check(lib().fv_hierarchy_ell_width(self._h, int(level), int(colour), C.byref(w)),
                "fv_hierarchy_ell_width")
         return w.value
 

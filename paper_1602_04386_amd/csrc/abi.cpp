@@ -341,9 +341,10 @@ fv_status fv_hierarchy_bytes(const fv_hierarchy* h, int64_t* bytes) {
   return FV_OK;
 }
 
-fv_status fv_hierarchy_ell_width(const fv_hierarchy* h, int32_t level, int32_t* width) {
+fv_status fv_hierarchy_ell_width(const fv_hierarchy* h, int32_t level, int32_t colour,
+                                 int32_t* width) {
   if (!h || !width || level < 0 || level >= h->levels) return FV_E_INVALID;
-  *width = h->lv[level].ew;
+  *width = h->lv[level].ell_width(colour);
   return FV_OK;
 }
 

@@ -86,10 +86,10 @@ struct LevelDesc {
   const int* perm;   // original index -> solve position
   const int* iperm;  // solve position -> original index
   double sigma;
-  // Slot-major (ELL) copy of the solve-order matrix, or ew == 0: entry k of
-  // row i at ecol[k * n + i] (CSR order; padding slots hold column -1 and
-  // weight 0), ew slots per row.
-  int ew;
+  // Slot-major (ELL) blocks of some colours of the solve-order matrix (null:
+  // none): colour c's block starts at the host's Level::ecoff[c]; entry k of
+  // its row r0 + i at k * rows + i (CSR order; padding slots hold column -1
+  // and weight 0).
   const int* ecol;
   const double* ew64;
   const float* ew32;
@@ -144,11 +144,16 @@ struct Level {
   int* perm = nullptr;
   int* iperm = nullptr;
   int* qs = nullptr;
-  // slot-major copy for the smoothing sweeps (ew slots per row; 0: none)
+  // Slot-major (ELL) blocks for the smoothing sweeps: ew slots per row (0:
+  // none); ecoff[c] the slot offset of colour c's block, or -1 when colour c
+  // is swept from CSR; eslots the slots of all blocks.
   int ew = 0;
+  std::vector<long long> ecoff;
+  long long eslots = 0;
   int* ecol = nullptr;
   double* ew64 = nullptr;
   float* ew32 = nullptr;
+  int ell_width(int c) const { return c >= 0 && c < (int)ecoff.size() && ecoff[c] >= 0 ? ew : 0; }
 };
 
 // The device descriptor of a level.
@@ -167,7 +172,6 @@ inline LevelDesc desc_of(const Level& F) {
   d.perm = F.perm;
   d.iperm = F.iperm;
   d.sigma = F.sigma;
-  d.ew = F.ew;
   d.ecol = F.ecol;
   d.ew64 = F.ew64;
   d.ew32 = F.ew32;

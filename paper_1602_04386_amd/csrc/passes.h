@@ -269,42 +269,31 @@ __global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_tile(Lev
 
 // ---- smoothing sweep, one colour, from the level's ELL copy ----------------
 
-template <class VT>
-struct EllW;
-template <>
-struct EllW<float> {
-  __device__ static const float* w(const LevelDesc& L) { return L.ew32; }
-};
-template <>
-struct EllW<double> {
-  __device__ static const double* w(const LevelDesc& L) { return L.ew64; }
-};
-
 // The rows, block-to-slot mapping, arithmetic and summation order of
 // k_gs_tile<VT, RPT>, so the two give bitwise-equal sweeps; the row's entries
-// come from the slot-major copy (EW slots, column -1 past the row's end)
-// straight into registers.  Entry k of the rows of a wave are consecutive
+// come from the colour's slot-major block (ec, ev: entry k of row r0 + i at
+// k * (r1 - r0) + i; EW slots, column -1 past the row's end) straight into
+// registers.  Entry k of the rows of a wave are consecutive
 // words, so the loads are coalesced and need no row pointers.  Two load
 // phases: the column indices (with the phase state), then the weights, the
 // row's own values and the gathers of the neighbour values together.  No LDS
 // staging and no barrier before the block's sum.
 // Waves per SIMD the ELL sweep asks the compiler to leave room for: those of
 // the tile sweep of the same rows per thread (the same block counts then run
-// in one round), four for rows of 12 or 16 slots (their registers: 16 index,
-// weight and gathered values per row), which only the smaller levels have.
+// in one round), four for rows of 12 or 16 slots and two for wider rows
+// (their registers: an index, a weight and a gathered value per slot), which
+// only smaller colours have.
 template <class VT, int EW, int RPT>
-constexpr int ell_waves() { return EW <= 8 ? tile_waves<VT, RPT>() : 4; }
+constexpr int ell_waves() { return EW <= 8 ? tile_waves<VT, RPT>() : EW <= 16 ? 4 : 2; }
 
 template <class VT, int EW, int RPT>
 __global__ __launch_bounds__(kBlock, (ell_waves<VT, EW, RPT>())) void k_gs_ell(
-    LevelDesc L, int r0, int r1, VT* xa, VT* xb, const DevState* st, double* part, int stride,
-    int slot_base, double omega) {
+    int r0, int r1, const int* __restrict__ ec, const VT* __restrict__ ev, VT* xa, VT* xb,
+    const DevState* st, double* part, int stride, int slot_base, double omega) {
   __shared__ double lds[block_sum_lds(kBlock)];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int rs = r0 + b * RPT * kBlock;
-  const int n = L.n;
-  const int* __restrict__ ecol = L.ecol;
-  const VT* __restrict__ ew = EllW<VT>::w(L);
+  const int rows = r1 - r0;
   int done = st->done, cur = st->cur;
   double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
   int row[RPT];
@@ -314,7 +303,7 @@ __global__ __launch_bounds__(kBlock, (ell_waves<VT, EW, RPT>())) void k_gs_ell(
     // rows past the colour repeat its last row (loaded, never written)
     row[k] = min(rs + (int)threadIdx.x + k * kBlock, r1 - 1);
 #pragma unroll
-    for (int j = 0; j < EW; ++j) cc[k][j] = ecol[j * n + row[k]];
+    for (int j = 0; j < EW; ++j) cc[k][j] = ec[j * rows + row[k] - r0];
   }
   // The index loads and the phase state complete together here, before the
   // stop flag is tested: the compiler would otherwise test the flag first and
@@ -334,7 +323,7 @@ __global__ __launch_bounds__(kBlock, (ell_waves<VT, EW, RPT>())) void k_gs_ell(
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
 #pragma unroll
-    for (int j = 0; j < EW; ++j) ww[k][j] = ew[j * n + row[k]];
+    for (int j = 0; j < EW; ++j) ww[k][j] = ev[j * rows + row[k] - r0];
     xown[k] = x[row[k]];
 #pragma unroll
     for (int j = 0; j < EW; ++j) xg[k][j] = x[cc[k][j] >= 0 ? cc[k][j] : row[k]];

@@ -393,38 +393,77 @@ __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, con
   }
 }
 
-// ELL copies (the sweeps' storage for near-regular levels).  A level that
-// the multi-workgroup sweeps visit (more than kEllMinRows rows) whose longest
-// row has at most kEllMaxWidth entries gets rows of 4, 8, 12 or 16 slots when
-// the padding is cheap: at most an eighth more slots than entries, or at most
-// kEllPadBytes of padding read per colour launch (FP32 index and weight).  A
-// CSR tile launch pays a dependent load phase (the row pointers) that the
+// ELL blocks (the sweeps' storage for the rows of regular enough colours).  On
+// a level that the multi-workgroup sweeps visit (more than kEllMinRows rows)
+// whose longest row has at most kEllMaxWidth entries, every row gets that
+// length rounded up to a multiple of 4 slots, and each of the first
+// kEllMaxCol colours gets a block when its padding is cheap: at most an eighth
+// more slots than entries, or at most kEllPadBytes of padding read per launch
+// (FP32 index and weight).  A CSR tile launch pays a dependent load phase
+// (the row pointers), and on dense rows more (one per staging chunk), that the
 // ELL launch does not, worth about that many bytes at the bandwidth such
-// launches reach.
+// launches reach.  So large near-regular colours (grid levels) and the small
+// dense colours of irregular levels (the last colours of a random geometric
+// graph) take ELL; the large colours of irregular levels keep CSR.
 constexpr int kEllMinRows = 8192;
-constexpr int kEllMaxWidth = 16;
+constexpr int kEllMaxWidth = 32;
+constexpr int kEllMaxCol = 32;
 constexpr long long kEllPadBytes = 8LL << 20;
 
-static int ell_width(int n, long long m, int ncol, long long longest) {
-  if (n <= kEllMinRows || longest < 1 || longest > kEllMaxWidth) return 0;
+// The ELL blocks of one level: slot width and, per colour, row range and slot
+// offset (count colours with a block, in colour order).
+struct EllBlocks {
+  int count;
+  int ew;
+  int r0[kEllMaxCol];
+  int rows[kEllMaxCol];
+  long long off[kEllMaxCol];
+};
+
+// Decides a level's ELL blocks from its longest row and its colours' row and
+// entry counts; fills F.ew, F.ecoff, F.eslots and B.  Blocks start at
+// multiples of 64 slots.
+static void ell_plan(Level& F, long long longest, EllBlocks& B) {
+  B.count = 0;
+  F.ew = 0;
+  F.ecoff.assign(F.ncol, -1);
+  F.eslots = 0;
+  if (F.n <= kEllMinRows || longest < 1 || longest > kEllMaxWidth) return;
   const int ew = (int)((longest + 3) / 4) * 4;
-  const long long slots = (long long)ew * n;
-  if (slots >= INT_MAX) return 0;
-  if (slots <= m + m / 8 || (slots - m) * 8 <= kEllPadBytes * std::max(ncol, 1)) return ew;
-  return 0;
+  B.ew = ew;
+  long long off = 0;
+  for (int c = 0; c < std::min(F.ncol, kEllMaxCol); ++c) {
+    const long long rows = F.cptr_h[c + 1] - F.cptr_h[c];
+    const long long ent = F.cnnz_h[c + 1] - F.cnnz_h[c];
+    const long long slots = (long long)ew * rows;
+    if (rows <= 0 || off + slots >= INT_MAX) continue;
+    if (!(slots <= ent + ent / 8 || (slots - ent) * 8 <= kEllPadBytes)) continue;
+    F.ecoff[c] = off;
+    B.r0[B.count] = F.cptr_h[c];
+    B.rows[B.count] = (int)rows;
+    B.off[B.count] = off;
+    ++B.count;
+    off += (slots + 63) / 64 * 64;
+  }
+  if (B.count == 0) return;
+  F.ew = ew;
+  F.eslots = off;
 }
 
-// Slot-major copy of a level's solve-order matrix: entry k of row i goes to
-// k * n + i; the slots past the row's end hold column -1 and weight 0.
-__global__ void k_ell_fill(int n, int ew, const int* __restrict__ rp, const int* __restrict__ col,
+// Copies the rows of the ELL colours into their slot-major blocks: block y of
+// the grid is ELL colour y; entry k of its row r0 + i goes to off + k * rows +
+// i, the slots past the row's end hold column -1 and weight 0.
+__global__ void k_ell_fill(EllBlocks B, const int* __restrict__ rp, const int* __restrict__ col,
                            const double* __restrict__ w64, const float* __restrict__ w32,
                            int* __restrict__ ecol, double* __restrict__ ew64,
                            float* __restrict__ ew32) {
+  const int c = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int a = rp[i], e = rp[i + 1];
-  for (int k = 0; k < ew; ++k) {
-    const int o = k * n + i;
+  const int rows = B.rows[c];
+  if (i >= rows) return;
+  const int a = rp[B.r0[c] + i], e = rp[B.r0[c] + i + 1];
+  for (int k = 0; k < B.ew; ++k) {
+    const long long o = B.off[c] + (long long)k * rows + i;
     const bool in = a + k < e;
     ecol[o] = in ? col[a + k] : -1;
     ew64[o] = in ? w64[a + k] : 0.0;
@@ -1540,7 +1579,7 @@ static void free_level(fv_hierarchy* h, Level& L) {
   f(L.perm, n * sizeof(int));
   f(L.iperm, n * sizeof(int));
   f(L.qs, n * sizeof(int));
-  const size_t slots = (size_t)L.ew * n;
+  const size_t slots = (size_t)std::max<long long>(L.eslots, 1);
   f(L.ecol, slots * sizeof(int));
   f(L.ew64, slots * sizeof(double));
   f(L.ew32, slots * sizeof(float));
@@ -1988,18 +2027,19 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       std::memcpy(&d, &dm[k], sizeof(double));
       h->lv[k].sigma = 2.0 * d;
     }
-    // ELL copies of the near-regular levels the multi-workgroup sweeps visit.
+    // ELL blocks of the colours the multi-workgroup sweeps visit.
     for (int k = 0; k < J && ell >= 0; ++k) {
       Level& F = h->lv[k];
-      const int ew = ell_width(F.n, F.m, F.ncol, (long long)dm[FV_MAX_LEVELS + k]);
-      if (!ew) continue;
-      const size_t slots = (size_t)ew * F.n;
-      F.ecol = halloc<int>(h, slots);
-      F.ew64 = halloc<double>(h, slots);
-      F.ew32 = halloc<float>(h, slots);
-      F.ew = ew;
-      k_ell_fill<<<nblk(F.n), kBlock, 0, s>>>(F.n, ew, F.rp, F.col, F.w64, F.w32, F.ecol, F.ew64,
-                                              F.ew32);
+      EllBlocks B;
+      ell_plan(F, (long long)dm[FV_MAX_LEVELS + k], B);
+      if (!F.ew) continue;
+      F.ecol = halloc<int>(h, F.eslots);
+      F.ew64 = halloc<double>(h, F.eslots);
+      F.ew32 = halloc<float>(h, F.eslots);
+      int maxrows = 1;
+      for (int b = 0; b < B.count; ++b) maxrows = std::max(maxrows, B.rows[b]);
+      k_ell_fill<<<dim3(nblk(maxrows), B.count), kBlock, 0, s>>>(B, F.rp, F.col, F.w64, F.w32,
+                                                                 F.ecol, F.ew64, F.ew32);
       FV_HIP(hipGetLastError());
     }
     // Device descriptors.

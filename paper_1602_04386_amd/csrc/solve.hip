@@ -628,6 +628,45 @@ struct LaunchTimer {
   }
 };
 
+// Launches colour c's sweep from its ELL block when it has one (returns false
+// otherwise): EW the level's slot count, RPT the tile sweep's rows per thread
+// (two only with at most 8 slots).
+template <class VT, int EW>
+static void gs_ell_launch(const Level& Lh, int c, int rpt, int nb, hipStream_t s, int r0, int r1,
+                          VT* xa, VT* xb, const Workspace& W, int base, double omega) {
+  const int* ec = Lh.ecol + Lh.ecoff[c];
+  const VT* ev = sizeof(VT) == 4 ? reinterpret_cast<const VT*>(Lh.ew32 + Lh.ecoff[c])
+                                 : reinterpret_cast<const VT*>(Lh.ew64 + Lh.ecoff[c]);
+  if constexpr (EW <= 8) {
+    if (rpt == 2) {
+      k_gs_ell<VT, EW, 2><<<nb, kBlock, 0, s>>>(r0, r1, ec, ev, xa, xb, W.st, W.part, W.stride,
+                                                base, omega);
+      return;
+    }
+  }
+  k_gs_ell<VT, EW, 1><<<nb, kBlock, 0, s>>>(r0, r1, ec, ev, xa, xb, W.st, W.part, W.stride, base,
+                                            omega);
+}
+
+template <class VT>
+static bool launch_gs_ell(const Level& Lh, int c, int rpt, int nb, hipStream_t s, int r0, int r1,
+                          VT* xa, VT* xb, const Workspace& W, int base, double omega) {
+  const int ew = Lh.ell_width(c);
+  if (!ew || (rpt == 2 && ew > 8)) return false;
+  switch (ew) {
+    case 4: gs_ell_launch<VT, 4>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 8: gs_ell_launch<VT, 8>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 12: gs_ell_launch<VT, 12>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 16: gs_ell_launch<VT, 16>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 20: gs_ell_launch<VT, 20>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 24: gs_ell_launch<VT, 24>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 28: gs_ell_launch<VT, 28>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    case 32: gs_ell_launch<VT, 32>(Lh, c, rpt, nb, s, r0, r1, xa, xb, W, base, omega); break;
+    default: return false;
+  }
+  return true;
+}
+
 // Enqueues one smoothing (gs) or power phase: `forced` steps exactly when it
 // is not negative, else up to `cap` steps with the cosine test.  The step
 // count lands in *rec on the device.  before_wait, when given, runs once
@@ -667,30 +706,15 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
           const int r0 = Lh.cptr_h[c], r1 = Lh.cptr_h[c + 1];
           hipEvent_t* ev = timer ? timer->pair() : nullptr;
           if (ev) FV_HIP(hipEventRecord(ev[0], s));
-          if (L.ew == 4 && rpt[c] == 2)
-            k_gs_ell<VT, 4, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
-                                                         W.stride, base, omega);
-          else if (L.ew == 4)
-            k_gs_ell<VT, 4, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
-                                                         W.stride, base, omega);
-          else if (L.ew == 8 && rpt[c] == 2)
-            k_gs_ell<VT, 8, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
-                                                         W.stride, base, omega);
-          else if (L.ew == 8)
-            k_gs_ell<VT, 8, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
-                                                         W.stride, base, omega);
-          else if (L.ew == 12 && rpt[c] == 1)
-            k_gs_ell<VT, 12, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
-                                                          W.stride, base, omega);
-          else if (L.ew == 16 && rpt[c] == 1)
-            k_gs_ell<VT, 16, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part,
-                                                          W.stride, base, omega);
-          else if (rpt[c] == 2)
+          if (launch_gs_ell<VT>(Lh, c, rpt[c], nbs[c], s, r0, r1, xa, xb, W, base, omega)) {
+            // swept from the colour's ELL block
+          } else if (rpt[c] == 2) {
             k_gs_tile<VT, 2><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
                                                        base, omega);
-          else
+          } else {
             k_gs_tile<VT, 1><<<nbs[c], kBlock, 0, s>>>(L, r0, r1, xa, xb, W.st, W.part, W.stride,
                                                        base, omega);
+          }
           if (ev) {
             FV_HIP(hipEventRecord(ev[1], s));
             timer->bytes.push_back(pass_bytes(r1 - r0, Lh.cnnz_h[c + 1] - Lh.cnnz_h[c],

@@ -1,11 +1,15 @@
-"""The smoothing sweeps' ELL storage (slot-major copies of near-regular levels
-of at least 65,536 rows) against the CSR tile sweeps and against the oracle.
+"""The smoothing sweeps' ELL storage (slot-major blocks of the colours of
+levels of more than 8,192 rows whose padding is cheap) against the CSR tile
+sweeps and against the oracle.
 
 The ELL sweep keeps the CSR sweep's rows per block, arithmetic and summation
-order, so a hierarchy built with ELL copies and one built without give
+order, so a hierarchy built with ELL blocks and one built without give
 bitwise-equal solves: same schedule, same eigenvalue, same vector.  The 5-point
-grids take four slots per row, the 8-neighbour (king's move) grids eight; the
-1024 x 1000 grid's colours are large enough for two rows per thread.
+grids take four slots per row on level 0 and twelve on the coarse levels, the
+8-neighbour (king's move) grids eight; the 1024 x 1000 grid's colours are
+large enough for two rows per thread; the random geometric graph's level 0
+(rows of up to 26 entries) keeps CSR for its large colours and takes 28-slot
+blocks for its small dense ones.
 """
 import numpy as np
 import pytest
@@ -37,6 +41,7 @@ CASES = {
     "king300x300": (lambda: king(300, 300, 8), 8),
     "grid1024x1000": (lambda: gen.grid_1024x1000(), 4),
     "king1280x1280": (lambda: king(1280, 1280, 9), 8),
+    "rgg200k": (lambda: gen.rgg(200000, 3), 28),
 }
 _graphs = {}
 
@@ -59,8 +64,14 @@ def test_ell_sweeps_equal_csr_sweeps(fv, ctx, name, prec):
     print(f"case {name} {prec}", flush=True)
     he = fv.build_hierarchy_graph(ctx, g)
     hc = fv.build_hierarchy_graph(ctx, g, ell=False)
-    # the ELL copy of level 0: ew slots per row, 4 + 8 + 4 bytes each
-    assert he.device_bytes() - hc.device_bytes() >= 16 * ew * g.n
+    # the ELL blocks: slots per row of each colour's block, 4 + 8 + 4 bytes a slot
+    blocks = 0
+    for lvl in range(he.levels - 1):
+        rows = np.bincount(he.export_level(lvl).colour, minlength=he.colours[lvl])
+        blocks += sum(16 * he.ell_width(lvl, c) * int(rows[c]) for c in range(he.colours[lvl]))
+        assert all(hc.ell_width(lvl, c) == 0 for c in range(he.colours[lvl]))
+    assert he.ell_width(0, he.colours[0] - 1) == ew
+    assert he.device_bytes() - hc.device_bytes() >= blocks > 0
     re = fv.fiedler_solve(ctx, he, prec=prec, **SOLVE)
     rc = fv.fiedler_solve(ctx, hc, prec=prec, **SOLVE)
     assert re.schedule == rc.schedule
@@ -70,7 +81,7 @@ def test_ell_sweeps_equal_csr_sweeps(fv, ctx, name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["grid320x300u", "king300x300"])
+@pytest.mark.parametrize("name", ["grid320x300u", "king300x300", "rgg200k"])
 def test_ell_replay_parity(fv, ctx, orc, name, prec):
     """The ELL path against the oracle on the oracle's schedule (the bars of the
     replay parity tests)."""
