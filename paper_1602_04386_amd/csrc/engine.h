@@ -71,15 +71,31 @@ __device__ __forceinline__ void vrow_batch(const V& L, XP x, int pb, int p1, int
   }
 }
 
+// A row's bounds, own value and first batch of neighbours (indices, weights,
+// values), loaded before any is used.
+struct RowHead {
+  int p0, p1;
+  double xr;
+  int jj[kRowU];
+  double ww[kRowU], xx[kRowU];
+};
+
+// The update of row i from its loaded head: later batches are fetched here,
+// the new value stored, and the row's sums added to acc.
 template <class VT, class V, class XP>
-__device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, double mu, double inv_s,
-                               double rho, double omega, double (&acc)[kNP]) {
-  const int p0 = L.rp[i], p1 = L.rp[i + 1];
-  const double xo = ((double)x[i] - mu) * inv_s;
+__device__ __forceinline__ void vrow_finish(int i, const RowHead& H, const V& L, XP x,
+                                            int lower_end, double mu, double inv_s, double rho,
+                                            double omega, double (&acc)[kNP]) {
+  const int p0 = H.p0, p1 = H.p1;
+  const double xo = (H.xr - mu) * inv_s;
   double num = 0.0, den = 0.0;
-  int j0[kRowU];
-  double w0[kRowU], x0[kRowU];
-  for (int pb = p0; pb < p1; pb += kRowU) {
+  if (p1 > p0)
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) {
+      num += H.ww[u] * (H.jj[u] < lower_end ? H.xx[u] : (H.xx[u] - mu) * inv_s);
+      den += H.ww[u];
+    }
+  for (int pb = p0 + kRowU; pb < p1; pb += kRowU) {
     int jj[kRowU];
     double ww[kRowU], xx[kRowU];
     vrow_batch<VT>(L, x, pb, p1, jj, ww, xx);
@@ -88,13 +104,6 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
       num += ww[u] * (jj[u] < lower_end ? xx[u] : (xx[u] - mu) * inv_s);
       den += ww[u];
     }
-    if (pb == p0)
-#pragma unroll
-      for (int u = 0; u < kRowU; ++u) {
-        j0[u] = jj[u];
-        w0[u] = ww[u];
-        x0[u] = xx[u];
-      }
   }
   double u = xo;
   if (den > 0.0) {
@@ -108,8 +117,8 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
   if (p1 > p0)
 #pragma unroll
     for (int k = 0; k < kRowU; ++k) {
-      const double d = ud - x0[k];
-      e += (j0[k] < lower_end ? w0[k] : 0.0) * d * d;
+      const double d = ud - H.xx[k];
+      e += (H.jj[k] < lower_end ? H.ww[k] : 0.0) * d * d;
     }
   for (int pb = p0 + kRowU; pb < p1; pb += kRowU) {
     int jj[kRowU];
@@ -129,12 +138,76 @@ __device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, 
 }
 
 template <class VT, class V, class XP>
+__device__ __forceinline__ void vrow_gs(int i, const V& L, XP x, int lower_end, double mu, double inv_s,
+                               double rho, double omega, double (&acc)[kNP]) {
+  RowHead H;
+  H.p0 = L.rp[i];
+  H.p1 = L.rp[i + 1];
+  H.xr = (double)x[i];
+  if (H.p1 > H.p0) vrow_batch<VT>(L, x, H.p0, H.p1, H.jj, H.ww, H.xx);
+  vrow_finish<VT>(i, H, L, x, lower_end, mu, inv_s, rho, omega, acc);
+}
+
+// Rows iA and iB (iA first) of one colour with their first batches loaded
+// together: both rows' pointers and own values, then both batches' indices and
+// weights, then both batches' gathers, so the two rows cost the dependent load
+// phases of one.  Rows of one colour have no edges among them, so neither
+// reads the other's new value; the sums are added in the order of two
+// vrow_gs calls.  A row without entries takes the plain path.
+template <class VT, class V, class XP>
+__device__ __forceinline__ void vrow_gs2(int iA, int iB, const V& L, XP x, int lower_end,
+                                         double mu, double inv_s, double rho, double omega,
+                                         double (&acc)[kNP]) {
+  RowHead A, B;
+  A.p0 = L.rp[iA];
+  A.p1 = L.rp[iA + 1];
+  B.p0 = L.rp[iB];
+  B.p1 = L.rp[iB + 1];
+  const VT xa = x[iA], xb = x[iB];
+  if (A.p1 <= A.p0 || B.p1 <= B.p0) {
+    vrow_gs<VT>(iA, L, x, lower_end, mu, inv_s, rho, omega, acc);
+    vrow_gs<VT>(iB, L, x, lower_end, mu, inv_s, rho, omega, acc);
+    return;
+  }
+  A.xr = (double)xa;
+  B.xr = (double)xb;
+  VT wa[kRowU], wb[kRowU], ga[kRowU], gb[kRowU];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) A.jj[u] = L.col[min(A.p0 + u, A.p1 - 1)];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) B.jj[u] = L.col[min(B.p0 + u, B.p1 - 1)];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) wa[u] = L.w[min(A.p0 + u, A.p1 - 1)];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) wb[u] = L.w[min(B.p0 + u, B.p1 - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) ga[u] = x[A.jj[u]];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) gb[u] = x[B.jj[u]];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) {
+    A.ww[u] = A.p0 + u < A.p1 ? (double)wa[u] : 0.0;
+    A.xx[u] = (double)ga[u];
+    B.ww[u] = B.p0 + u < B.p1 ? (double)wb[u] : 0.0;
+    B.xx[u] = (double)gb[u];
+  }
+  vrow_finish<VT>(iA, A, L, x, lower_end, mu, inv_s, rho, omega, acc);
+  vrow_finish<VT>(iB, B, L, x, lower_end, mu, inv_s, rho, omega, acc);
+}
+
+template <class VT, class V, class XP>
 __device__ __forceinline__ Scal vsweep(const V& L, XP x, Scal s, double omega, EngineCtx& E) {
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int c = 0; c < L.ncol; ++c) {
     const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-      vrow_gs<VT>(i, L, x, r0, s.mu, s.inv_s, s.rho, omega, acc);
+    const int bd = blockDim.x;
+    int i = r0 + threadIdx.x;
+    if constexpr (sizeof(VT) == 4)  // FP64 pairs would spill registers
+      for (; i + bd < r1; i += 2 * bd)
+        vrow_gs2<VT>(i, i + bd, L, x, r0, s.mu, s.inv_s, s.rho, omega, acc);
+    for (; i < r1; i += bd) vrow_gs<VT>(i, L, x, r0, s.mu, s.inv_s, s.rho, omega, acc);
     if (c + 1 < L.ncol) __syncthreads();  // the last colour: block_allsum's barrier
   }
   block_allsum<kNP>(acc, E.red, E.flip);
