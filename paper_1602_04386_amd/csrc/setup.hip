@@ -1242,6 +1242,126 @@ __global__ void k_solve_fill(int n, const int* __restrict__ rp_c, const int* __r
   }
 }
 
+// ---- solve-order copies of the small levels, one workgroup per level -------
+// The colour-ordered copy (stable counting sort by colour in 256-row
+// segments, colour ranges, solve-order row pointers, relabelled CSR) of every
+// level of at most kSmallCopyRows rows in one launch: the same arrays the
+// multi-block kernels above produce (k_colour_block_count, the cell scan,
+// k_colour_scatter, k_colour_ptr, the PermDeg scan, k_solve_fill), with the
+// colours, counters, permutations and row pointers in LDS.  A level without
+// colours (the coarsest) keeps its order.  The aggregate maps (k_qs) follow in
+// a launch of their own, since they read the next level's permutation.
+constexpr int kSmallCopyRows = 4096;
+constexpr int kSmallCopyCells = 4096;  // colours x 256-row segments
+constexpr int kSmallCopyThreads = 1024;
+constexpr int kSmallCopyMax = 16;      // levels per launch
+
+struct SmallCopy {
+  int n, ncol;
+  const int* colour;  // canonical colours, or null: one colour
+  const int* rp_c;
+  const int* col_c;
+  const double* w_c;
+  const int* q_c;        // aggregate of each row (k_qs_small), null on the coarsest level
+  const int* perm_next;  // the next level's permutation (k_qs_small)
+  int* perm;
+  int* iperm;
+  int* cptr;
+  int* rp;
+  int* col;
+  double* w64;
+  float* w32;
+  int* qs;
+};
+struct SmallCopies {
+  int count;
+  SmallCopy lv[kSmallCopyMax];
+};
+
+// Dynamic LDS ints of a level: colours, counters (+1), iperm, perm, row pointers (+1).
+__host__ __device__ inline int small_copy_ints(int n, int ncol) {
+  const int nb = (n + kBlock - 1) / kBlock;
+  return 4 * n + ncol * nb + 2;
+}
+
+// Exclusive scan over a[0, len) in place (len <= 4 * blockDim.x); returns the total.
+__device__ inline int block_excl_scan4(int* a, int len, long long* lds) {
+  const int base = 4 * (int)threadIdx.x;
+  int v[4];
+  long long sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = base + k < len ? a[base + k] : 0;
+    sum += v[k];
+  }
+  __syncthreads();  // every value read before any is overwritten
+  const long long inc = block_inclusive_scan_ll(sum, lds);
+  long long run = inc - sum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < len) a[base + k] = (int)run;
+    run += v[k];
+  }
+  __shared__ int total;
+  if (threadIdx.x == blockDim.x - 1) total = (int)inc;
+  __syncthreads();
+  return total;
+}
+
+__global__ __launch_bounds__(kSmallCopyThreads) void k_small_copy(SmallCopies S) {
+  extern __shared__ int sm[];
+  __shared__ long long lds[kSmallCopyThreads / 64];
+  const SmallCopy& C = S.lv[blockIdx.x];
+  const int n = C.n, ncol = C.ncol, nb = (n + kBlock - 1) / kBlock, cells = ncol * nb;
+  const int T = blockDim.x, t = threadIdx.x;
+  int* cl = sm;
+  int* cnt = cl + n;
+  int* ip = cnt + cells + 1;
+  int* pm = ip + n;
+  int* rpl = pm + n;
+  for (int v = t; v < n; v += T) cl[v] = C.colour ? C.colour[v] : 0;
+  for (int k = t; k < cells; k += T) cnt[k] = 0;
+  __syncthreads();
+  for (int v = t; v < n; v += T) atomicAdd(&cnt[cl[v] * nb + v / kBlock], 1);
+  __syncthreads();
+  block_excl_scan4(cnt, cells, lds);  // ends with a barrier
+  for (int v = t; v < n; v += T) {
+    const int c = cl[v], seg = v / kBlock;
+    int r = 0;
+    for (int u = seg * kBlock; u < v; ++u) r += cl[u] == c;
+    const int p = cnt[c * nb + seg] + r;
+    pm[v] = p;
+    ip[p] = v;
+    C.perm[v] = p;
+    C.iperm[p] = v;
+  }
+  for (int c = t; c <= ncol; c += T) C.cptr[c] = c < ncol ? cnt[c * nb] : n;
+  __syncthreads();
+  for (int i = t; i < n; i += T) rpl[i] = C.rp_c[ip[i] + 1] - C.rp_c[ip[i]];
+  __syncthreads();
+  const int m = block_excl_scan4(rpl, n, lds);
+  for (int i = t; i < n; i += T) C.rp[i] = rpl[i];
+  if (t == 0) C.rp[n] = m;
+  for (int i = t; i < n; i += T) {
+    const int v = ip[i];
+    int k = rpl[i];
+    for (int p = C.rp_c[v]; p < C.rp_c[v + 1]; ++p, ++k) {
+      C.col[k] = pm[C.col_c[p]];
+      const double wv = C.w_c[p];
+      C.w64[k] = wv;
+      C.w32[k] = (float)wv;
+    }
+  }
+}
+
+// k_qs for the levels of a SmallCopies batch that have a next level.
+__global__ void k_qs_small(SmallCopies S) {
+  const SmallCopy& C = S.lv[blockIdx.y];
+  if (!C.q_c) return;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < C.n; v += gridDim.x * blockDim.x)
+    C.qs[C.perm[v]] = C.perm_next[C.q_c[v]];
+}
+
 __global__ void k_qs(int n, const int* perm, const int* q, const int* perm_next, int* qs) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
@@ -1618,6 +1738,15 @@ size_t hierarchy_nmax(const fv_hierarchy* h) { return h->levels ? (size_t)h->lv[
 
 // Allows k_colour_local more than the 64 KiB of dynamic LDS a launch gets by
 // default; done once per process.
+static void enable_small_copy_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    FV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_copy),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(int) * small_copy_ints(kSmallCopyRows, kSmallCopyCells / nblk(kSmallCopyRows)))));
+  });
+}
+
 static void enable_colour_local_lds() {
   static std::once_flag once;
   std::call_once(once, [] {
@@ -1960,8 +2089,60 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
     const int J = l;
     h->levels = J + 1;
 
-    // Solve-order copies, coarsest first so that q can use the next perm.
-    for (int k = J; k >= 0; --k) {
+    // Solve-order copies, coarsest first so that q can use the next perm.  The
+    // small levels (the coarsest run of levels that fit one workgroup each)
+    // in one launch, then their aggregate maps in another.
+    int kbig = J;  // levels above kbig go through the per-level kernels
+    {
+      SmallCopies S;
+      std::memset(&S, 0, sizeof(S));
+      int lds_ints = 0;
+      for (int k = J; k >= 0 && S.count < kSmallCopyMax; --k) {
+        Level& F = h->lv[k];
+        const int fn = F.n;
+        const int ncol = k == J ? 1 : F.ncol;
+        if (fn > kSmallCopyRows || (long long)ncol * nblk(fn) > kSmallCopyCells) break;
+        if (k == J) {
+          F.ncol = 1;
+          F.cptr_h = {0, fn};
+        }
+        F.perm = halloc<int>(h, fn);
+        F.iperm = halloc<int>(h, fn);
+        F.cptr = halloc<int>(h, ncol + 1);
+        F.rp = halloc<int>(h, fn + 1);
+        F.col = halloc<int>(h, F.m);
+        F.w64 = halloc<double>(h, F.m);
+        F.w32 = halloc<float>(h, F.m);
+        if (k < J) F.qs = halloc<int>(h, fn);
+        SmallCopy& C = S.lv[S.count++];
+        C.n = fn;
+        C.ncol = ncol;
+        C.colour = k == J ? nullptr : F.colour_c;
+        C.rp_c = F.rp_c;
+        C.col_c = F.col_c;
+        C.w_c = F.w_c;
+        C.q_c = k < J ? F.q_c : nullptr;
+        C.perm_next = k < J ? h->lv[k + 1].perm : nullptr;
+        C.perm = F.perm;
+        C.iperm = F.iperm;
+        C.cptr = F.cptr;
+        C.rp = F.rp;
+        C.col = F.col;
+        C.w64 = F.w64;
+        C.w32 = F.w32;
+        C.qs = F.qs;
+        lds_ints = std::max(lds_ints, small_copy_ints(fn, ncol));
+        kbig = k - 1;
+      }
+      if (S.count > 0) {
+        const size_t lds = sizeof(int) * (size_t)lds_ints;
+        if (lds > 64 * 1024) enable_small_copy_lds();
+        k_small_copy<<<S.count, kSmallCopyThreads, lds, s>>>(S);
+        k_qs_small<<<dim3(nblk(kSmallCopyRows), S.count), kBlock, 0, s>>>(S);
+        FV_HIP(hipGetLastError());
+      }
+    }
+    for (int k = kbig; k >= 0; --k) {
       Level& F = h->lv[k];
       const int fn = F.n;
       F.perm = halloc<int>(h, fn);
