@@ -306,32 +306,18 @@ __device__ inline double wave_sum_low32(double v) {
 }
 
 // The power-iteration steps of the one-wavefront coarsest solve, lane i
-// holding x_i (lanes >= n hold 0).  R > 0: row i of W in R registers (columns
-// j >= n are zero), n <= R <= 32; R = 0: rows read from LDS, any n <= 64.
-// Runs until the stop test passes (cv = 1), max_it steps, or exactly forced
-// steps; returns the steps taken and leaves the iterate in x.
-template <int R>
-__device__ int coarsest_steps(__attribute__((address_space(3))) const double* Wd, int n, int base,
-                              bool has, double sigma, double tol, int max_it, int forced,
-                              double& x, int& cv) {
-  auto bcast = [](double v, int j) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), j),
-                            __builtin_amdgcn_readlane(__double2loint(v), j));
-  };
-  auto sum = [](double v) { return R > 0 ? wave_sum_low32(v) : wave_sum(v); };
-  double wr[R > 0 ? R : 1];
-#pragma unroll
-  for (int j = 0; j < R; ++j) wr[j] = j < n ? Wd[j * n + base] : 0.0;
+// holding x_i (lanes >= n hold 0); rowl(x) returns lane i's (L x)_i.  Sums run
+// over half a wave when n <= 32 (half).  Runs until the stop test passes
+// (cv = 1), max_it steps, or exactly forced steps; returns the steps taken
+// and leaves the iterate in x.
+template <class RowL>
+__device__ int coarsest_iterate(RowL rowl, bool half, int n, bool has, double sigma, double tol,
+                                int max_it, int forced, double& x, int& cv) {
+  auto sum = [half](double v) { return half ? wave_sum_low32(v) : wave_sum(v); };
   int it = 0;
   cv = 0;
   for (;;) {
-    double l = 0.0;
-    if (R > 0) {
-#pragma unroll
-      for (int j = 0; j < R; ++j) l += wr[j] * (x - bcast(x, j));
-    } else {
-      for (int j = 0; j < n; ++j) l += Wd[j * n + base] * (x - bcast(x, j));
-    }
+    double l = rowl(x);
     l = has ? l : 0.0;
     // The shifted step does not depend on the stop test, so its mean is
     // reduced together with the Rayleigh quotient.
@@ -361,6 +347,66 @@ __device__ int coarsest_steps(__attribute__((address_space(3))) const double* Wd
     ++it;
   }
   return it;
+}
+
+__device__ inline double lane_bcast(double v, int j) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), j),
+                          __builtin_amdgcn_readlane(__double2loint(v), j));
+}
+
+// Dense form: lane i's row of W in R registers (columns j >= n are zero),
+// n <= R <= 32, or read from LDS (R = 0, any n <= 64); x_j is broadcast with
+// readlane, j ascending.
+template <int R>
+__device__ int coarsest_steps(__attribute__((address_space(3))) const double* Wd, int n, int base,
+                              bool has, double sigma, double tol, int max_it, int forced,
+                              double& x, int& cv) {
+  double wr[R > 0 ? R : 1];
+#pragma unroll
+  for (int j = 0; j < R; ++j) wr[j] = j < n ? Wd[j * n + base] : 0.0;
+  auto rowl = [&](double xv) {
+    double l = 0.0;
+    if (R > 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) l += wr[j] * (xv - lane_bcast(xv, j));
+    } else {
+      for (int j = 0; j < n; ++j) l += Wd[j * n + base] * (xv - lane_bcast(xv, j));
+    }
+    return l;
+  };
+  return coarsest_iterate(rowl, R > 0, n, has, sigma, tol, max_it, forced, x, cv);
+}
+
+// Sparse form for levels whose rows hold at most K entries: lane i keeps its
+// row's columns and weights (column order; padded with its own index and
+// weight 0, which add exact zeros) and fetches x_j with a lane shuffle.  The
+// terms are the dense form's nonzero ones in the same order, and the zero
+// terms the dense form adds leave its sums unchanged, so both give the same
+// iterates; the shuffles replace R broadcasts by K.
+template <int K>
+__device__ int coarsest_steps_sparse(const int* __restrict__ rp, const int* __restrict__ col,
+                                     const double* __restrict__ w, int n, int lane, bool has,
+                                     double sigma, double tol, int max_it, int forced, double& x,
+                                     int& cv) {
+  int ck[K];
+  double wk[K];
+  const int p0 = has ? rp[lane] : 0, p1 = has ? rp[lane + 1] : 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool in = p0 + k < p1;
+    ck[k] = in ? col[p0 + k] : lane;
+    wk[k] = in ? w[p0 + k] : 0.0;
+  }
+  auto rowl = [&](double xv) {
+    double xj[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) xj[k] = __shfl(xv, ck[k], 64);
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) l += wk[k] * (xv - xj[k]);
+    return l;
+  };
+  return coarsest_iterate(rowl, n <= 32, n, has, sigma, tol, max_it, forced, x, cv);
 }
 
 // Coarsest solve in FP64 (Algorithm 3, Step 2): power iteration on
@@ -398,10 +444,22 @@ __device__ int engine_coarsest(const LevelDesc& L, unsigned long long seed, int 
       x = has ? x - m : 0.0;
       x *= 1.0 / sqrt(wave_sum(x * x));
       int cv = 0;
-      // Up to 32 vertices (the usual coarsest size) the row is also held in
+      // Rows of at most 16 entries (the usual coarsest level: ~4 a row) take
+      // the sparse form.  Otherwise, up to 32 vertices the row is also held in
       // registers, so an iteration touches no memory at all; the row length is
       // rounded up to 8, 16, 24 or 32 (the padding columns add exact zeros).
-      if (n <= 8) it = coarsest_steps<8>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
+      const int len = has ? L.rp[lane + 1] - L.rp[lane] : 0;
+      int maxlen = len;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
+      maxlen = __builtin_amdgcn_readfirstlane(maxlen);
+      if (maxlen <= 4)
+        it = coarsest_steps_sparse<4>(L.rp, col, w, n, lane, has, sigma, tol, max_it, forced, x, cv);
+      else if (maxlen <= 8)
+        it = coarsest_steps_sparse<8>(L.rp, col, w, n, lane, has, sigma, tol, max_it, forced, x, cv);
+      else if (maxlen <= 16)
+        it = coarsest_steps_sparse<16>(L.rp, col, w, n, lane, has, sigma, tol, max_it, forced, x, cv);
+      else if (n <= 8) it = coarsest_steps<8>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
       else if (n <= 16) it = coarsest_steps<16>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
       else if (n <= 24) it = coarsest_steps<24>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
       else if (n <= 32) it = coarsest_steps<32>(Wd, n, base, has, sigma, tol, max_it, forced, x, cv);
