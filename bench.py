@@ -79,8 +79,12 @@ RGG_SOLVE = dict(SOLVE, tol_cos=0.0, max_gs=30, max_pi=30, max_outer=100)
 # pool (one solve at a time) converges 17 of the 32 graphs in 1.15 s; 8, 20
 # and 30 rounds: 13, 18 and 21 of 32 in 0.97, 1.49 and 1.84 s; 12 gives the
 # most solves at residual 1e-6 per second (the grid's parameters with 10
-# rounds: 4 of 32 in 1.06 s).
-SERVE_SOLVE = dict(SOLVE, tol_cos=0.0, max_gs=30, max_pi=30, omega=1.95, max_outer=12)
+# rounds: 4 of 32 in 1.06 s).  Early exit: a request whose residual, falling
+# at its last rate, cannot reach 1e-6 within the 12 rounds ends there (the
+# stalling random geometric graphs after 2 to 5 rounds instead of 12) and
+# returns not converged, which frees the GPU for the requests that do.
+SERVE_SOLVE = dict(SOLVE, tol_cos=0.0, max_gs=30, max_pi=30, omega=1.95, max_outer=12,
+                   early_exit=True)
 # Recursive bisection of the 1024 x 1000 grid: its quarters (512 x 500) are
 # nearly square; at SOR factor 1.9 the FP64 oracle needs 82 to 336 finest
 # rounds on three of them and stalls at 1.005e-6 on the fourth, at 1.95 every

@@ -130,6 +130,14 @@ typedef struct {
   int32_t time_finest;   /* 1: time every finest-level smoothing launch with a pair
                             of HIP events (totals in fv_solve_stats; the first 2048
                             launches of a solve); 0 (default): no timing */
+  int32_t early_exit;    /* 1: end the finest rounds of tol_res once the residual,
+                            falling each round by its last reduction factor
+                            (residual / the previous round's residual, products
+                            taken one round at a time in double), cannot reach
+                            tol_res within the rounds max_outer leaves, or did not
+                            fall; such a solve returns FV_E_NOT_CONVERGED early (a
+                            serving policy, not part of Section 4's rule).
+                            0 (default): rounds until tol_res or max_outer */
 } fv_solve_opts;
 
 /* Per-solve statistics.  schedule = [coarsest steps, then (gs sweeps, pi steps)

@@ -98,6 +98,8 @@ def lib():
         L.or_pair_hash.argtypes = [C.c_int32, C.c_int32]
         L.or_level_seed.restype = C.c_uint32
         L.or_level_seed.argtypes = [C.c_uint64, C.c_int32]
+        L.or_can_reach.restype = C.c_int32
+        L.or_can_reach.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32]
         L.or_colour_priority.restype = C.c_uint32
         L.or_colour_priority.argtypes = [C.c_int32, C.c_uint32]
         L.or_input_to_adjacency.restype = C.c_int32
@@ -174,7 +176,7 @@ class SolveParams(C.Structure):
                 ("gs_unshifted", C.c_int32), ("omega", C.c_double),
                 ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32),
                 ("tol_coarse", C.c_double), ("coarse_mass", C.c_int32), ("gs_rhs_y", C.c_int32),
-                ("lanczos_k", C.c_int32)]
+                ("lanczos_k", C.c_int32), ("early_exit", C.c_int32)]
 
 
 def _i32(a):
@@ -282,6 +284,11 @@ def level_colouring(n, rowptr, col, level_seed, finest=True):
 
 def level_seed(colour_seed, level):
     return lib().or_level_seed(colour_seed, level)
+
+
+def can_reach(res, res_prev, tol, left):
+    """or_can_reach: the finest rounds' early-exit test."""
+    return bool(lib().or_can_reach(res, res_prev, tol, left))
 
 
 def pair_hash(a, b):
@@ -411,12 +418,14 @@ class Hierarchy:
     def solve(self, seed=1, tol_cos=1e-6, tol_res=0.0, max_gs=100, max_pi=100, max_outer=50,
               max_coarsest=100000, lexicographic=False, unshifted=False, omega=1.0,
               replay=None, tol_coarse=1e-13, coarse_mass=False, rhs_y=False,
-              lanczos_k=0) -> SolveResult:
+              lanczos_k=0, early_exit=False) -> SolveResult:
         """Algorithm 3, Steps 2-3, then the finest Rayleigh quotient.  Variants
         (oracle-only, for comparison): lexicographic (Algorithm 2's row
         order), unshifted (the sweep on L x = 0), rhs_y (the sweep on L x = y),
         coarse_mass (coarse problems L_c y = lambda M_c y), lanczos_k (k
-        Lanczos steps in place of each smoothing phase)."""
+        Lanczos steps in place of each smoothing phase).  early_exit: the
+        finest rounds end once the residual cannot reach tol_res within the
+        rounds left at its last reduction factor (or_can_reach)."""
         n0 = self.level(0).n if self.nlevels else 0
         x = np.zeros(n0)
         scal = np.zeros(3)
@@ -425,7 +434,7 @@ class Hierarchy:
         clen = C.c_int32(0)
         P = SolveParams(seed, tol_cos, tol_res, max_gs, max_pi, max_outer, max_coarsest,
                         1 if lexicographic else 0, 1 if unshifted else 0, omega, None, 0,
-                        tol_coarse, int(coarse_mass), int(rhs_y), int(lanczos_k))
+                        tol_coarse, int(coarse_mass), int(rhs_y), int(lanczos_k), int(early_exit))
         keep = None
         if replay is not None:
             keep = (C.c_int32 * len(replay))(*[int(v) for v in replay])

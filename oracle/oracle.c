@@ -881,7 +881,25 @@ typedef struct {
   int32_t coarse_mass;      /* 1: coarse levels solve L_c y = lambda M_c y, M_c = I I^T */
   int32_t gs_rhs_y;         /* 1: the sweep solves L x = y with y the iterate before it */
   int32_t lanczos_k;        /* > 0: each smoothing phase is k Lanczos steps on sigma I - L */
+  int32_t early_exit;       /* 1: end the finest rounds once the residual, falling by its
+                               last factor each round, cannot reach tol_res within the
+                               rounds max_outer leaves (or_can_reach) */
 } or_solve_params;
+
+/* The finest rounds' early exit (a serving policy beside Section 4's stop
+ * rule): 1 when the residual res, multiplied round after round by its last
+ * reduction factor q = res / res_prev, falls to tol within `left` more rounds
+ * (the products taken one at a time, in double); 0 when it did not fall. */
+int32_t or_can_reach(double res, double res_prev, double tol, int32_t left) {
+  if (!(res < res_prev)) return 0;
+  const double q = res / res_prev;
+  double v = res;
+  for (int32_t k = 0; k < left; ++k) {
+    v *= q;
+    if (v <= tol) return 1;
+  }
+  return 0;
+}
 
 /* Rayleigh quotient x^T L x / x^T x in the edge form of or_rq_residual. */
 static double or_rq(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
@@ -1186,6 +1204,7 @@ int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double
   const or_level* F0 = &h->lv[0];
   double rho, res;
   or_rq_residual(F0->n, F0->rp, F0->col, F0->w, x, &rho, &res);
+  double res_prev = res;
   int32_t outer = 0;
   for (;;) {
     int32_t fg, fp;
@@ -1195,6 +1214,9 @@ int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double
       fp = OR_NEXT_FORCED();
     } else {
       if (!(P->tol_res > 0.0) || res <= P->tol_res || outer >= P->max_outer) break;
+      if (P->early_exit && outer > 0 &&
+          !or_can_reach(res, res_prev, P->tol_res, P->max_outer - outer))
+        break;
       fg = fp = -1;
     }
     if (J == 0) break; /* a one-level hierarchy is solved by the coarsest solve */
@@ -1203,6 +1225,7 @@ int32_t or_solve(const void* hp, const or_solve_params* P, double* x_out, double
     OR_PUSH(g);
     OR_PUSH(p);
     ++outer;
+    res_prev = res;
     or_rq_residual(F0->n, F0->rp, F0->col, F0->w, x, &rho, &res);
   }
   if (!R && P->tol_res > 0.0 && res > P->tol_res) status = OR_E_NOT_CONVERGED;

@@ -54,7 +54,8 @@ class fv_solve_opts(C.Structure):
                 ("tol_res", C.c_double), ("omega", C.c_double), ("max_gs", C.c_int32),
                 ("max_pi", C.c_int32), ("max_outer", C.c_int32), ("max_coarsest", C.c_int32),
                 ("replay", C.POINTER(C.c_int32)), ("replay_len", C.c_int32),
-                ("stream", C.c_void_p), ("tol_coarse", C.c_double), ("time_finest", C.c_int32)]
+                ("stream", C.c_void_p), ("tol_coarse", C.c_double), ("time_finest", C.c_int32),
+                ("early_exit", C.c_int32)]
 
 
 class fv_solve_stats(C.Structure):
@@ -393,7 +394,7 @@ class SolveResult:
 
 def solve_opts(prec="fp64", seed=1, tol_cos=1e-6, tol_res=0.0, omega=1.0, max_gs=100,
                max_pi=100, max_outer=50, max_coarsest=100000, replay=None, stream=None,
-               tol_coarse=1e-13, time_finest=False):
+               tol_coarse=1e-13, time_finest=False, early_exit=False):
     o = fv_solve_opts()
     lib().fv_solve_opts_default(C.byref(o))
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -401,6 +402,7 @@ def solve_opts(prec="fp64", seed=1, tol_cos=1e-6, tol_res=0.0, omega=1.0, max_gs
     o.max_gs, o.max_pi, o.max_outer, o.max_coarsest = max_gs, max_pi, max_outer, max_coarsest
     o.tol_coarse = tol_coarse
     o.time_finest = 1 if time_finest else 0
+    o.early_exit = 1 if early_exit else 0
     keep = None
     if replay is not None:
         keep = (C.c_int32 * len(replay))(*[int(v) for v in replay])

@@ -183,6 +183,7 @@ void fv_solve_opts_default(fv_solve_opts* o) {
   o->stream = nullptr;
   o->tol_coarse = 1e-13;
   o->time_finest = 0;
+  o->early_exit = 0;
 }
 
 const char* fv_status_str(fv_status st) {

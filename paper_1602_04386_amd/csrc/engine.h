@@ -416,6 +416,7 @@ __device__ __forceinline__ void finish_level0(const V& L, XP x, VT* ytmp, Scal& 
                               int& si, int& slen, double& lam, double& res, EngineCtx& E) {
   double sign = 1.0;
   vrq_residual<VT>(L, x, s, T.lx, lam, res, sign, E);
+  double res_prev = res;
   int outer = 0;
   if (J > 0) {
     for (;;) {
@@ -426,6 +427,9 @@ __device__ __forceinline__ void finish_level0(const V& L, XP x, VT* ytmp, Scal& 
         fp = si < T.replay_len ? T.replay[si++] : -1;
       } else {
         if (!(T.tol_res > 0.0) || res <= T.tol_res || outer >= T.max_outer) break;
+        if (T.early_exit && outer > 0 &&
+            !can_reach(res, res_prev, T.tol_res, T.max_outer - outer))
+          break;
         fg = fp = -1;
       }
       s.rho = lam;
@@ -440,6 +444,7 @@ __device__ __forceinline__ void finish_level0(const V& L, XP x, VT* ytmp, Scal& 
       slen += 2;
       ++outer;
       __syncthreads();
+      res_prev = res;
       vrq_residual<VT>(L, x, s, T.lx, lam, res, sign, E);
     }
   }

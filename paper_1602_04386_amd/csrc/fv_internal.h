@@ -73,6 +73,21 @@ struct DevState {
 
 // Per-level descriptor as the kernels see it (solve order: rows of one colour
 // contiguous, ascending original index inside a colour).
+// The finest rounds' early exit (fv_solve_opts.early_exit): true when the
+// residual res, multiplied round after round by its last reduction factor
+// res / res_prev, falls to tol within `left` more rounds (the products taken
+// one at a time in double); false when it did not fall.
+__host__ __device__ inline bool can_reach(double res, double res_prev, double tol, int left) {
+  if (!(res < res_prev)) return false;
+  const double q = res / res_prev;
+  double v = res;
+  for (int k = 0; k < left; ++k) {
+    v *= q;
+    if (v <= tol) return true;
+  }
+  return false;
+}
+
 struct LevelDesc {
   int n;
   int ncol;
@@ -116,6 +131,7 @@ struct GraphTask {
   unsigned long long seed;
   double tol_cos, tol_res, omega, tol_coarse;
   int max_gs, max_pi, max_outer, max_coarsest;
+  int early_exit;       // fv_solve_opts.early_exit
   long long work;       // ordering key (bigger first)
 };
 

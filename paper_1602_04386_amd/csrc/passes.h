@@ -623,11 +623,16 @@ __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* 
   if (done) *hdone = 1;
 }
 
+// Finishes the finest residual pass.  The halt flag (later phases do
+// nothing) goes up when the residual meets tol_halt or, with early exit
+// (early_left >= 0: rounds max_outer leaves after this pass, which follows
+// at least one finest round), when it cannot reach tol_halt in those rounds.
 template <class VT>
 __global__ __launch_bounds__(kBlock) void k_finish_res(LevelDesc L, const VT* xa, const VT* xb,
                                                      DevState* st, const double* part,
                                                      const int* ipart, int nslots,
-                                                     double tol_halt, double* hres) {
+                                                     double tol_halt, int early_left,
+                                                     double* hres) {
   __shared__ double lds[block_sum_lds(kBlock)];
   __shared__ int ilds[kBlock / 64];
   double s[1] = {0.0};
@@ -641,9 +646,14 @@ __global__ __launch_bounds__(kBlock) void k_finish_res(LevelDesc L, const VT* xa
   if (threadIdx.x != 0) return;
   const VT* x = st->cur ? xb : xa;
   const double res = sqrt(s[0] / st->sumsq);
+  const double res_prev = st->res;
   st->res = res;
   *hres = res;
-  st->halt = (tol_halt > 0.0 && res <= tol_halt) ? 1 : 0;
+  st->halt = (tol_halt > 0.0 && (res <= tol_halt ||
+                                 (early_left >= 0 && !can_reach(res, res_prev, tol_halt,
+                                                                early_left))))
+                 ? 1
+                 : 0;
   st->sign_idx = c;
   const double xv = c < INT_MAX ? ((double)x[L.perm[c]] - st->mu) * st->inv_s : 1.0;
   st->sign = xv < 0.0 ? -1.0 : 1.0;

@@ -854,6 +854,7 @@ static void fill_task(GraphTask& T, const fv_hierarchy* h, const fv_solve_opts* 
   T.max_gs = o->max_gs;
   T.max_pi = o->max_pi;
   T.max_outer = o->max_outer;
+  T.early_exit = o->early_exit ? 1 : 0;
   T.max_coarsest = o->max_coarsest;
   T.tol_coarse = o->tol_coarse;
 }
@@ -1029,7 +1030,9 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
     // Under the residual test the last residual pass raises the device's halt
     // flag itself, so a round enqueued before the host has read it is void.
     const double tol_halt = o->replay ? 0.0 : o->tol_res;
-    auto rq_res = [&]() {
+    // early_left: with early exit, the rounds max_outer leaves after the
+    // round this pass follows (-1: none, or no early exit).
+    auto rq_res = [&](int early_left) {
       const int nb = nblk(F0.n);
       const VT* xa = static_cast<const VT*>(W.xa);
       const VT* xb = static_cast<const VT*>(W.xb);
@@ -1037,10 +1040,12 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
       k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nb, F0.n, kFinRQ, nullptr, nullptr);
       k_res_tile<VT><<<nb, kBlock, 0, s>>>(L0, xa, xb, W.st, W.lx, W.part, W.ipart);
       k_finish_res<VT><<<1, kBlock, 0, s>>>(L0, xa, xb, W.st, W.part, W.ipart, nb, tol_halt,
-                                            hsync.hres_dev);
+                                            early_left, hsync.hres_dev);
       FV_HIP(hipGetLastError());
     };
-    rq_res();
+    rq_res(-1);
+    const bool early = o->early_exit && !o->replay;
+    double last_res = 0.0;  // the residual the host read before the current one
     int outer = 0;
     for (;;) {
       int fg, fp;
@@ -1056,10 +1061,17 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
         spec = true;
       }
       // The round's first chunk is enqueued before the last residual is read.
+      // With early exit it also ends the rounds when the residual cannot reach
+      // tol_res in the rounds left, the test the residual pass made on the device.
       auto residual_met = [&]() -> bool {
         if (!spec) return false;
         FV_HIP(hipEventSynchronize(hsync.ev_res));
-        return *hsync.hres <= o->tol_res;
+        const double r = *hsync.hres;
+        const bool stop = r <= o->tol_res ||
+                          (early && outer > 0 && !can_reach(r, last_res, o->tol_res,
+                                                            o->max_outer - outer));
+        last_res = r;
+        return stop;
       };
       if (run_phase_multi<VT>(true, F0, L0, W, fg, o->max_gs, o->tol_cos, o->omega, s, hsync,
                               rec_slot(), spec, residual_met, tptr)) {
@@ -1069,7 +1081,7 @@ static fv_status solve_one_t(fv_context* ctx, SolveScratch& sc, void* ws, const 
       run_phase_multi<VT>(false, F0, L0, W, fp, o->max_pi, o->tol_cos, o->omega, s, hsync,
                           rec_slot(), spec, no_wait);
       ++outer;
-      rq_res();
+      rq_res(early ? o->max_outer - outer : -1);
     }
     k_output<VT><<<nblk(F0.n), kBlock, 0, s>>>(L0, static_cast<const VT*>(W.xa),
                                                static_cast<const VT*>(W.xb), W.st, out_dev);

@@ -436,3 +436,44 @@ def test_long_phase_parameters(fv, ctx, orc, name):
     assert abs(rb.lam - ro.lam) <= 1e-10 * ro.lam
     r32 = fv.fiedler_solve(ctx, h, prec="fp32", **LONG_PHASES)
     check_fp32_result(g, r32, oh.solve(**dict(LONG_PHASES, replay=r32.schedule)), h.sigma[0])
+
+
+# The serving policy's early exit (fv_solve_opts.early_exit): the finest rounds
+# end once the residual cannot reach tol_res in the rounds left at its last
+# reduction factor.  Two random geometric graphs that stall (one solved in the
+# engine, one with its finest level on the multi-workgroup passes) and one
+# that converges within the cap.
+EARLY_CASES = {
+    "rgg1.5k": (1523, gen.derive_seed(5, 22) ^ 0x55),
+    "rgg10k": (10381, gen.derive_seed(5, 10) ^ 0x55),
+    "rgg3k": (3000, 11),
+}
+SERVE_PHASES = dict(LONG_PHASES, max_outer=12)
+
+
+@pytest.mark.parametrize("name", list(EARLY_CASES))
+def test_early_exit_matches_oracle(fv, ctx, orc, name):
+    n, seed = EARLY_CASES[name]
+    g = gen.rgg(n, seed)
+    print(f"case {name} early exit", flush=True)
+    h = fv.build_hierarchy_graph(ctx, g, n_coarse=25)
+    oh = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=25)
+    ro = oh.solve(early_exit=True, **SERVE_PHASES)
+    # FP64: the oracle's schedule, its rounds included, and its result
+    r = fv.fiedler_solve(ctx, h, prec="fp64", early_exit=True, **SERVE_PHASES)
+    assert r.schedule == ro.counts
+    assert r.status == ro.status
+    assert abs(r.residual - ro.residual) <= 1e-9 * ro.residual
+    assert abs(r.lam - ro.lam) <= 1e-10 * ro.lam
+    rb = fv.fiedler_solve_batch(ctx, [h], prec="fp64", early_exit=True, **SERVE_PHASES)[0]
+    assert rb.schedule == ro.counts and rb.status == ro.status
+    # FP32-mixed: the same rule on its own residuals; a stalling graph stops
+    # well before the cap, a converging one runs as without early exit
+    r32 = fv.fiedler_solve(ctx, h, prec="fp32", early_exit=True, **SERVE_PHASES)
+    r32_full = fv.fiedler_solve(ctx, h, prec="fp32", **SERVE_PHASES)
+    J = h.levels - 1
+    rounds = (len(r32.schedule) - 1 - 2 * J) // 2
+    if ro.status == 0:
+        assert r32.schedule == r32_full.schedule and r32.residual == r32_full.residual
+    else:
+        assert rounds < SERVE_PHASES["max_outer"] and r32.status == fv.E_NOT_CONVERGED

@@ -940,3 +940,65 @@ def test_zero_cosine_tolerance_runs_every_phase_to_its_cap(orc):
         J = h.nlevels - 1
         r = h.solve(seed=1, tol_cos=0.0, max_gs=7, max_pi=40, tol_res=1e-30, max_outer=3)
         assert r.counts[1:] == [7, 40] * (J + 3)
+
+
+def _reaches(res, res_prev, tol, left):
+    """Closed form of the early-exit test: a residual falling by q = res /
+    res_prev per round reaches tol within `left` rounds iff the rounds it
+    needs, ceil(log(tol / res) / log q), are at most `left`."""
+    if not res < res_prev:
+        return False
+    if res <= tol:
+        return True
+    return math.ceil(math.log(tol / res) / math.log(res / res_prev)) <= left
+
+
+def test_early_exit_rule_against_its_closed_form(orc):
+    """or_can_reach (round-by-round products) against the logarithmic closed
+    form, on cases kept away from ties, and its answers when the residual did
+    not fall."""
+    rng = np.random.default_rng(3)
+    checked = 0
+    for _ in range(3000):
+        res, q = 10 ** rng.uniform(-6, -3), rng.uniform(0.3, 0.999)
+        left, tol = int(rng.integers(0, 60)), 1e-6
+        need = math.log(tol / res) / math.log(q)
+        if res <= tol or abs(need - round(need)) < 1e-6:
+            continue
+        assert orc.can_reach(res, res / q, tol, left) == (math.ceil(need) <= left), (res, q, left)
+        checked += 1
+    assert checked > 1500
+    assert not orc.can_reach(2e-6, 2e-6, 1e-6, 400)  # no fall
+    assert not orc.can_reach(2e-6, 1e-6, 1e-6, 400)  # a rise
+
+
+# Serving-pool parameters: long phases, no cosine stop, SOR 1.95, 12 rounds.
+SERVE_PARAMS = dict(seed=1, tol_cos=0.0, tol_res=1e-6, max_gs=30, max_pi=30, omega=1.95,
+                    max_outer=12, tol_coarse=1e-6)
+
+
+def test_early_exit_stops_where_the_rule_says(orc):
+    """With early exit the oracle's finest rounds end at the first round whose
+    residual, against the one before it, fails the closed-form test (the
+    trajectory taken from the same solve run for 0, 1, 2, ... rounds without
+    early exit), and return that round's residual; a graph that converges
+    within the cap runs as without early exit."""
+    for n, seed, stalls in ((1523, gen.derive_seed(5, 22) ^ 0x55, True), (3000, 11, False)):
+        g = gen.rgg(n, seed)
+        h = orc.Hierarchy(g.n, g.rowptr, g.col, g.w, n_coarse=25)
+        J = h.nlevels - 1
+        P = dict(SERVE_PARAMS)
+        traj = [h.solve(**dict(P, max_outer=k)).residual for k in range(P["max_outer"] + 1)]
+        expect = P["max_outer"]
+        for k in range(1, P["max_outer"] + 1):
+            if traj[k] <= P["tol_res"] or not _reaches(traj[k], traj[k - 1], P["tol_res"],
+                                                       P["max_outer"] - k):
+                expect = k
+                break
+        r = h.solve(early_exit=True, **P)
+        rounds = (len(r.counts) - 1 - 2 * J) // 2
+        assert rounds == expect and r.residual == traj[expect], (n, rounds, expect)
+        assert (rounds < P["max_outer"]) == stalls
+        r0 = h.solve(**P)
+        if not stalls:
+            assert r0.counts == r.counts and r0.residual == r.residual
