@@ -572,37 +572,100 @@ __global__ __launch_bounds__(kBlock) void k_finish(DevState* st, const double* p
 // barrier ordering them), adding their sums to the partial slots of the
 // colours the tile kernels did, then finishes as k_finish does.  One launch
 // instead of one per small trailing colour (first-fit colourings leave a few
-// colours with a handful of rows each).
+// colours with a handful of rows each).  A tail colour with an ELL block
+// (eoff[c - c0] >= 0, EW > 0 slots a row) is swept from it: two dependent
+// load phases instead of a row-pointer phase and one pair per batch of eight
+// entries (the dense last colours of irregular levels hold 15 to 20).
 constexpr int kTailBlock = 512;
 constexpr int kTailRows = 512;  // one row per thread: the tail adds one dependent row pass
+constexpr int kTailEll = 8;     // tail colours that may have ELL blocks
 
-template <class VT>
+struct TailEll {
+  long long eoff[kTailEll];  // slot offset of tail colour c0 + k's block, or -1
+};
+
+// Shifted sweep update of row i (of a colour with rows [r0, r0 + rows)) from
+// the colour's ELL block at ec / ev: the arithmetic of row_gs_batched.
+template <class VT, int EW>
+__device__ inline void row_gs_ell(int i, int r0, int rows, const int* __restrict__ ec,
+                                  const VT* __restrict__ ev, VT* __restrict__ x, double mu,
+                                  double inv_s, double rho, double omega, double (&acc)[kNP]) {
+  const int li = i - r0;
+  int cc[EW];
+  VT ww[EW], xg[EW];
+#pragma unroll
+  for (int j = 0; j < EW; ++j) cc[j] = ec[j * rows + li];
+#pragma unroll
+  for (int j = 0; j < EW; ++j) ww[j] = ev[j * rows + li];
+  const VT xv = x[i];
+#pragma unroll
+  for (int j = 0; j < EW; ++j) xg[j] = x[cc[j] >= 0 ? cc[j] : i];
+  const double xo = ((double)xv - mu) * inv_s;
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int j = 0; j < EW; ++j)
+    if (cc[j] >= 0) gs_entry(num, den, (double)ww[j], (double)xg[j], cc[j] < r0, mu, inv_s);
+  const VT us = (VT)gs_relax(num, den, xo, rho, omega);
+  x[i] = us;
+  const double ud = (double)us;
+  double e = 0.0;
+#pragma unroll
+  for (int j = 0; j < EW; ++j)
+    if (cc[j] >= 0 && cc[j] < r0) gs_energy(e, (double)ww[j], ud, (double)xg[j]);
+  gs_sums(acc, ud, xo, e);
+}
+
+template <class VT, int EW>
 __global__ __launch_bounds__(kTailBlock) void k_finish_gs_tail(LevelDesc L, VT* xa, VT* xb,
                                                              DevState* st, const double* part,
                                                              int stride, int nslots, int c0,
                                                              int tr0, int tr1, double omega,
-                                                             int* rec, int* hdone) {
+                                                             TailEll te, int* rec, int* hdone) {
   __shared__ double lds[block_sum_lds(kTailBlock)];
   if (st->done) return;
   VT* x = st->cur ? xb : xa;
   const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
+  const VT* ev0 = nullptr;
+  if constexpr (EW > 0)
+    ev0 = sizeof(VT) == 4 ? reinterpret_cast<const VT*>(L.ew32) : reinterpret_cast<const VT*>(L.ew64);
+  auto ell_of = [&](int c) -> long long {
+    return EW > 0 && c - c0 < kTailEll ? te.eoff[c - c0] : -1;
+  };
   // The first tail colour holds rows [tr0, tr1) (at most kTailRows, one per
   // thread); its row pointers are requested before the partial slots are
   // added, so that the two round trips overlap.
   const int i0 = tr0 + threadIdx.x;
+  const long long e0 = ell_of(c0);
   int p0 = 0, p1 = 0;
-  if (i0 < tr1) {
+  if (i0 < tr1 && e0 < 0) {
     p0 = L.rp[i0];
     p1 = L.rp[i0 + 1];
   }
   double S[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   sum_slots<kNP>(part, stride, nslots, S);
-  if (i0 < tr1) row_gs_batched<VT>(i0, p0, p1, L, x, tr0, mu, inv_s, rho, omega, S);
+  if (i0 < tr1) {
+    if constexpr (EW > 0) {
+      if (e0 >= 0)
+        row_gs_ell<VT, EW>(i0, tr0, tr1 - tr0, L.ecol + e0, ev0 + e0, x, mu, inv_s, rho, omega, S);
+      else
+        row_gs_batched<VT>(i0, p0, p1, L, x, tr0, mu, inv_s, rho, omega, S);
+    } else {
+      row_gs_batched<VT>(i0, p0, p1, L, x, tr0, mu, inv_s, rho, omega, S);
+    }
+  }
   __syncthreads();  // the next colour reads this colour's new values
   for (int c = c0 + 1; c < L.ncol; ++c) {
     const int r0 = L.cptr[c], r1 = L.cptr[c + 1];
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+    const long long ec = ell_of(c);
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+      if constexpr (EW > 0) {
+        if (ec >= 0) {
+          row_gs_ell<VT, EW>(i, r0, r1 - r0, L.ecol + ec, ev0 + ec, x, mu, inv_s, rho, omega, S);
+          continue;
+        }
+      }
       row_gs_batched<VT>(i, L.rp[i], L.rp[i + 1], L, x, r0, mu, inv_s, rho, omega, S);
+    }
     __syncthreads();
   }
   const double t = block_sum_spread<kNP>(S, lds);

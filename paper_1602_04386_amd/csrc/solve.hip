@@ -725,6 +725,41 @@ static bool launch_gs_ell(const Level& Lh, int c, int rpt, int nb, hipStream_t s
   return true;
 }
 
+// Launches the finishing block of a sweep whose colours from ct on are swept
+// by it, with the ELL blocks of those colours where they have them.
+template <class VT, int EW>
+static void gs_tail_launch(const Level& Lh, const LevelDesc& L, int ct, hipStream_t s, VT* xa,
+                           VT* xb, const Workspace& W, int nslots, double omega, int* rec,
+                           int* hdone, const TailEll& te) {
+  k_finish_gs_tail<VT, EW><<<1, kTailBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride, nslots,
+                                                    ct, Lh.cptr_h[ct], Lh.cptr_h[ct + 1], omega,
+                                                    te, rec, hdone);
+}
+
+template <class VT>
+static void launch_gs_tail(const Level& Lh, const LevelDesc& L, int ct, hipStream_t s, VT* xa,
+                           VT* xb, const Workspace& W, int nslots, double omega, int* rec,
+                           int* hdone) {
+  TailEll te;
+  bool any = false;
+  for (int k = 0; k < kTailEll; ++k) {
+    const int c = ct + k;
+    te.eoff[k] = Lh.ell_width(c) ? Lh.ecoff[c] : -1;
+    any = any || te.eoff[k] >= 0;
+  }
+  switch (any ? Lh.ew : 0) {
+    case 4: gs_tail_launch<VT, 4>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 8: gs_tail_launch<VT, 8>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 12: gs_tail_launch<VT, 12>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 16: gs_tail_launch<VT, 16>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 20: gs_tail_launch<VT, 20>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 24: gs_tail_launch<VT, 24>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 28: gs_tail_launch<VT, 28>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    case 32: gs_tail_launch<VT, 32>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te); break;
+    default: gs_tail_launch<VT, 0>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hdone, te);
+  }
+}
+
 // Enqueues one smoothing (gs) or power phase: `forced` steps exactly when it
 // is not negative, else up to `cap` steps with the cosine test.  The step
 // count lands in *rec on the device.  before_wait, when given, runs once
@@ -783,9 +818,7 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
           base += nbs[c];
         }
         if (ct < L.ncol)
-          k_finish_gs_tail<VT><<<1, kTailBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride, nslots,
-                                                        ct, Lh.cptr_h[ct], Lh.cptr_h[ct + 1],
-                                                        omega, rec, hs.hdone_dev);
+          launch_gs_tail<VT>(Lh, L, ct, s, xa, xb, W, nslots, omega, rec, hs.hdone_dev);
         else
           k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec,
                                         hs.hdone_dev);
