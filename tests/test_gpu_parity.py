@@ -477,3 +477,36 @@ def test_early_exit_matches_oracle(fv, ctx, orc, name):
         assert r32.schedule == r32_full.schedule and r32.residual == r32_full.residual
     else:
         assert rounds < SERVE_PHASES["max_outer"] and r32.status == fv.E_NOT_CONVERGED
+
+
+def test_server_early_exit_results_equal_batch(fv, ctx):
+    """Served requests under the early exit (small random geometric graphs,
+    stalling and converging, mixed in one admission) give the batched
+    launch's results bit for bit: the same schedules, statuses and vectors."""
+    import time
+
+    gs = [gen.rgg(n, seed) for n, seed in EARLY_CASES.values() if n <= 4000]
+    gs += [gen.rgg(2500, 31), gen.rgg(1800, 32)]
+    srv = fv.Server(ctx, max_inflight=4, n_coarse=25, prec="fp32", early_exit=True,
+                    **{k: v for k, v in SERVE_PHASES.items() if k != "seed"})
+    tickets = [srv.submit(k, g) for k, g in enumerate(gs)]
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 60:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.001)
+    srv.close()
+    assert len(out) == len(tickets)
+    hs = [fv.build_hierarchy_graph(ctx, g, n_coarse=25) for g in gs]
+    ref = fv.fiedler_solve_batch(ctx, hs, prec="fp32", early_exit=True, **SERVE_PHASES)
+    statuses = set()
+    for k, t in enumerate(tickets):
+        info, x = out[t]
+        assert info["status"] == ref[k].status and info["lambda"] == ref[k].lam
+        assert np.array_equal(x, ref[k].x)
+        statuses.add(ref[k].status)
+    assert statuses == {0, fv.E_NOT_CONVERGED}  # both kinds are in the mix
