@@ -93,18 +93,55 @@ __device__ __forceinline__ void stage_chunk(const int* __restrict__ col,
 // their values are used: the loads a thread issues there (its own rows'
 // values) travel alongside the CSR staging instead of after it.  The block has
 // kBlock threads.
+// A tile's row pointers as for_tile_chunks stages them: thread t holds those
+// of rows t + k kBlock (k < RPT) and thread 0 the one past a full tile.
+template <int RPT>
+struct TileRp {
+  int a[RPT];
+  int b;
+};
+
+template <int RPT>
+__device__ inline TileRp<RPT> load_tile_rp(const LevelDesc& L, int rs, int re) {
+  constexpr int kRows = RPT * kBlock;
+  const int nr = re - rs;
+  const int t = threadIdx.x;
+  TileRp<RPT> r;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) r.a[k] = t + k * kBlock <= nr ? L.rp[rs + t + k * kBlock] : 0;
+  r.b = (t == 0 && nr == kRows) ? L.rp[rs + kRows] : 0;
+  return r;
+}
+
+template <class WT, class XT, int RPT, class P, class G, class B, class D>
+__device__ inline bool for_tile_chunks_from(const LevelDesc& L, const WT* __restrict__ w, int rs,
+                                            int re, TileLds<WT, XT, RPT>& T, int skip,
+                                            const TileRp<RPT>& rpl, P pre, G gather, B body,
+                                            D direct);
+
 template <class WT, class XT, int RPT, class P, class G, class B, class D>
 __device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict__ w, int rs,
                                        int re, TileLds<WT, XT, RPT>& T, int skip, P pre,
                                        G gather, B body, D direct) {
+  const TileRp<RPT> rpl = load_tile_rp<RPT>(L, rs, re);
+  return for_tile_chunks_from<WT, XT, RPT>(L, w, rs, re, T, skip, rpl, pre, gather, body, direct);
+}
+
+// for_tile_chunks with the tile's row pointers already requested (rpl), so
+// that a loop over tiles can request the next tile's while this one runs.
+template <class WT, class XT, int RPT, class P, class G, class B, class D>
+__device__ inline bool for_tile_chunks_from(const LevelDesc& L, const WT* __restrict__ w, int rs,
+                                            int re, TileLds<WT, XT, RPT>& T, int skip,
+                                            const TileRp<RPT>& rpl, P pre, G gather, B body,
+                                            D direct) {
   constexpr int kRows = TileLds<WT, XT, RPT>::kRows;
   const int nr = re - rs;
   const int t = threadIdx.x;
   const bool extra = t == 0 && nr == kRows;  // the pointer past a full tile
   int rp_a[RPT];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) rp_a[k] = t + k * kBlock <= nr ? L.rp[rs + t + k * kBlock] : 0;
-  const int rp_b = extra ? L.rp[rs + kRows] : 0;
+  for (int k = 0; k < RPT; ++k) rp_a[k] = rpl.a[k];
+  const int rp_b = rpl.b;
   pre();
 #pragma unroll
   for (int k = 0; k < RPT; ++k)
@@ -394,6 +431,68 @@ __global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile(Lev
       },
       [&](int t) { row_pi<VT>(rs + t, L, x, y, mu, inv_s, sigma, acc); });
   if (!ran) return;
+  store_block_sum(acc, lds, part, stride, blockIdx.x);
+}
+
+// The power step over a level of more tiles than one round of resident
+// blocks: each of the grid's blocks takes tiles b, b + G, b + 2G, ... (G the
+// grid; b in XCD order) and requests the next tile's row pointers before it
+// stages the current one, so that their round trip overlaps the current
+// tile's loads and arithmetic.  The block adds all its tiles' sums into one
+// partial slot.
+template <class VT, int RPT>
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile_loop(
+    LevelDesc L, VT* xa, VT* xb, const DevState* st, double* part, int stride, int ntiles) {
+  __shared__ TileLds<VT, VT, RPT> T;
+  __shared__ double lds[block_sum_lds(kBlock)];
+  const int done = st->done;
+  const int cur = st->cur;
+  const VT* x = cur ? xb : xa;
+  VT* y = cur ? xa : xb;
+  const double mu = st->mu, inv_s = st->inv_s, sigma = L.sigma;
+  const int G = gridDim.x;
+  const auto* w = WSel<VT>::w(L);
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int tile = xcd_block(blockIdx.x, G);
+  int rs = tile * T.kRows, re = min(rs + T.kRows, L.n);
+  TileRp<RPT> rpl = load_tile_rp<RPT>(L, rs, re);
+  for (; tile < ntiles; tile += G) {
+    const int ns = (tile + G) * T.kRows;
+    const bool more = tile + G < ntiles;
+    TileRp<RPT> next = rpl;
+    if (more) next = load_tile_rp<RPT>(L, ns, min(ns + T.kRows, L.n));
+    VT xown[RPT];
+    const bool ran = for_tile_chunks_from<VT, VT, RPT>(
+        L, w, rs, re, T, done, rpl,
+        [&] {
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            const int i = rs + (int)threadIdx.x + k * kBlock;
+            xown[k] = i < re ? x[i] : VT(0);
+          }
+        },
+        [&](int c) { return x[c]; },
+        [&](int t, int kk, int a, int e) {
+          const int i = rs + t;
+          const double xi = (double)xown[kk];
+          double lx = 0.0;
+          for (int k = a; k < e; ++k) lx += (double)T.w[k] * (xi - (double)T.x[k]);
+          const double xo = (xi - mu) * inv_s;
+          const VT ys = (VT)(sigma * xo - lx * inv_s);
+          y[i] = ys;
+          const double yd = (double)ys;
+          acc[0] += yd;
+          acc[1] += yd * yd;
+          acc[2] += yd * xo;
+          acc[3] += xo;
+        },
+        [&](int t) { row_pi<VT>(rs + t, L, x, y, mu, inv_s, sigma, acc); });
+    if (!ran) return;
+    __syncthreads();  // the tile's LDS is read before the next tile stages into it
+    rs = ns;
+    re = min(rs + T.kRows, L.n);
+    rpl = next;
+  }
   store_block_sum(acc, lds, part, stride, blockIdx.x);
 }
 

@@ -577,6 +577,19 @@ static int tile_rpt(long long rows, long long entries) {
   return rows > one_round && entries <= 4 * rows ? 2 : 1;
 }
 
+// Blocks of a tile kernel that one round of residency holds: the CU count
+// times the blocks per CU the tile's LDS allows.
+template <class VT>
+static int resident_tiles(int rpt) {
+  static const int ncu = [] {
+    int dev = 0, n = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n;
+  }();
+  return ncu * (rpt == 2 ? tile_waves<VT, 2>() : tile_waves<VT, 1>());
+}
+
 // Allows an engine instantiation the dynamic LDS it is launched with (more
 // than the 64 KiB default); done once per instantiation and process.
 template <class VT, int NT>
@@ -790,6 +803,10 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
   }
   const int pi_rpt = tile_rpt<VT>(L.n, L.m);
   const int pi_nb = nblk(L.n, kBlock * pi_rpt);
+  // A level of more tiles than one round of resident blocks takes the power
+  // step as a loop of tiles per block (one round of blocks).
+  const int pi_grid = std::min(pi_nb, resident_tiles<VT>(pi_rpt));
+  const bool pi_loop = pi_nb > pi_grid;
   if (nslots > W.stride) throw Error(FV_E_DEVICE, "partial-sum slots exceeded");
   auto enqueue = [&](int k) {
     for (int it = 0; it < k; ++it) {
@@ -822,6 +839,15 @@ static bool run_phase_multi(bool gs, const Level& Lh, const LevelDesc& L, const 
         else
           k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, nslots, L.n, kFinGS, rec,
                                         hs.hdone_dev);
+      } else if (pi_loop) {
+        if (pi_rpt == 2)
+          k_pi_tile_loop<VT, 2><<<pi_grid, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride,
+                                                           pi_nb);
+        else
+          k_pi_tile_loop<VT, 1><<<pi_grid, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride,
+                                                           pi_nb);
+        k_finish<<<1, kBlock, 0, s>>>(W.st, W.part, W.stride, pi_grid, L.n, kFinPI, rec,
+                                      hs.hdone_dev);
       } else {
         if (pi_rpt == 2)
           k_pi_tile<VT, 2><<<pi_nb, kBlock, 0, s>>>(L, xa, xb, W.st, W.part, W.stride);
