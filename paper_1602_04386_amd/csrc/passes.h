@@ -79,21 +79,7 @@ __device__ __forceinline__ void stage_chunk(const int* __restrict__ col,
   }
 }
 
-// Walks the rows [rs, re) (re - rs <= T.kRows) of a tile chunk by chunk.  For
-// each chunk it stages the CSR slice and gather(col) in LDS, then calls
-// body(tt, k, a, e) for every row rs + tt of the chunk in the thread that owns
-// it (tt = threadIdx.x + k kBlock, k < RPT a compile-time index after
-// unrolling), [a, e) being that row's entries in T.  A row longer than
-// T.kCap is passed to direct(tt) instead.  Every thread of the block must
-// call; the rows of one tile never read values that the body writes.
-// skip (the phase's stop flag, loaded by the caller before this call) is
-// tested only after the row pointers are requested, so that both loads are in
-// flight together; when set, nothing else happens and false is returned.
-// pre() runs in every thread once the row pointer loads are issued and before
-// their values are used: the loads a thread issues there (its own rows'
-// values) travel alongside the CSR staging instead of after it.  The block has
-// kBlock threads.
-// A tile's row pointers as for_tile_chunks stages them: thread t holds those
+// A tile's row pointers as for_tile_chunks_from stages them: thread t holds those
 // of rows t + k kBlock (k < RPT) and thread 0 the one past a full tile.
 template <int RPT>
 struct TileRp {
@@ -113,22 +99,22 @@ __device__ inline TileRp<RPT> load_tile_rp(const LevelDesc& L, int rs, int re) {
   return r;
 }
 
-template <class WT, class XT, int RPT, class P, class G, class B, class D>
-__device__ inline bool for_tile_chunks_from(const LevelDesc& L, const WT* __restrict__ w, int rs,
-                                            int re, TileLds<WT, XT, RPT>& T, int skip,
-                                            const TileRp<RPT>& rpl, P pre, G gather, B body,
-                                            D direct);
-
-template <class WT, class XT, int RPT, class P, class G, class B, class D>
-__device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict__ w, int rs,
-                                       int re, TileLds<WT, XT, RPT>& T, int skip, P pre,
-                                       G gather, B body, D direct) {
-  const TileRp<RPT> rpl = load_tile_rp<RPT>(L, rs, re);
-  return for_tile_chunks_from<WT, XT, RPT>(L, w, rs, re, T, skip, rpl, pre, gather, body, direct);
-}
-
-// for_tile_chunks with the tile's row pointers already requested (rpl), so
-// that a loop over tiles can request the next tile's while this one runs.
+// Walks the rows [rs, re) (re - rs <= T.kRows) of a tile chunk by chunk.  For
+// each chunk it stages the CSR slice and gather(col) in LDS, then calls
+// body(tt, k, a, e) for every row rs + tt of the chunk in the thread that owns
+// it (tt = threadIdx.x + k kBlock, k < RPT a compile-time index after
+// unrolling), [a, e) being that row's entries in T.  A row longer than
+// T.kCap is passed to direct(tt) instead.  Every thread of the block must
+// call; the rows of one tile never read values that the body writes.
+// skip (the phase's stop flag, loaded by the caller before this call) is
+// tested only after the row pointers are requested, so that both loads are in
+// flight together; when set, nothing else happens and false is returned.
+// pre() runs in every thread once the row pointer loads are issued and before
+// their values are used: the loads a thread issues there (its own rows'
+// values) travel alongside the CSR staging instead of after it.  The block has
+// kBlock threads.
+// The tile's row pointers come already requested (rpl, from load_tile_rp),
+// so that a loop over tiles can request the next tile's while this one runs.
 template <class WT, class XT, int RPT, class P, class G, class B, class D>
 __device__ inline bool for_tile_chunks_from(const LevelDesc& L, const WT* __restrict__ w, int rs,
                                             int re, TileLds<WT, XT, RPT>& T, int skip,
@@ -183,6 +169,15 @@ __device__ inline bool for_tile_chunks_from(const LevelDesc& L, const WT* __rest
     lo = hi;
   }
   return true;
+}
+
+// for_tile_chunks_from with the tile's own row pointers requested first.
+template <class WT, class XT, int RPT, class P, class G, class B, class D>
+__device__ inline bool for_tile_chunks(const LevelDesc& L, const WT* __restrict__ w, int rs,
+                                       int re, TileLds<WT, XT, RPT>& T, int skip, P pre,
+                                       G gather, B body, D direct) {
+  const TileRp<RPT> rpl = load_tile_rp<RPT>(L, rs, re);
+  return for_tile_chunks_from<WT, XT, RPT>(L, w, rs, re, T, skip, rpl, pre, gather, body, direct);
 }
 
 // Opens a phase.  With use_halt set, a phase enqueued after the finest
@@ -261,22 +256,18 @@ __device__ inline void close_gs_sweep(DevState* st, const double (&S)[kNP], int 
 
 // ---- smoothing sweep, one colour -------------------------------------------
 
+// The rows [rs, re) of colour [r0, r1) as one tile, their row pointers
+// already requested (rpl): each row relaxed in place, its sums added to acc.
+// False, with nothing done, when the phase has ended (skip).
 template <class VT, int RPT>
-__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
-                                                  const DevState* st, double* part, int stride,
-                                                  int slot_base, double omega) {
-  __shared__ TileLds<VT, VT, RPT> T;
-  __shared__ double lds[block_sum_lds(kBlock)];
-  const int done = st->done;
-  VT* x = st->cur ? xb : xa;
-  const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int rs = r0 + b * T.kRows, re = min(rs + T.kRows, r1);
+__device__ inline bool gs_tile_rows(const LevelDesc& L, int r0, int rs, int re,
+                                    TileLds<VT, VT, RPT>& T, int skip, const TileRp<RPT>& rpl,
+                                    VT* x, double mu, double inv_s, double rho, double omega,
+                                    double (&acc)[kNP]) {
   const auto* w = WSel<VT>::w(L);
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   VT xown[RPT];
-  const bool ran = for_tile_chunks<VT, VT, RPT>(
-      L, w, rs, re, T, done,
+  return for_tile_chunks_from<VT, VT, RPT>(
+      L, w, rs, re, T, skip, rpl,
       [&] {
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
@@ -300,7 +291,25 @@ __global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_tile(Lev
         gs_sums(acc, ud, xo, en);
       },
       [&](int t) { row_gs<VT>(rs + t, L, x, r0, mu, inv_s, rho, omega, acc); });
-  if (!ran) return;
+}
+
+// One tile of a colour per block (tile b, in XCD order); its sums go to
+// partial slot slot_base + blockIdx.x.
+template <class VT, int RPT>
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_gs_tile(LevelDesc L, int r0, int r1, VT* xa, VT* xb,
+                                                  const DevState* st, double* part, int stride,
+                                                  int slot_base, double omega) {
+  __shared__ TileLds<VT, VT, RPT> T;
+  __shared__ double lds[block_sum_lds(kBlock)];
+  const int done = st->done;
+  VT* x = st->cur ? xb : xa;
+  const double mu = st->mu, inv_s = st->inv_s, rho = st->rho;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int rs = r0 + b * T.kRows, re = min(rs + T.kRows, r1);
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (!gs_tile_rows<VT, RPT>(L, r0, rs, re, T, done, load_tile_rp<RPT>(L, rs, re), x, mu, inv_s,
+                             rho, omega, acc))
+    return;
   store_block_sum(acc, lds, part, stride, slot_base + blockIdx.x);
 }
 
@@ -390,23 +399,18 @@ __global__ __launch_bounds__(kBlock, (ell_waves<VT, EW, RPT>())) void k_gs_ell(
 
 // ---- power step ------------------------------------------------------------
 
+// The rows [rs, re) as one tile of the power step, their row pointers already
+// requested (rpl): y = (sigma I - L) x over the normalised x, the sums added to
+// acc.  False, with nothing done, when the phase has ended (skip).
 template <class VT, int RPT>
-__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
-                                                  const DevState* st, double* part, int stride) {
-  __shared__ TileLds<VT, VT, RPT> T;
-  __shared__ double lds[block_sum_lds(kBlock)];
-  const int done = st->done;
-  const int cur = st->cur;
-  const VT* x = cur ? xb : xa;
-  VT* y = cur ? xa : xb;
-  const double mu = st->mu, inv_s = st->inv_s, sigma = L.sigma;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int rs = b * T.kRows, re = min(rs + T.kRows, L.n);
+__device__ inline bool pi_tile_rows(const LevelDesc& L, int rs, int re, TileLds<VT, VT, RPT>& T,
+                                    int skip, const TileRp<RPT>& rpl, const VT* x, VT* y,
+                                    double mu, double inv_s, double (&acc)[kNP]) {
   const auto* w = WSel<VT>::w(L);
-  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double sigma = L.sigma;
   VT xown[RPT];
-  const bool ran = for_tile_chunks<VT, VT, RPT>(
-      L, w, rs, re, T, done,
+  return for_tile_chunks_from<VT, VT, RPT>(
+      L, w, rs, re, T, skip, rpl,
       [&] {
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
@@ -430,7 +434,24 @@ __global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile(Lev
         acc[3] += xo;
       },
       [&](int t) { row_pi<VT>(rs + t, L, x, y, mu, inv_s, sigma, acc); });
-  if (!ran) return;
+}
+
+template <class VT, int RPT>
+__global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile(LevelDesc L, VT* xa, VT* xb,
+                                                  const DevState* st, double* part, int stride) {
+  __shared__ TileLds<VT, VT, RPT> T;
+  __shared__ double lds[block_sum_lds(kBlock)];
+  const int done = st->done;
+  const int cur = st->cur;
+  const VT* x = cur ? xb : xa;
+  VT* y = cur ? xa : xb;
+  const double mu = st->mu, inv_s = st->inv_s;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int rs = b * T.kRows, re = min(rs + T.kRows, L.n);
+  double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (!pi_tile_rows<VT, RPT>(L, rs, re, T, done, load_tile_rp<RPT>(L, rs, re), x, y, mu, inv_s,
+                             acc))
+    return;
   store_block_sum(acc, lds, part, stride, blockIdx.x);
 }
 
@@ -449,45 +470,17 @@ __global__ __launch_bounds__(kBlock, (tile_waves<VT, RPT>())) void k_pi_tile_loo
   const int cur = st->cur;
   const VT* x = cur ? xb : xa;
   VT* y = cur ? xa : xb;
-  const double mu = st->mu, inv_s = st->inv_s, sigma = L.sigma;
+  const double mu = st->mu, inv_s = st->inv_s;
   const int G = gridDim.x;
-  const auto* w = WSel<VT>::w(L);
   double acc[kNP] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int tile = xcd_block(blockIdx.x, G);
   int rs = tile * T.kRows, re = min(rs + T.kRows, L.n);
   TileRp<RPT> rpl = load_tile_rp<RPT>(L, rs, re);
   for (; tile < ntiles; tile += G) {
-    const int ns = (tile + G) * T.kRows;
-    const bool more = tile + G < ntiles;
+    const int ns = rs + G * T.kRows;
     TileRp<RPT> next = rpl;
-    if (more) next = load_tile_rp<RPT>(L, ns, min(ns + T.kRows, L.n));
-    VT xown[RPT];
-    const bool ran = for_tile_chunks_from<VT, VT, RPT>(
-        L, w, rs, re, T, done, rpl,
-        [&] {
-#pragma unroll
-          for (int k = 0; k < RPT; ++k) {
-            const int i = rs + (int)threadIdx.x + k * kBlock;
-            xown[k] = i < re ? x[i] : VT(0);
-          }
-        },
-        [&](int c) { return x[c]; },
-        [&](int t, int kk, int a, int e) {
-          const int i = rs + t;
-          const double xi = (double)xown[kk];
-          double lx = 0.0;
-          for (int k = a; k < e; ++k) lx += (double)T.w[k] * (xi - (double)T.x[k]);
-          const double xo = (xi - mu) * inv_s;
-          const VT ys = (VT)(sigma * xo - lx * inv_s);
-          y[i] = ys;
-          const double yd = (double)ys;
-          acc[0] += yd;
-          acc[1] += yd * yd;
-          acc[2] += yd * xo;
-          acc[3] += xo;
-        },
-        [&](int t) { row_pi<VT>(rs + t, L, x, y, mu, inv_s, sigma, acc); });
-    if (!ran) return;
+    if (tile + G < ntiles) next = load_tile_rp<RPT>(L, ns, min(ns + T.kRows, L.n));
+    if (!pi_tile_rows<VT, RPT>(L, rs, re, T, done, rpl, x, y, mu, inv_s, acc)) return;
     __syncthreads();  // the tile's LDS is read before the next tile stages into it
     rs = ns;
     re = min(rs + T.kRows, L.n);
