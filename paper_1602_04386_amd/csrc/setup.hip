@@ -310,42 +310,57 @@ __device__ inline int find_col(const int* rp, const int* col, int i, int j) {
   return -1;
 }
 
+// G lanes per row (a group of consecutive lanes): lane j checks entries j,
+// j + G, ... of row i (finite, off-diagonal weights positive, the mirror
+// entry present with the same bits), so a row's mirror searches run side by
+// side; the group's first lane then adds the row's degree in CSR order and
+// checks the diagonal against it.
+template <int G>
 __global__ void k_val_values(int n, const int* rp, const int* col, const double* val, int adj,
                              int* offdeg, int* flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(g / G), j = (int)(g % G);
   if (i >= n) return;
-  int a = rp[i], b = rp[i + 1];
-  bool has_diag = false;
-  double diag = 0.0, deg = 0.0;
-  int nd = 0;
+  const int a = rp[i], b = rp[i + 1];
   int f = 0;
-  for (int p = a; p < b; ++p) {
-    double v = val[p];
-    int j = col[p];
+  for (int p = a + j; p < b; p += G) {
+    const double v = val[p];
+    const int c = col[p];
     if (!isfinite(v)) f |= 2;
-    if (j == i) {
+    if (c == i) {
       if (adj) f |= 2;
-      has_diag = true;
-      diag = v;
     } else {
-      double wij = adj ? v : -v;
+      const double wij = adj ? v : -v;
       if (!(wij > 0.0)) f |= 2;
-      deg += wij;
-      ++nd;
-      int t = find_col(rp, col, j, i);
+      const int t = find_col(rp, col, c, i);
       if (t < 0 || __double_as_longlong(val[t]) != __double_as_longlong(v)) f |= 4;
     }
   }
-  if (!adj && b > a) {
-    if (!has_diag) {
-      f |= 2;
-    } else {
-      double tol = 1e-12 * (fabs(diag) > 1.0 ? fabs(diag) : 1.0);
-      if (fabs(diag - deg) > tol) f |= 2;
+  if (j == 0) {
+    bool has_diag = false;
+    double diag = 0.0, deg = 0.0;
+    int nd = 0;
+    for (int p = a; p < b; ++p) {
+      const double v = val[p];
+      if (col[p] == i) {
+        has_diag = true;
+        diag = v;
+      } else {
+        deg += adj ? v : -v;
+        ++nd;
+      }
     }
+    if (!adj && b > a) {
+      if (!has_diag) {
+        f |= 2;
+      } else {
+        double tol = 1e-12 * (fabs(diag) > 1.0 ? fabs(diag) : 1.0);
+        if (fabs(diag - deg) > tol) f |= 2;
+      }
+    }
+    if (nd == 0) f |= 8;
+    offdeg[i] = nd;
   }
-  if (nd == 0) f |= 8;
-  offdeg[i] = nd;
   if (f) atomicOr(flags, f);
 }
 
@@ -1224,21 +1239,52 @@ __global__ void k_colour_ptr(int n, int ncol, int nb, const int* off, int* cptr)
 // Colour-ordered copy: row i of the solve order is original row iperm[i];
 // columns are relabelled but keep their original order (so row sums add in
 // the same order as in the original numbering).
+// G lanes per row (a group of consecutive lanes): lane j of row i's group
+// copies entries j, j + G, ... of the canonical row iperm[i] to solve-order
+// row i, so the reads of a row and the writes of its copy are consecutive
+// words across the group instead of one word per lane.
+template <int G>
 __global__ void k_solve_fill(int n, const int* __restrict__ rp_c, const int* __restrict__ col_c,
                              const double* __restrict__ w_c, const int* __restrict__ iperm,
                              const int* __restrict__ perm, const int* __restrict__ rp,
                              int* __restrict__ col, double* __restrict__ w64,
                              float* __restrict__ w32) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(g / G), j = (int)(g % G);
   if (i >= n) return;
-  int v = iperm[i];
-  int k = rp[i];
-#pragma unroll 4
-  for (int p = rp_c[v]; p < rp_c[v + 1]; ++p, ++k) {
-    col[k] = perm[col_c[p]];
-    double wv = w_c[p];
-    w64[k] = wv;
-    w32[k] = (float)wv;
+  const int v = iperm[i];
+  const int a = rp_c[v], b = rp_c[v + 1];
+  const int k = rp[i] - a;
+  for (int p = a + j; p < b; p += G) {
+    col[k + p] = perm[col_c[p]];
+    const double wv = w_c[p];
+    w64[k + p] = wv;
+    w32[k + p] = (float)wv;
+  }
+}
+
+// Lanes per row of the row-group kernels: about one entry per lane of an
+// average row, between 4 and 16.
+static int row_group(long long rows, long long entries) {
+  const long long mean = entries / std::max<long long>(rows, 1);
+  return mean <= 4 ? 4 : mean <= 8 ? 8 : 16;
+}
+
+static void launch_solve_fill(int n, long long m, hipStream_t s, const int* rp_c,
+                              const int* col_c, const double* w_c, const int* iperm,
+                              const int* perm, const int* rp, int* col, double* w64, float* w32) {
+  switch (row_group(n, m)) {
+    case 4:
+      k_solve_fill<4><<<nblk(4LL * n), kBlock, 0, s>>>(n, rp_c, col_c, w_c, iperm, perm, rp, col,
+                                                        w64, w32);
+      break;
+    case 8:
+      k_solve_fill<8><<<nblk(8LL * n), kBlock, 0, s>>>(n, rp_c, col_c, w_c, iperm, perm, rp, col,
+                                                        w64, w32);
+      break;
+    default:
+      k_solve_fill<16><<<nblk(16LL * n), kBlock, 0, s>>>(n, rp_c, col_c, w_c, iperm, perm, rp,
+                                                          col, w64, w32);
   }
 }
 
@@ -1464,11 +1510,19 @@ __device__ inline bool term_less(int J1, int a1, int b1, int J2, int a2, int b2)
   return b1 < b2;
 }
 
+// Makes a wave's LDS stores visible to the wave's other lanes (the sorting
+// helpers below use a region of their own per wave, so no block barrier).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Coarse row I with at most 64 terms sorted by one wavefront: each lane ranks
 // its term against the row's others (broadcast with readlane), the terms go
-// to LDS in rank order, and each run of equal J is summed in that order.
-// Every thread of the block calls (one barrier); rows with more terms, and
-// I >= nc, leave their wave idle.
+// to the wave's LDS region (64 slots) in rank order, and each run of equal J
+// is summed in that order.  Every lane of the wave calls; rows with more
+// terms, and I >= nc, leave the wave idle.
 __device__ inline void gal_row64(int I, int nc, const int* tstart, const int* tJ, const int* ta,
                                  const int* tb, const double* tw, int* sJ, double* sw, int* cJ,
                                  double* cw, int* uniq) {
@@ -1500,7 +1554,7 @@ __device__ inline void gal_row64(int I, int nc, const int* tstart, const int* tJ
     sJ[rank] = myJ;
     sw[rank] = myw;
   }
-  __syncthreads();
+  wave_lds_sync();
   bool head = false;
   if (active && lane < T) head = lane == 0 || sJ[lane] != sJ[lane - 1];
   unsigned long long mask = __ballot(head);
@@ -1513,7 +1567,59 @@ __device__ inline void gal_row64(int I, int nc, const int* tstart, const int* tJ
     cw[s + pos] = sum;
   }
   if (active && lane == 0) uniq[I] = __popcll(mask);
-  __syncthreads();  // the next call reuses sJ / sw
+  wave_lds_sync();  // the next call reuses sJ / sw
+}
+
+
+// Two coarse rows of at most 32 terms each, one per half of the wave (row I
+// in lanes h * 32 + l, h = 0, 1): the same ranks and sums as gal_row64, the
+// terms broadcast within each half by a cross-lane read.
+__device__ inline void gal_row32(int I, int nc, const int* tstart, const int* tJ, const int* ta,
+                                 const int* tb, const double* tw, int* sJ, double* sw, int* cJ,
+                                 double* cw, int* uniq) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  int s = 0, T = 0;
+  if (I < nc) {
+    s = tstart[I];
+    T = tstart[I + 1] - s;
+  }
+  const bool mine = I < nc && l < T;
+  int myJ = INT_MAX, mya = 0, myb = 0;
+  double myw = 0.0;
+  if (mine) {
+    myJ = tJ[s + l];
+    mya = ta[s + l];
+    myb = tb[s + l];
+    myw = tw[s + l];
+  }
+  // Padding lanes hold (INT_MAX, 0, 0), after every real term of the row.
+  const int Tm = max(__builtin_amdgcn_readlane(T, 0), __builtin_amdgcn_readlane(T, 32));
+  int rank = 0;
+  for (int k = 0; k < Tm; ++k) {
+    const int src = (h << 5) + k;
+    const int J2 = __shfl(myJ, src), a2 = __shfl(mya, src), b2 = __shfl(myb, src);
+    if (term_less(J2, a2, b2, myJ, mya, myb)) ++rank;
+  }
+  int* rJ = sJ + (h << 5);
+  double* rw = sw + (h << 5);
+  if (mine) {
+    rJ[rank] = myJ;
+    rw[rank] = myw;
+  }
+  wave_lds_sync();
+  bool head = false;
+  if (mine) head = l == 0 || rJ[l] != rJ[l - 1];
+  const unsigned long long rowmask = (__ballot(head) >> (h << 5)) & 0xFFFFFFFFULL;
+  if (head) {
+    const int pos = __popcll(rowmask & ((1ULL << l) - 1ULL));
+    const int J = rJ[l];
+    double sum = 0.0;
+    for (int p = l; p < T && rJ[p] == J; ++p) sum += rw[p];
+    cJ[s + pos] = J;
+    cw[s + pos] = sum;
+  }
+  if (I < nc && l == 0) uniq[I] = __popcll(rowmask);
+  wave_lds_sync();  // the next call reuses sJ / sw
 }
 
 // Lane value of the lane k places further round its row of 16 (DPP row_ror).
@@ -1523,13 +1629,14 @@ __device__ inline int row_ror(int v) {
 }
 
 // Rows with at most 64 terms.  With packed set, a block of four waves takes
-// 16 consecutive rows, four per wave: when each of the 16 has at most 16
-// terms (the common case on large levels: a pair of fine rows of a 5-point
-// grid gives six), a wave sorts its four rows at once in rows of 16 lanes,
-// ranking each term against the 15 others of its row by DPP rotations;
-// otherwise it sorts them one after another across all 64 lanes.  Without
-// packed (levels with few rows, where latency decides), one row per wave.
-// Same ranks, same sums either way.
+// Four consecutive rows per wave: when each of the four has at most 16 terms
+// (the common case on large levels: a pair of fine rows of a 5-point grid
+// gives six), the wave sorts them at once in rows of 16 lanes, ranking each
+// term against the 15 others of its row by DPP rotations; when each has at
+// most 32 (a pair of rows of a random geometric graph gives 14 on average, up
+// to ~50), two at a time in halves of the wave; otherwise one after another
+// across all 64 lanes.  Without packed (levels with few rows, where latency
+// decides), one row per wave.  Same ranks, same sums either way.
 constexpr int kGalPackedRows = 32768;  // coarse rows from which packed pays
 
 __global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, int packed, const int* tstart,
@@ -1552,9 +1659,18 @@ __global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, int packed, c
     s = tstart[I];
     T = tstart[I + 1] - s;
   }
-  if (!__syncthreads_and(T <= 16)) {
+  // the longest of the wave's four rows (lanes 0, 16, 32, 48 hold them)
+  const int Tw = max(max(__builtin_amdgcn_readlane(T, 0), __builtin_amdgcn_readlane(T, 16)),
+                     max(__builtin_amdgcn_readlane(T, 32), __builtin_amdgcn_readlane(T, 48)));
+  if (Tw > 32) {
     for (int r = 0; r < 4; ++r)
       gal_row64(I0 + r, nc, tstart, tJ, ta, tb, tw, sJ[wave], sw[wave], cJ, cw, uniq);
+    return;
+  }
+  if (Tw > 16) {
+    for (int r = 0; r < 4; r += 2)
+      gal_row32(I0 + r + (lane >> 5), nc, tstart, tJ, ta, tb, tw, sJ[wave], sw[wave], cJ, cw,
+                uniq);
     return;
   }
   const bool mine = I < nc && l16 < T;
@@ -1580,7 +1696,7 @@ __global__ __launch_bounds__(kBlock) void k_gal_rows_small(int nc, int packed, c
     rJ[rank] = myJ;
     rw[rank] = myw;
   }
-  __syncthreads();
+  wave_lds_sync();
   bool head = false;
   if (mine) head = l16 == 0 || rJ[l16] != rJ[l16 - 1];
   const unsigned long long rowmask = (__ballot(head) >> (g * 16)) & 0xFFFFULL;
@@ -1813,8 +1929,18 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
   if (read_int(flags, s, pin_i) & 1) throw Error(FV_E_INVALID, "CSR structure invalid");
   int* offdeg = tmp.get<int>(n);
   int* rp0 = tmp.get<int>(n + 1);
-  k_val_values<<<nblk(n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, Lin->is_adjacency ? 1 : 0,
-                                          offdeg, flags);
+  const int adj = Lin->is_adjacency ? 1 : 0;
+  switch (row_group(n, nnz)) {
+    case 4:
+      k_val_values<4><<<nblk(4LL * n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, adj, offdeg, flags);
+      break;
+    case 8:
+      k_val_values<8><<<nblk(8LL * n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, adj, offdeg, flags);
+      break;
+    default:
+      k_val_values<16><<<nblk(16LL * n), kBlock, 0, s>>>(n, rp_in, col_in, val_in, adj, offdeg,
+                                                          flags);
+  }
   FV_HIP(hipGetLastError());
   sc.enqueue(FromArray{offdeg}, n, rp0, true);
   k_gather_ints<<<1, 64, 0, s>>>(IntSrc{{flags, rp0 + n}}, 2, gath);
@@ -2174,8 +2300,8 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       F.col = halloc<int>(h, F.m);
       F.w64 = halloc<double>(h, F.m);
       F.w32 = halloc<float>(h, F.m);
-      k_solve_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, F.iperm, F.perm, F.rp,
-                                               F.col, F.w64, F.w32);
+      launch_solve_fill(fn, F.m, s, F.rp_c, F.col_c, F.w_c, F.iperm, F.perm, F.rp, F.col, F.w64,
+                        F.w32);
       FV_HIP(hipGetLastError());
       if (k < J) {
         F.qs = halloc<int>(h, fn);
