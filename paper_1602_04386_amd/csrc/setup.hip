@@ -10,6 +10,7 @@
 #include <climits>
 #include <cmath>
 #include <initializer_list>
+#include <type_traits>
 
 #include "fv_device.h"
 #include "fv_internal.h"
@@ -1438,69 +1439,90 @@ __device__ inline void gal_batch(int pb, int b, const int* __restrict__ col,
   __builtin_amdgcn_sched_barrier(0);
 }
 
-__global__ void k_gal_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                            const int* __restrict__ q, int* __restrict__ tcount) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int I = q[v], a = rp[v], b = rp[v + 1];
-  int c = 0;
-  for (int pb = a; pb < b; pb += kNbU) {
-    int jj[kNbU], JJ[kNbU];
-    double ww[kNbU];
-    gal_batch(pb, b, col, nullptr, q, jj, JJ, ww);
-#pragma unroll
-    for (int k = 0; k < kNbU; ++k) c += (pb + k < b && JJ[k] != I) ? 1 : 0;
-  }
-  if (c) atomicAdd(&tcount[I], c);
+// G lanes per fine row (a group of consecutive lanes of one wave): lane j
+// takes entries j, j + G, ... of row v.  ext_mask gives the group's lanes
+// whose entry in this pass is a term of v's coarse row (its neighbour in
+// another aggregate), as bits of the wave.
+template <int G>
+__device__ inline unsigned long long gal_group_mask() {
+  const int lane = threadIdx.x & 63;
+  return (G == 64 ? ~0ULL : ((1ULL << G) - 1ULL)) << (lane & ~(G - 1));
 }
 
-// The terms of fine row v, in CSR order, at v's place in its coarse row's
-// list.  The first batch of neighbours stays in registers between the count
-// and the fill (a grid row fits in one batch).
+template <int G>
+__global__ void k_gal_count(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const int* __restrict__ q, int* __restrict__ tcount) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = (int)(g / G), j = (int)(g % G);
+  if (v >= n) return;  // the whole group leaves together
+  const int I = q[v], a = rp[v], b = rp[v + 1];
+  const unsigned long long gm = gal_group_mask<G>();
+  int c = 0;
+  for (int pb = a; pb < b; pb += G) {
+    const int p = pb + j;
+    const bool ext = p < b && q[col[p]] != I;
+    c += __popcll(__ballot(ext) & gm);
+  }
+  if (j == 0 && c) atomicAdd(&tcount[I], c);
+}
+
+// The terms of fine row v at v's place in its coarse row's list (lane order
+// within each pass of the group; the rows are sorted afterwards, so the order
+// in the list does not matter).  The group's first pass stays in registers
+// between the count and the fill (most rows fit one pass).
+template <int G>
 __global__ void k_gal_fill(int n, const int* __restrict__ rp, const int* __restrict__ col,
                            const double* __restrict__ w, const int* __restrict__ q,
                            const int* __restrict__ tstart, int* __restrict__ tfill,
                            int* __restrict__ tJ, int* __restrict__ ta, int* __restrict__ tb,
                            double* __restrict__ tw) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = (int)(g / G), j = (int)(g % G);
+  if (v >= n) return;  // the whole group leaves together
   const int I = q[v], a = rp[v], b = rp[v + 1];
-  int j0[kNbU], J0[kNbU];
-  double w0[kNbU];
-  int c = 0;
-  for (int pb = a; pb < b; pb += kNbU) {
-    int jj[kNbU], JJ[kNbU];
-    double ww[kNbU];
-    gal_batch(pb, b, col, w, q, jj, JJ, ww);
-#pragma unroll
-    for (int k = 0; k < kNbU; ++k) c += (pb + k < b && JJ[k] != I) ? 1 : 0;
-    if (pb == a)
-#pragma unroll
-      for (int k = 0; k < kNbU; ++k) {
-        j0[k] = jj[k];
-        J0[k] = JJ[k];
-        w0[k] = ww[k];
-      }
+  const int lane = threadIdx.x & 63;
+  const unsigned long long gm = gal_group_mask<G>();
+  const unsigned long long below = gm & ((1ULL << lane) - 1ULL);
+  int j0 = 0, J0 = I;
+  double w0 = 0.0;
+  if (a + j < b) {
+    j0 = col[a + j];
+    w0 = w[a + j];
+    J0 = q[j0];
+  }
+  const bool ext0 = a + j < b && J0 != I;
+  const unsigned long long m0 = __ballot(ext0) & gm;
+  int c = __popcll(m0);
+  for (int pb = a + G; pb < b; pb += G) {
+    const int p = pb + j;
+    const bool ext = p < b && q[col[p]] != I;
+    c += __popcll(__ballot(ext) & gm);
   }
   if (!c) return;
-  int k = tstart[I] + atomicAdd(&tfill[I], c);
-  auto emit = [&](int j, int J, double wv) {
-    tJ[k] = J;
-    ta[k] = v < j ? v : j;
-    tb[k] = v < j ? j : v;
-    tw[k] = wv;
-    ++k;
+  int base = 0;
+  if (j == 0) base = atomicAdd(&tfill[I], c);
+  int k = tstart[I] + __shfl(base, lane & ~(G - 1));
+  auto emit = [&](int jv, int J, double wv, int pos) {
+    tJ[pos] = J;
+    ta[pos] = v < jv ? v : jv;
+    tb[pos] = v < jv ? jv : v;
+    tw[pos] = wv;
   };
-#pragma unroll
-  for (int u = 0; u < kNbU; ++u)
-    if (a + u < b && J0[u] != I) emit(j0[u], J0[u], w0[u]);
-  for (int pb = a + kNbU; pb < b; pb += kNbU) {
-    int jj[kNbU], JJ[kNbU];
-    double ww[kNbU];
-    gal_batch(pb, b, col, w, q, jj, JJ, ww);
-#pragma unroll
-    for (int u = 0; u < kNbU; ++u)
-      if (pb + u < b && JJ[u] != I) emit(jj[u], JJ[u], ww[u]);
+  if (ext0) emit(j0, J0, w0, k + __popcll(m0 & below));
+  k += __popcll(m0);
+  for (int pb = a + G; pb < b; pb += G) {
+    const int p = pb + j;
+    int jv = 0, J = I;
+    double wv = 0.0;
+    if (p < b) {
+      jv = col[p];
+      wv = w[p];
+      J = q[jv];
+    }
+    const bool ext = p < b && J != I;
+    const unsigned long long m = __ballot(ext) & gm;
+    if (ext) emit(jv, J, wv, k + __popcll(m & below));
+    k += __popcll(m);
   }
 }
 
@@ -2186,11 +2208,20 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       // Galerkin coarse graph
       Level& Cl = h->lv[l + 1];
       Cl.n = nc;
-      k_gal_count<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.q_c, tcount);
-      FV_HIP(hipGetLastError());
-      sc.enqueue(FromArray{tcount}, nc, tstart, true);
-      k_gal_fill<<<nblk(fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.w_c, F.q_c, tstart, tfill, tJ,
-                                             ta, tb, tw);
+      auto gal_terms = [&](auto G) {
+        constexpr int kG = decltype(G)::value;
+        k_gal_count<kG><<<nblk((long long)kG * fn), kBlock, 0, s>>>(fn, F.rp_c, F.col_c, F.q_c,
+                                                                    tcount);
+        FV_HIP(hipGetLastError());
+        sc.enqueue(FromArray{tcount}, nc, tstart, true);
+        k_gal_fill<kG><<<nblk((long long)kG * fn), kBlock, 0, s>>>(
+            fn, F.rp_c, F.col_c, F.w_c, F.q_c, tstart, tfill, tJ, ta, tb, tw);
+      };
+      switch (row_group(fn, F.m)) {
+        case 4: gal_terms(std::integral_constant<int, 4>{}); break;
+        case 8: gal_terms(std::integral_constant<int, 8>{}); break;
+        default: gal_terms(std::integral_constant<int, 16>{});
+      }
       {
         const int packed = nc >= kGalPackedRows ? 1 : 0;
         k_gal_rows_small<<<nblk(nc, (packed ? 4 : 1) * (kBlock / 64)), kBlock, 0, s>>>(
