@@ -394,12 +394,34 @@ __global__ __launch_bounds__(kBlock) void k_degree_max(int n, const int* rp, con
                                                      unsigned long long* lmax) {
   __shared__ double lds[kBlock / 64];
   double m = 0.0, len = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  // The next row's pointers are requested before this row is summed, and a
+  // row's weights eight at a time before any is added (in row order).
+  const int stride = gridDim.x * blockDim.x;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int a = 0, e = 0;
+  if (i < n) {
+    a = rp[i];
+    e = rp[i + 1];
+  }
+  for (; i < n; i += stride) {
+    int an = 0, en = 0;
+    if (i + stride < n) {
+      an = rp[i + stride];
+      en = rp[i + stride + 1];
+    }
     double d = 0.0;
-    const int a = rp[i], e = rp[i + 1];
-    for (int p = a; p < e; ++p) d += w[p];
+    for (int p = a; p < e; p += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = w[min(p + u, e - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (p + u < e) d += v[u];
+    }
     m = fmax(m, d);
     len = fmax(len, (double)(e - a));
+    a = an;
+    e = en;
   }
   m = block_max(m, lds);
   len = block_max(len, lds);
@@ -1780,12 +1802,15 @@ __global__ void k_list_fill(int n, const int* tstart, const int* pos, int* list)
   if (i < n && (tstart[i + 1] - tstart[i]) > 64) list[pos[i]] = i;
 }
 
+// G lanes per coarse row: lane j moves entries j, j + G, ... of the row.
+template <int G>
 __global__ void k_gal_compact(int nc, const int* tstart, const int* uniq, const int* crp,
                               const int* cJ, const double* cw, int* col, double* w) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = (int)(g / G), j = (int)(g % G);
   if (I >= nc) return;
-  int s = tstart[I], d = crp[I], u = uniq[I];
-  for (int k = 0; k < u; ++k) {
+  const int s = tstart[I], d = crp[I], u = uniq[I];
+  for (int k = j; k < u; k += G) {
     col[d + k] = cJ[s + k];
     w[d + k] = cw[s + k];
   }
@@ -2238,8 +2263,19 @@ fv_hierarchy* build_hierarchy(fv_context* ctx, const fv_csr* Lin, const fv_hier_
       Cl.m = mc;
       Cl.col_c = halloc<int>(h, mc);
       Cl.w_c = halloc<double>(h, mc);
-      k_gal_compact<<<nblk(nc), kBlock, 0, s>>>(nc, tstart, uniq, Cl.rp_c, cJ, cw, Cl.col_c,
-                                                Cl.w_c);
+      switch (row_group(nc, mc)) {
+        case 4:
+          k_gal_compact<4><<<nblk(4LL * nc), kBlock, 0, s>>>(nc, tstart, uniq, Cl.rp_c, cJ, cw,
+                                                              Cl.col_c, Cl.w_c);
+          break;
+        case 8:
+          k_gal_compact<8><<<nblk(8LL * nc), kBlock, 0, s>>>(nc, tstart, uniq, Cl.rp_c, cJ, cw,
+                                                              Cl.col_c, Cl.w_c);
+          break;
+        default:
+          k_gal_compact<16><<<nblk(16LL * nc), kBlock, 0, s>>>(nc, tstart, uniq, Cl.rp_c, cJ, cw,
+                                                                Cl.col_c, Cl.w_c);
+      }
       FV_HIP(hipGetLastError());
       ++l;
     }
