@@ -78,6 +78,10 @@ CASES = {
     # vertices and below average 30 to 120 neighbours): the one-workgroup
     # matching and colouring scan such rows with a whole wavefront
     "er12000": (lambda: gen.erdos_renyi(12000, 6 / 11999, 21), 25),
+    # mean degree ~20: the row copies of levels 0 and 1 (20,000 and 9,683
+    # rows) take groups of 16 lanes per row, and most of level 1's rows hold
+    # more than 32 Galerkin terms
+    "rgg20k_deg20": (lambda: gen.rgg(20000, 12, radius=math.sqrt(20 / (math.pi * 20000))), 25),
 }
 _graphs = {}
 
