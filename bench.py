@@ -636,12 +636,14 @@ def run_serve(args):
     import paper_1602_04386_amd as fv
 
     t = time.perf_counter()
-    pool = gen.serve_pool(args.pool)
+    pool = gen.serve_pool(args.pool, progress=lambda g: g and g % 64 == 0 and log(
+        f"generating pool: {g} of {args.pool} graphs ({time.perf_counter() - t:.0f} s)"))
     log(f"generated pool of {len(pool)} graphs, sum n={sum(g.n for g in pool)} in "
         f"{time.perf_counter() - t:.1f} s")
     solve = SERVE_SOLVE
     ctx = fv.Context(0)
     srv = fv.Server(ctx, max_inflight=64, queue_capacity=1 << 16, cache_hierarchies=True,
+                    hbm_budget_bytes=int(args.hbm_budget_gb * (1 << 30)),
                     workers=args.serve_workers,
                     n_coarse=N_COARSE, prec="fp32", **solve)
 
@@ -746,6 +748,7 @@ def run_serve(args):
             "workload": f"pool of {len(pool)} graphs, n log-uniform [1e3, 2e6] (SplitMix64 seed 5), "
                         f"70% random geometric / 30% 4:3 grids; sum n={sum(g.n for g in pool)}",
             "solve": solve, "workers": args.serve_workers or 8,
+            "hbm_budget_gb": args.hbm_budget_gb or None,
             "requested_rate": args.rate, "offered_rate": round(rate, 2),
             "closed_loop_capacity": round(cap_rate, 2),
             "saturated_at_requested_rate": args.rate > 0.8 * cap_rate,
@@ -1007,6 +1010,8 @@ def main():
     ap.add_argument("--build-threads", type=int, default=8,
                     help="batch: host threads of the concurrent hierarchy builds")
     ap.add_argument("--pool", type=int, default=32)
+    ap.add_argument("--hbm-budget-gb", type=float, default=0.0,
+                    help="serve: HBM budget of the server's cached hierarchies (0: none)")
     ap.add_argument("--serve-workers", type=int, default=0,
                     help="serve: server worker threads (0: the library's default, 8)")
     ap.add_argument("--rate", type=float, default=2000.0)

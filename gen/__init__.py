@@ -340,12 +340,17 @@ def batch_mix(count: int = 4096, seed: int = 4, nmin: int = 200, nmax: int = 500
     return out
 
 
-def serve_pool(count: int = 32, seed: int = 5, nmin: int = 1000, nmax: int = 2_000_000):
+def serve_pool(count: int = 32, seed: int = 5, nmin: int = 1000, nmax: int = 2_000_000,
+               progress=None):
     """Pool of request graphs: n log-uniform in [nmin, nmax]; a seeded coin
     picks a random geometric graph (probability 0.7, largest component) or a
-    4:3 grid with U[0.5,1.5] weights."""
+    4:3 grid with U[0.5,1.5] weights.  Graph g depends on (seed, g) alone, so
+    a pool is a prefix of any larger one.  progress(g), if given, is called
+    before graph g is generated."""
     out = []
     for g in range(count):
+        if progress is not None:
+            progress(g)
         s = derive_seed(seed, g)
         u = uniform01(s, 2)
         n = int(round(math.exp(math.log(nmin) + u[0] * (math.log(nmax) - math.log(nmin)))))
