@@ -18,7 +18,9 @@ Other workloads (one JSON line each):
   against a loop of per-graph FP64 solves on the same hierarchies.
 * ``serve``: open-loop Poisson requests against the serving loop (pool of
   request graphs, n log-uniform in [1e3, 2e6], 70% random geometric / 30%
-  grids), latency from the scheduled arrival, p50/p99.
+  grids; 32 by default, ``--pool 1024`` for the full resident pool, with
+  ``--hbm-budget-gb`` bounding the cached hierarchies), latency from the
+  scheduled arrival, p50/p99.
 * ``partition``: an 8-way recursive spectral bisection (median cuts) of the
   1024 x 1000 grid, with cut ratio and part sizes.
 * ``scaling``: the paper's grid-scaling experiment (Section 4, the second
